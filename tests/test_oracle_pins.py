@@ -1,0 +1,351 @@
+"""Pins of the CPU oracle against facts outside it: closed forms, the lemma of
+Sec. 3.3.3, superposition (Sec. 3.1), invariants of RC networks, library
+routines and brute force. Each names the part of the oracle it fixes."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import circuit as C
+from oracle import reference as R
+from oracle import rmatex as RM
+from oracle.expm import THETA, expm, pade_coefficients
+from paper_1511_04519_amd import instances as I
+from tests.helpers import problem, single_rc, sources, uniform_mesh
+
+PS, NS, FS = I.PS, I.NS, 1e-15
+
+
+# ------------------------------------------------------------ Cholesky
+
+def _random_spd_csr(n, seed, density=0.2):
+    rng = np.random.default_rng(seed)
+    A = np.where(rng.random((n, n)) < density, rng.standard_normal((n, n)), 0.0)
+    A = A + A.T
+    A += np.diag(np.abs(A).sum(1) + 1.0)
+    r, c = np.nonzero(A)
+    rp = np.zeros(n + 1, np.int64)
+    np.add.at(rp, r + 1, 1)
+    return A, np.cumsum(rp), c.astype(np.int32), A[r, c]
+
+
+@pytest.mark.parametrize("nd", [False, True])
+def test_cholesky_reconstructs(nd):
+    """L L^T equals the permuted matrix (definition of the factor)."""
+    A, rp, ci, v = _random_spd_csr(120, 1)
+    F = C.Cholesky(rp, ci, v, nested_dissection=nd)
+    cp, ri, lv, perm = F.export()
+    n = A.shape[0]
+    L = np.zeros((n, n))
+    for j in range(n):
+        L[ri[cp[j]:cp[j + 1]], j] = lv[cp[j]:cp[j + 1]]
+    assert np.allclose(np.tril(L), L)
+    P = A[np.ix_(perm, perm)]
+    assert np.abs(L @ L.T - P).max() <= 1e-13 * np.abs(A).max()
+    # same factor as LAPACK's for the same ordering (unique for SPD)
+    assert np.abs(L - np.linalg.cholesky(P)).max() <= 1e-12 * np.abs(L).max()
+
+
+def test_cholesky_solve_residual_mesh():
+    p = I.config0()
+    rp, ci, gv = C.assemble_G(p.netlist)
+    for vals in (gv, C.csr_add_diag(rp, ci, gv, p.netlist.c_node, alpha=1e-11)):
+        F = C.Cholesky(rp, ci, vals)
+        b = np.random.default_rng(0).standard_normal((p.netlist.n, 3))
+        x = F.solve(b)
+        for k in range(3):
+            r = C.csr_matvec(rp, ci, vals, x[:, k]) - b[:, k]
+            assert np.abs(r).max() <= 1e-12 * np.abs(b).max()
+
+
+def test_nested_dissection_reduces_fill():
+    p = I.small(5, layers=1, nx=60, ny=60, n_src=4)
+    rp, ci, gv = C.assemble_G(p.netlist)
+    nd = C.Cholesky(rp, ci, gv, nested_dissection=True).nnz
+    nat = C.Cholesky(rp, ci, gv, nested_dissection=False).nnz
+    assert nd < 0.5 * nat
+
+
+def test_not_spd_is_reported():
+    A = np.array([[1.0, 2.0], [2.0, 1.0]])
+    rp = np.array([0, 2, 4], np.int64)
+    ci = np.array([0, 1, 0, 1], np.int32)
+    with pytest.raises(np.linalg.LinAlgError):
+        C.Cholesky(rp, ci, A.ravel(), nested_dissection=False)
+
+
+# ------------------------------------------------------------ circuit
+
+def test_G_kills_constant_vector_up_to_pads():
+    """P3 (DC): G 1 = g_pad, so x = Vdd 1 solves G x = B u with no sinks."""
+    p = I.config0()
+    rp, ci, gv = C.assemble_G(p.netlist)
+    lhs = C.csr_matvec(rp, ci, gv, np.ones(p.netlist.n))
+    rhs = np.zeros(p.netlist.n)
+    rhs[p.netlist.pad_node] = p.netlist.pad_g
+    assert np.abs(lhs - rhs).max() <= 1e-13 * rhs.max()
+    D = C.csr_dense(rp, ci, gv)
+    assert np.array_equal(D, D.T)
+
+
+def test_pulse_shape():
+    d, r, w, f = (np.array([x]) for x in (1000, 200, 500, 100))
+    t = np.array([0, 1000, 1100, 1200, 1500, 1700, 1750, 1800, 5000])
+    u = np.array([C.pulse(tt, d, r, w, f)[0] for tt in t])
+    assert np.allclose(u, [0, 0, 0.5, 1, 1, 1, 0.5, 0, 0])
+    assert np.allclose(C.pulse_slope(1000, d, r, w, f), 1 / 200)
+    assert np.allclose(C.pulse_slope(1700, d, r, w, f), -1 / 100)
+    assert np.allclose(C.pulse_slope(1300, d, r, w, f), 0)
+
+
+# ------------------------------------------------------------ expm
+
+def test_pade_coefficients_degree3():
+    # [3/3] Pade numerator of exp: 1 + x/2 + x^2/10 + x^3/120
+    assert np.allclose(pade_coefficients(3), [1, 1 / 2, 1 / 10, 1 / 120])
+
+
+@pytest.mark.parametrize("scale", [1e-3, 0.2, 0.9, 2.0, 5.0, 50.0, 1e4])
+def test_expm_against_closed_forms(scale):
+    """P12: scalar, diagonal, 2x2 rotation, Jordan block, symmetric (eigh)."""
+    sc = min(scale, 700.0)
+    assert np.isclose(expm(np.array([[sc]]))[0, 0], np.exp(sc), rtol=1e-15 * (10 + sc))
+    assert np.isclose(expm(np.array([[-scale]]))[0, 0], np.exp(-scale), rtol=1e-15 * (10 + scale),
+                      atol=1e-300)
+    d = np.array([-scale, -scale / 3, 0.1])
+    assert np.allclose(expm(np.diag(d)), np.diag(np.exp(d)), rtol=1e-12, atol=0)
+    th = min(scale, 30.0)
+    Rm = expm(np.array([[0, th], [-th, 0]]))
+    assert np.allclose(Rm, [[np.cos(th), np.sin(th)], [-np.sin(th), np.cos(th)]], atol=1e-11)
+    lam = -min(scale, 40.0)
+    J = lam * np.eye(4) + np.diag(np.ones(3), 1)
+    E = expm(J)
+    from math import factorial
+    for i in range(4):
+        for j in range(i, 4):
+            k = j - i
+            assert np.isclose(E[i, j], np.exp(lam) / factorial(k), rtol=1e-11, atol=1e-300)
+    rng = np.random.default_rng(int(scale * 7) % 1000)
+    S = rng.standard_normal((6, 6))
+    S = (S + S.T) * min(scale, 20.0) / 6
+    ev, Q = np.linalg.eigh(S)
+    ref = (Q * np.exp(ev)) @ Q.T
+    assert np.abs(expm(S) - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_expm_against_scipy():
+    rng = np.random.default_rng(3)
+    for nrm in [1e-3, THETA[3], THETA[7], THETA[13], 30.0, 1e3]:
+        A = rng.standard_normal((12, 12))
+        A *= nrm / np.abs(A).sum(0).max()
+        ref = scipy.linalg.expm(A)
+        assert np.abs(expm(A) - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+
+
+# ------------------------------------------------------------ R-MATEX pins
+
+def test_P1_single_rc_decay_exact_at_m1():
+    """P1: C y' = -g y, y(0) = V: y = V exp(-t g / c); R-MATEX is exact at m=1."""
+    c, g = 3e-14, 0.7
+    s = RM.RMatex(single_rc(c, g), 1e-11)
+    taus = np.array([1e-15, 1e-13, 1e-12, 5e-12, 3e-11])
+    out, m, est, ok = s.expv(np.array([0.8]), taus, 1e-14, 20)
+    assert ok and m == 1 and est == 0.0
+    # exp of an exponent with relative rounding eps has relative error ~eps*|exponent|
+    ref = 0.8 * np.exp(-taus * g / c)
+    assert (np.abs(out[0] - ref) <= 4e-16 * (1 + taus * g / c) * ref).all()
+
+
+def test_P2_single_rc_trapezoid_closed_form():
+    """P2: one RC node driven by a trapezoidal sink pulse. The response is the
+    sum of four ramp responses (s/g)(t - t0 - tc (1 - e^{-(t - t0)/tc}))."""
+    c, g = 4e-14, 0.02
+    tc = c / g
+    a, d, r, w, f = 1e-3, 300 * PS, 40 * PS, 500 * PS, 70 * PS
+    nl = single_rc(c, g)
+    prob = problem(nl, sources([0], [a], [d], [r], [w], [f]), 3 * NS, step=5 * PS)
+    t = prob.t_out * FS
+
+    def ramp(t0, slope):
+        s_ = np.maximum(t - t0 * FS, 0.0)
+        return slope / g * (s_ - tc * (1 - np.exp(-s_ / tc)))
+
+    y = (ramp(d, a / (r * FS)) - ramp(d + r, a / (r * FS))
+         - ramp(d + r + w, a / (f * FS)) + ramp(d + r + w + f, a / (f * FS)))
+    x, _ = RM.RMatex(nl, 1e-11).transient(prob, tol=1e-14)
+    assert np.abs((1.0 - x[0]) - y).max() <= 1e-12 * np.abs(y).max()
+    ym, _ = R.modal(prob)
+    assert np.abs(ym[0] - y).max() <= 1e-12 * np.abs(y).max()
+
+
+def test_P3_dc_steady_state():
+    """P3: sources held on for t >> the slowest time constant reach G^-1 i."""
+    p = I.small(11, nx=6, ny=6, n_src=3, t_end=2 * NS)
+    src = p.sources
+    src.delay[:] = 10 * PS
+    src.width[:] = 10 * NS        # still on at t_end
+    rp, ci, gv = C.assemble_G(p.netlist)
+    i_inf = C.current(src, np.arange(src.n_src), p.netlist.n, p.t_end)
+    y_inf = np.linalg.solve(C.csr_dense(rp, ci, gv), i_inf)
+    _, y_end = RM.RMatex(p.netlist, 1e-11).transient(p, tol=1e-13)
+    assert np.abs(y_end - y_inf).max() <= 1e-10 * np.abs(y_inf).max()
+
+
+def test_P4_superposition_subtasks_equal_full_run():
+    """P4: the sum of subtask runs (Sec. 3.1) equals the undivided run."""
+    p = I.small(21, nx=10, ny=10, n_src=12, t_end=3 * NS, n_groups=4)
+    s = RM.RMatex(p.netlist, 1e-11)
+    x_dec, _ = s.transient(p, tol=1e-13, decompose=True)
+    x_full, _ = s.transient(p, tol=1e-13, decompose=False)
+    assert np.abs(x_dec - x_full).max() <= 1e-11
+    # and equals the modal truth
+    ym, _ = R.modal(p)
+    assert np.abs((1.0 - x_dec) - ym).max() <= 1e-11
+
+
+def test_P5_modal_equals_dense_eq5():
+    """P5: two exact routes (modal closed form, dense Eq. 5 with Pade expm)."""
+    p = I.small(31, nx=9, ny=9, n_src=7, t_end=2 * NS)
+    ym, _ = R.modal(p)
+    yd, _ = R.dense_eq5(p)
+    assert np.abs(ym - yd).max() <= 1e-12 * np.abs(ym).max()
+
+
+@pytest.mark.parametrize("tol,bound", [(1e-10, 1e-9), (1e-13, 1e-12)])
+def test_P5_rmatex_matches_modal_config0(tol, bound):
+    """P5 on the 32x32 workload: R-MATEX error follows its tolerance."""
+    p = I.config0()
+    ym, _ = R.modal(p)
+    x, _ = RM.RMatex(p.netlist, p.gamma).transient(p, tol=tol)
+    err = np.abs((p.netlist.vdd - x) - ym).max() / np.abs(x).max()
+    assert err <= bound
+
+
+def test_P6_lemma_generalized_eigenvector():
+    """P6 (lemma of Sec. 3.3.3): y(0) = u, an eigenvector of the pencil
+    (-G, C), gives y = e^{lam t} u; the Krylov space is invariant at m = 1."""
+    k, Rb, c, g0 = 7, 0.8, 2e-14, 0.03
+    nl = uniform_mesh(k, Rb, c, g0)
+    s = RM.RMatex(nl, 1e-11)
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+    for pm, qm in [(0, 0), (1, 2), (3, 5), (6, 6)]:
+        u = (np.cos(np.pi * pm * (ii + 0.5) / k) * np.cos(np.pi * qm * (jj + 0.5) / k)).ravel()
+        lam = -(g0 + (2 / Rb) * (2 - np.cos(np.pi * pm / k) - np.cos(np.pi * qm / k))) / c
+        taus = np.array([1e-14, 1e-12, 2e-11])
+        out, m, est, ok = s.expv(u, taus, 1e-14, 20)
+        assert ok and m == 1
+        for q, tau in enumerate(taus):
+            assert np.abs(out[:, q] - np.exp(lam * tau) * u).max() <= 1e-13
+
+
+def test_P7_reciprocity():
+    """P7: response at b to a source at a equals response at a to one at b."""
+    p = I.small(41, nx=8, ny=8, n_src=2, t_end=1 * NS)
+    nl = p.netlist
+    a_node, b_node = 10, 45
+    kw = dict(amp=[1e-3], delay=[50 * PS], rise=[30 * PS], width=[200 * PS], fall=[40 * PS])
+    s = RM.RMatex(nl, 1e-11)
+    pa = problem(nl, sources([a_node], **kw), 1 * NS, probe=[b_node])
+    pb = problem(nl, sources([b_node], **kw), 1 * NS, probe=[a_node])
+    xa, _ = s.transient(pa, tol=1e-14)
+    xb, _ = s.transient(pb, tol=1e-14)
+    assert np.abs(xa - xb).max() <= 1e-13
+
+
+def test_P8_positivity_and_bound():
+    """P8: e^{tA} >= 0 (A Metzler) and the droop stays in [0, G^-1 i_peak]."""
+    p = I.small(51, nx=10, ny=10, n_src=8, t_end=4 * NS)
+    x, _ = RM.RMatex(p.netlist, 1e-11).transient(p, tol=1e-13)
+    y = p.netlist.vdd - x
+    rp, ci, gv = C.assemble_G(p.netlist)
+    i_pk = np.zeros(p.netlist.n)
+    np.add.at(i_pk, p.sources.node, p.sources.amp)
+    bound = np.linalg.solve(C.csr_dense(rp, ci, gv), i_pk)
+    assert y.min() >= -1e-13
+    assert (y <= bound[:, None] + 1e-13).all()
+
+
+def test_P9_passivity():
+    """P9: with no sources the stored energy y^T C y does not grow."""
+    p = I.small(61, nx=8, ny=8)
+    s = RM.RMatex(p.netlist, 1e-11)
+    v = np.random.default_rng(1).random(p.netlist.n) * 1e-3
+    taus = np.linspace(0.2e-12, 30e-12, 40)
+    out, m, est, ok = s.expv(v, taus, 1e-15, 20)
+    e = np.einsum("it,i,it->t", out, p.netlist.c_node, out)
+    assert (np.diff(e) <= 1e-12 * e[0]).all()
+
+
+def test_P10_linearity_and_time_shift():
+    p = I.small(71, nx=8, ny=8, n_src=5, t_end=2 * NS)
+    s = RM.RMatex(p.netlist, 1e-11)
+    x1, _ = s.transient(p, tol=1e-14)
+    p.sources.amp *= 2.5
+    x2, _ = s.transient(p, tol=1e-14)
+    assert np.abs((1 - x2) - 2.5 * (1 - x1)).max() <= 1e-12
+    p.sources.amp /= 2.5
+    shift = 100 * PS                        # 10 output steps
+    p.sources.delay += shift
+    x3, _ = s.transient(p, tol=1e-14)
+    assert np.abs(x3[:, 10:] - x1[:, :-10]).max() <= 1e-12
+
+
+def test_P11_krylov_internals():
+    """P11: orthonormal basis, the Arnoldi relation of Sec. 3.3.2, and exactness
+    at m = n."""
+    p = I.small(81, nx=6, ny=6)
+    s = RM.RMatex(p.netlist, 1e-11)
+    v = np.random.default_rng(2).random(p.netlist.n)
+    m = 12
+    s.arnoldi(v, [1e-12], 0.0, m)          # tol 0: runs to m
+    # rebuild H~ from a fresh run with access to internals
+    n = p.netlist.n
+    rp, ci, gv = C.assemble_G(p.netlist)
+    Mdense = np.diag(p.netlist.c_node) + 1e-11 * C.csr_dense(rp, ci, gv)
+    K = np.linalg.solve(Mdense, np.diag(p.netlist.c_node))
+    b, _ = s.arnoldi(v, [1e-12], 0.0, m)
+    V = b.V
+    assert np.abs(V.T @ V - np.eye(m)).max() <= 1e-12
+    Ht = np.linalg.inv(np.eye(m) - 1e-11 * b.Hm)           # from H = (I - Ht^-1)/gamma
+    # (I - gamma A)^-1 V_m = V_m Ht_m + h v_{m+1} e_m^T: project out the last term
+    resid = K @ V - V @ Ht
+    assert np.abs(V.T @ resid).max() <= 1e-10 * np.abs(Ht).max()
+    assert np.isclose(np.linalg.norm(resid), b.h_next, rtol=1e-8)
+    # exact at m = n on a tiny grid
+    q = I.small(82, nx=2, ny=3, n_src=1)
+    s2 = RM.RMatex(q.netlist, 1e-11)
+    v2 = np.random.default_rng(3).random(q.netlist.n)
+    rp, ci, gv = C.assemble_G(q.netlist)
+    A = -C.csr_dense(rp, ci, gv) / q.netlist.c_node[:, None]
+    out, mm, est, ok = s2.expv(v2, [3e-12], 0.0, q.netlist.n)
+    ref = scipy.linalg.expm(3e-12 * A) @ v2
+    assert np.abs(out[:, 0] - ref).max() <= 1e-12 * np.abs(v2).max()
+
+
+def test_P13_error_falls_with_step():
+    """P13 (Fig. 5): at fixed m the rational Krylov error falls as h grows,
+    for h above gamma."""
+    p = I.config0()
+    rp, ci, gv = C.assemble_G(p.netlist)
+    A = -C.csr_dense(rp, ci, gv) / p.netlist.c_node[:, None]
+    v = np.random.default_rng(4).random(p.netlist.n) * 1e-3
+    s = RM.RMatex(p.netlist, 1e-11)
+    hs = np.array([1e-11, 3e-11, 1e-10, 3e-10])
+    for m in (4, 6):
+        b, _ = s.arnoldi(v, [1e-11], 0.0, m)
+        errs = [np.linalg.norm(b.expv(h) - scipy.linalg.expm(h * A) @ v) for h in hs]
+        assert all(e2 < e1 for e1, e2 in zip(errs, errs[1:])), errs
+
+
+def test_trapezoidal_second_order():
+    """Eq. 2 converges to the exact solution at second order (non-stiff mesh,
+    so every mode is resolved by the step)."""
+    nl = uniform_mesh(5, 1.0, 1e-11, 0.05)
+    src = sources([3, 17], [1e-3, 5e-4], [20 * PS, 35 * PS], [30 * PS, 25 * PS],
+                  [100 * PS, 80 * PS], [40 * PS, 60 * PS])
+    p = problem(nl, src, 400 * PS, step=5 * PS)
+    ym, _ = R.modal(p)
+    e = []
+    for h in (200, 100):                      # fs
+        yt, _, _ = R.trapezoidal(p, h)
+        e.append(np.abs(yt - ym).max())
+    assert 3.5 < e[0] / e[1] < 4.5
