@@ -1,0 +1,216 @@
+/*
+ * matex.h - C ABI of the MI355X rational-Krylov (R-MATEX) transient library.
+ *
+ * Problem (Sec. 2.1, Eq. 1): C x' = -G x + B u(t) for a linear RC power grid.
+ * C is the diagonal of node-to-ground capacitances, G the branch-conductance
+ * Laplacian plus Norton supply-pad conductances, and B u injects Vdd through
+ * the pads and draws piecewise-linear sink currents (trapezoidal pulses, the
+ * timing of Fig. 3) out of their nodes. The library works in the droop
+ * y = Vdd - x, for which C y' = -G y + i(t) and y(0) = 0.
+ *
+ * Method (Sec. 3.3.2, R-MATEX): e^{hA} v with A = -C^-1 G is approximated in
+ * the rational Krylov space K_m((C + gamma G)^-1 C, v) built by Alg. 1 with
+ * X1 = C + gamma G (factored once) and X2 = C:  e^{hA} v ~= ||v|| V_m e^{h H_m} e1,
+ * H_m = (I - Ht_m^-1)/gamma (Eq. 9). Alg. 2 steps between transition spots of
+ * the piecewise-linear input with Eq. 6 and reuses each basis for every
+ * output time (snapshot) before the next spot; sources are grouped into
+ * subtasks whose responses add up (Sec. 3.1).
+ *
+ * Conventions:
+ *  - Every function returns matex_status; MATEX_OK is 0. On error, the text of
+ *    matex_last_error() (thread-local) says what went wrong; nothing is
+ *    written to outputs unless stated.
+ *  - "host" pointers are read during the call only and stay owned by the
+ *    caller. "device" pointers are HIP device memory owned by the caller
+ *    (e.g. torch tensors on cuda:0); the library never frees them.
+ *  - stream: a hipStream_t (NULL = default stream). Device work is enqueued
+ *    on it; calls that must read a decision back from the device
+ *    (matex_krylov_step, matex_transient) synchronise that stream.
+ *  - All floating point is IEEE binary64. Times are integer femtoseconds in
+ *    problem descriptions and seconds (double) in matex_krylov_step.
+ *  - The library needs a gfx950 device; it has no CPU fallback and returns
+ *    MATEX_E_HIP if HIP reports an error.
+ */
+#ifndef MATEX_H
+#define MATEX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MATEX_OK = 0,
+    MATEX_E_INVALID = 1,     /* bad argument (sizes, ranges, ordering)          */
+    MATEX_E_NOT_SPD = 2,     /* a pivot of C + gamma G or G was not positive      */
+    MATEX_E_OOM = 3,         /* host or device allocation failed                  */
+    MATEX_E_HIP = 4,         /* a HIP runtime call failed                         */
+    MATEX_E_NOCONV = 5,      /* estimate still >= tol at m_max (and at h_min)     */
+    MATEX_E_UNSUPPORTED = 6  /* valid request outside what this build implements  */
+} matex_status;
+
+typedef struct matex_factor_s* matex_factor_t;
+
+/* A linear RC grid (host arrays). Node ids are 0..n-1. */
+typedef struct {
+    int64_t n;
+    int64_t n_branch;
+    const int32_t* br_a;     /* [n_branch] branch end nodes                      */
+    const int32_t* br_b;     /* [n_branch]                                       */
+    const double* br_g;      /* [n_branch] conductance (S), > 0                  */
+    const double* c_node;    /* [n] capacitance to ground (F), > 0               */
+    int32_t n_pad;
+    const int32_t* pad_node; /* [n_pad] nodes tied to Vdd through pad_g          */
+    const double* pad_g;     /* [n_pad] pad conductance (S), > 0                 */
+    double vdd;              /* supply voltage (V)                               */
+    const int32_t* coord;    /* optional [n][3] grid coordinates (layer, i, j)
+                                used by the nested-dissection ordering; NULL
+                                falls back to a graph-distance coordinate       */
+} matex_netlist;
+
+typedef struct {
+    int32_t n_shifts;        /* shifts gamma_k = gamma * 10^-k, k < n_shifts
+                                (default 4 when 0): one factor of C + gamma_k G
+                                each, plus one of G, all factored once          */
+    int32_t leaf_max;        /* nested-dissection leaf size (default 16 when 0) */
+} matex_factor_opts;
+
+typedef struct {
+    int64_t n;
+    int64_t nnz_l;           /* entries of one factor's lower triangle as stored */
+    int64_t panel_doubles;   /* doubles of one factor's panels (nr x nc each)    */
+    int32_t n_supernodes;
+    int32_t n_levels;
+    int32_t n_shifts;
+    int32_t max_nr;
+    double gamma;
+    double seconds_analyse;  /* host ordering + symbolic                         */
+    double seconds_numeric;  /* host numeric factorisation, all factors           */
+    int64_t device_bytes;    /* device memory held by the handle                 */
+} matex_factor_info;
+
+/*
+ * matex_factor - LU_Decompose(X1) of Alg. 2 (Sec. 3.2) for R-MATEX: factor
+ * C + gamma_k G (Sec. 3.3.2, X1) for every shift of the ladder, and G (for the
+ * F and P terms of Eq. 6), once, on one nested-dissection ordering, and upload
+ * the factors. gamma > 0 (seconds). The handle owns its device memory and is
+ * read-only afterwards; concurrent calls may share it if they use different
+ * streams and their own output buffers.
+ * Errors: MATEX_E_INVALID (n <= 0, a node id out of range, a non-positive
+ * conductance or capacitance, gamma <= 0), MATEX_E_NOT_SPD, MATEX_E_OOM,
+ * MATEX_E_HIP.
+ */
+matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_factor_opts* opts,
+                          void* stream, matex_factor_t* out);
+matex_status matex_factor_free(matex_factor_t f);
+matex_status matex_factor_get_info(matex_factor_t f, matex_factor_info* info);
+
+/*
+ * matex_solve - one forward/backward substitution pair (Alg. 1, the step
+ * U \ (L \ b)) with factor `which`: k in [0, n_shifts) for C + gamma_k G,
+ * -1 for G. Computes x = A^-1 (diag(scale) b) for nrhs right-hand sides.
+ * d_b, d_x: device, n x nrhs column-major (leading dimension n), natural node
+ * order; d_scale: device [n] or NULL (no scaling). d_b and d_x may not alias.
+ */
+matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const double* d_b,
+                         const double* d_scale, double* d_x, void* stream);
+
+/*
+ * matex_krylov_step - e^{tau_k A} v_r (Eq. 9) for every tau_k and every
+ * right-hand side v_r, with one rational Krylov basis per v_r (Alg. 1 with
+ * X1 = C + gamma_s G, X2 = C; shift index `shift` of the ladder).
+ * d_v: device, n x nrhs column-major, natural order. tau: host [n_tau],
+ * seconds, > 0. Stops at the first m whose estimate is < tol for every tau
+ * (the estimate is the larger of the empirical form of Sec. 3.3.3 and the
+ * change from dimension m-1), or at m_max (<= 32).
+ * d_out: device, n x nrhs x n_tau, out[i + n*(r + nrhs*k)].
+ * m_used, est: host [nrhs] (may be NULL). Returns MATEX_E_NOCONV if some
+ * right-hand side did not converge; d_out, m_used and est are still written.
+ */
+matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, const double* d_v,
+                               int32_t n_tau, const double* tau, int32_t m_max, double tol,
+                               double* d_out, int32_t* m_used, double* est, void* stream);
+
+/* Pulse current sinks (host arrays). Times in fs, delay >= 0, rise > 0,
+ * fall > 0, width >= 0; amplitude in A. group[k] in [0, n_group): the subtask
+ * of source k (Sec. 3.1 grouping); NULL puts every source in subtask 0. */
+typedef struct {
+    int32_t n_src;
+    const int32_t* node;
+    const double* amp;
+    const int64_t* delay;
+    const int64_t* rise;
+    const int64_t* width;
+    const int64_t* fall;
+    const int32_t* group;
+    int64_t t_end;           /* end of the window (fs), > 0                     */
+    int32_t n_out;
+    const int64_t* t_out;    /* [n_out] output times (fs), strictly increasing,
+                                within [0, t_end]                                */
+    int32_t n_probe;
+    const int32_t* probe;    /* [n_probe] node ids reported at every t_out       */
+} matex_problem;
+
+typedef enum { MATEX_PLAIN = 0, MATEX_BATCHED = 1 } matex_mode;
+
+typedef struct {
+    double tol;              /* per-basis error estimate bound (V), > 0          */
+    int32_t m_max;           /* largest Krylov dimension, 1..32                  */
+    int32_t mode;            /* MATEX_PLAIN: subtasks one after another          */
+    int64_t h_min;           /* smallest step after halving (fs), >= 1           */
+} matex_run_opts;
+
+typedef struct {
+    int64_t subtasks;
+    int64_t segments;        /* steps taken (after ladder cuts and halvings)    */
+    int64_t bases;           /* Krylov bases generated                          */
+    int64_t solve_pairs_m;   /* substitution pairs with C + gamma_k G           */
+    int64_t solve_pairs_g;   /* substitution pairs with G                       */
+    int64_t krylov_dims;     /* sum of m over bases                             */
+    int32_t m_peak;
+    int32_t halvings;
+    int32_t shift_downs;
+    int32_t pad_;
+    double seconds;          /* wall time of the call                           */
+} matex_stats;
+
+/*
+ * matex_transient - Alg. 2 for every subtask of the problem, summed by
+ * superposition (Sec. 3.1-3.2). Writes x = Vdd - sum_k y_k at the probes:
+ * d_probe_out device [n_probe][n_out] (row-major), and, if d_final is not
+ * NULL, x(t_end) at every node: device [n], natural order. Each subtask
+ * starts from y_k(0) = G^-1 i_k(0) = 0 (no source draws current at t = 0).
+ * Step rule: a basis is built at every transition spot of the subtask and
+ * reused for the output times before the next spot; the shift of the ladder
+ * is chosen from the first check offset tau_1 of the step (the largest
+ * gamma_k with tau_1 >= gamma_k/10; below the top shift the step ends at
+ * the last check offset <= 10 gamma_k); without convergence at m_max the
+ * step is retried one shift lower, and with the smallest shift it is halved
+ * down to h_min. Stats may be NULL.
+ * Errors: MATEX_E_INVALID, MATEX_E_NOCONV, MATEX_E_UNSUPPORTED (mode),
+ * MATEX_E_OOM, MATEX_E_HIP.
+ */
+matex_status matex_transient(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
+                             double* d_probe_out, double* d_final, matex_stats* stats,
+                             void* stream);
+
+/*
+ * matex_adjoint - gradients of a droop objective with respect to source
+ * amplitudes and node capacitances. Not provided by this build: returns
+ * MATEX_E_UNSUPPORTED.
+ */
+matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
+                           const double* d_dJdx, double* d_grad_amp, double* d_grad_c,
+                           void* stream);
+
+/* Copies the calling thread's last error text (NUL-terminated) into buf. */
+size_t matex_last_error(char* buf, size_t len);
+const char* matex_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MATEX_H */

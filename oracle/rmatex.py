@@ -115,10 +115,10 @@ class KrylovBasis:
         u = expm(tau * self.Hm)[:, 0]
         paper = self.beta * self.h_next * abs(u[self.m - 1])
         if self.m == 1:
-            prev = np.ones(1)
+            diff = self.beta * abs(u[0] - 1.0)          # against u_0 = 1 (v itself)
         else:
             prev = expm(tau * self.Hprev)[:, 0]
-        diff = self.beta * np.linalg.norm(u - np.concatenate([prev, [0.0]]))
+            diff = self.beta * np.linalg.norm(u - np.concatenate([prev, [0.0]]))
         return max(paper, diff)
 
 
@@ -147,6 +147,7 @@ class RMatex:
         self.Mfs = [Cholesky(rp, ci, csr_add_diag(rp, ci, gv, self.c, alpha=g))
                     for g in self.gammas]
         self.stats = Stats()
+        self.trace = False
 
     # ---------------------------------------------------------- Alg. 1
     def arnoldi(self, v: np.ndarray, check_taus, tol: float, m_max: int,
@@ -253,6 +254,9 @@ class RMatex:
                 t_b = t_a + h
                 snaps = snaps[snaps <= t_b]
             self.stats.segments += 1
+            if self.trace:
+                print(f"[oracle] seg t_a={t_a} t_b={t_b} shift={k} m={basis.m} conv={int(ok)} "
+                      f"est={max(basis.estimate(t) for t in offs * FS):.3e} checks={offs.size}")
             for ts_k in snaps:                             # snapshots (Alg. 2 reuse)
                 tau = (ts_k - t_a) * FS
                 yk = basis.expv(tau) + y0 + tau * z1 - z2

@@ -1,0 +1,98 @@
+// Device kernels of the R-MATEX hot path and their launch wrappers (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace matex {
+
+constexpr int MAXM = 32;          // largest Krylov dimension supported
+constexpr int FWD_ROWS = 64;      // rows of a forward task (one per lane)
+constexpr int FWD_KSPLIT = 4;     // k-slices of a forward task (one per wavefront)
+constexpr int BWD_COLS = 4;       // columns of a backward task (one per wavefront)
+constexpr int RED_BLOCKS = 256;   // blocks of the vector reductions
+
+// Shared (factor-independent) device view of the supernodal structure.
+struct DevSym {
+    int64_t n;
+    const int32_t* c0;
+    const int32_t* nc;
+    const int32_t* nr;
+    const int64_t* roff;
+    const int64_t* w;
+    const int64_t* u;
+    const int32_t* rows;
+    const int64_t* upd_ptr;
+    const int64_t* upd_idx;
+};
+
+// One level's task list: task t covers supernode sn[t] starting at first[t]
+// (a row for the forward sweep, a column for the backward sweep).
+struct LevelTasks {
+    const int32_t* sn;
+    const int32_t* first;
+    int32_t count;
+    int32_t lds_doubles;   // LDS the level needs (max nc fwd / max nr bwd)
+};
+
+// Per-Krylov-process device state (one per instance).
+struct KState {
+    int32_t done;          // 1 once converged, broken down or at m_max: later kernels return
+    int32_t converged;
+    int32_t m;             // current dimension
+    int32_t breakdown;
+    int32_t counter;       // last-block detection of the grid reductions
+    int32_t pad_;
+    double beta;           // ||v||
+    double est;            // max estimate over the check set at dimension m
+    double nrm2;           // ||w'||^2 after the first Gram-Schmidt pass
+    double h1[MAXM + 1];   // first Gram-Schmidt pass coefficients
+    double h2[MAXM + 1];   // second pass
+    double Ht[(MAXM + 1) * MAXM];   // column-major (MAXM+1) x MAXM
+};
+
+// ---- sweeps: w = (L L^T)^-1 (scale .* b) in the permuted ordering --------
+void launch_forward(const DevSym& s, const LevelTasks& lv, const double* W, const double* b,
+                    const double* scale, double* y, double* upd, const int32_t* done,
+                    hipStream_t st);
+void launch_backward(const DevSym& s, const LevelTasks& lv, const double* W, const double* y,
+                     double* x, const int32_t* done, hipStream_t st);
+
+// ---- Gram-Schmidt (two classical passes) -----------------------------------
+// partial: RED_BLOCKS x (MAXM + 2) doubles of scratch.
+void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const double* w,
+                    double* partial, KState* ks, const int32_t* done, hipStream_t st);
+void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w,
+                      double* partial, KState* ks, const int32_t* done, hipStream_t st);
+void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w, KState* ks,
+                      const int32_t* done, hipStream_t st);
+
+// ---- small dense part: H_m, exp(tau H_m) e1, estimates, decision ----------
+// One workgroup per check offset. u_buf[c*MAXM + i] = (e^{tau_c H_m} e1)_i;
+// when iterating (update_state) it also holds the previous dimension's vector.
+void launch_checks(KState* ks, double gamma, const double* tau, int n_tau, double tol,
+                   double* u_buf, double* est_buf, int m_max, int update_state, hipStream_t st);
+size_t checks_lds_bytes();
+
+// ---- segment set-up and reconstruction ------------------------------------
+void launch_setup_v(int64_t n, const double* y, const double* y0, const double* z2, double* v,
+                    double* partial, KState* ks, hipStream_t st);
+void launch_normalize_v(int64_t n, double* v, KState* ks, hipStream_t st);
+void launch_scatter_add(int32_t count, const int32_t* idx, const double* val, double* dst,
+                        hipStream_t st);
+void launch_recon_probes(int n_probe, const int32_t* probe_perm, int n_snap, int32_t snap0,
+                         const double* tau, const double* u, const KState* ks, const double* V,
+                         int64_t ldv, const double* y0, const double* z1, const double* z2,
+                         double* out, int32_t n_out, hipStream_t st);
+void launch_recon_full(int64_t n, double tau, const double* u, const KState* ks,
+                       const double* V, int64_t ldv, double* y, double* y0, const double* z1,
+                       const double* z2, hipStream_t st);
+void launch_axpy_scaled(int64_t n, double a, const double* x, double* y, hipStream_t st);
+void launch_gather_perm(int64_t n, const int32_t* perm, const double* src, double* dst,
+                        int64_t ld_src, int64_t ld_dst, int ncols, hipStream_t st);
+void launch_scatter_perm(int64_t n, const int32_t* perm, const double* src, double* dst,
+                         int64_t ld_src, int64_t ld_dst, int ncols, hipStream_t st);
+void launch_vdd_minus(int64_t count, double vdd, double* buf, hipStream_t st);
+
+}  // namespace matex

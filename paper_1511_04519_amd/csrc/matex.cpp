@@ -1,0 +1,711 @@
+// C-ABI entry points, device factor handle, segment planner and the
+// transient driver of the R-MATEX library (see include/matex.h).
+//
+// Everything numeric after the one-time factorisation runs in the HIP kernels
+// of kernels.hip, in the nested-dissection ordering (vectors are permuted
+// once on the way in and out). The host only plans steps (transition spots,
+// output times, shift choice) and reads back the few integers that decide
+// control flow (converged or not, Krylov dimension).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/matex.h"
+#include "factor.hpp"
+#include "kernels.hpp"
+
+using namespace matex;
+
+namespace {
+
+thread_local std::string g_err;
+
+matex_status fail(matex_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIPCHK(expr)                                                      \
+    do {                                                                  \
+        hipError_t e_ = (expr);                                           \
+        if (e_ != hipSuccess) throw HipError{e_, #expr};                  \
+    } while (0)
+
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    explicit DevMem(size_t b) : bytes(b) {
+        if (b) HIPCHK(hipMalloc(&p, b));
+    }
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    DevMem(DevMem&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+    DevMem& operator=(DevMem&& o) noexcept {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
+        return *this;
+    }
+    ~DevMem() {
+        if (p) (void)hipFree(p);
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <class T>
+DevMem upload(const std::vector<T>& v)
+{
+    DevMem m(sizeof(T) * v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(m.p, v.data(), m.bytes, hipMemcpyHostToDevice));
+    return m;
+}
+
+struct PinnedMem {
+    void* p = nullptr;
+    explicit PinnedMem(size_t b) { HIPCHK(hipHostMalloc(&p, b, hipHostMallocDefault)); }
+    ~PinnedMem() {
+        if (p) (void)hipHostFree(p);
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+struct matex_factor_s {
+    Symbolic sym;
+    double gamma = 0.0;
+    std::vector<double> gammas;       // shift ladder
+    double vdd = 1.0;
+    int device = 0;
+    // device structure
+    DevMem d_c0, d_nc, d_nr, d_roff, d_w, d_u, d_rows, d_upd_ptr, d_upd_idx;
+    DevMem d_perm, d_iperm, d_cperm;
+    std::vector<DevMem> d_W;          // [n_shifts] M factors, then G
+    DevMem d_fwd_sn, d_fwd_first, d_bwd_sn, d_bwd_first;
+    std::vector<LevelTasks> fwd, bwd;
+    DevSym dsym{};
+    matex_factor_info info{};
+};
+
+namespace {
+
+void build_tasks(matex_factor_s& F)
+{
+    const Symbolic& s = F.sym;
+    std::vector<int32_t> fsn, ffirst, bsn, bfirst;
+    std::vector<int64_t> foff(s.n_levels + 1, 0), boff(s.n_levels + 1, 0);
+    std::vector<int32_t> flds(s.n_levels, 1), blds(s.n_levels, 1);
+    for (int lv = 0; lv < s.n_levels; ++lv) {
+        for (int32_t k : s.level_sn[lv]) {
+            const Supernode& q = s.sn[k];
+            for (int32_t r = 0; r < q.nr; r += FWD_ROWS) { fsn.push_back(k); ffirst.push_back(r); }
+            for (int32_t c = 0; c < q.nc; c += BWD_COLS) { bsn.push_back(k); bfirst.push_back(c); }
+            flds[lv] = std::max(flds[lv], q.nc);
+            blds[lv] = std::max(blds[lv], q.nr);
+        }
+        foff[lv + 1] = int64_t(fsn.size());
+        boff[lv + 1] = int64_t(bsn.size());
+    }
+    F.d_fwd_sn = upload(fsn);
+    F.d_fwd_first = upload(ffirst);
+    F.d_bwd_sn = upload(bsn);
+    F.d_bwd_first = upload(bfirst);
+    for (int lv = 0; lv < s.n_levels; ++lv) {
+        LevelTasks f{F.d_fwd_sn.as<int32_t>() + foff[lv], F.d_fwd_first.as<int32_t>() + foff[lv],
+                     int32_t(foff[lv + 1] - foff[lv]), flds[lv]};
+        LevelTasks b{F.d_bwd_sn.as<int32_t>() + boff[lv], F.d_bwd_first.as<int32_t>() + boff[lv],
+                     int32_t(boff[lv + 1] - boff[lv]), blds[lv]};
+        F.fwd.push_back(f);
+        F.bwd.push_back(b);
+    }
+}
+
+// x = A_which^-1 (scale .* b), all in the permuted ordering. tmp: [n], upd: [n_upd].
+void dev_solve(const matex_factor_s& F, int which, const double* b, const double* scale,
+               double* x, double* tmp, double* upd, const int32_t* done, hipStream_t st)
+{
+    const double* W = F.d_W[which].as<double>();
+    const int L = F.sym.n_levels;
+    for (int lv = 0; lv < L; ++lv) launch_forward(F.dsym, F.fwd[lv], W, b, scale, tmp, upd, done, st);
+    for (int lv = L - 1; lv >= 0; --lv) launch_backward(F.dsym, F.bwd[lv], W, tmp, x, done, st);
+}
+
+// Scratch of one Krylov process.
+struct Work {
+    int64_t n = 0;
+    DevMem V, w, tmp, upd, partial, ks, u, est, taus;
+    int64_t max_checks = 0;
+    Work(const matex_factor_s& F, int64_t max_chk) {
+        n = F.sym.n;
+        V = DevMem(sizeof(double) * n * (MAXM + 1));
+        w = DevMem(sizeof(double) * n);
+        tmp = DevMem(sizeof(double) * n);
+        upd = DevMem(sizeof(double) * std::max<int64_t>(1, F.sym.n_upd));
+        partial = DevMem(sizeof(double) * RED_BLOCKS * (MAXM + 3));
+        ks = DevMem(sizeof(KState));
+        HIPCHK(hipMemset(ks.p, 0, sizeof(KState)));
+        max_checks = std::max<int64_t>(1, max_chk);
+        u = DevMem(sizeof(double) * max_checks * MAXM);
+        est = DevMem(sizeof(double) * max_checks);
+        taus = DevMem(sizeof(double) * max_checks);
+    }
+    KState* kst() const { return ks.as<KState>(); }
+    const int32_t* done() const { return &ks.as<KState>()->done; }
+};
+
+struct KsHost {
+    int32_t done, converged, m, breakdown;
+};
+
+KsHost read_state(const Work& wk, KsHost* pinned, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(pinned, wk.ks.p, sizeof(KsHost), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return *pinned;
+}
+
+double read_est(const Work& wk, double* pinned, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(pinned, &wk.kst()->est, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return *pinned;
+}
+
+// One Krylov iteration j (0-based): w = M^-1 C v_j, two Gram-Schmidt passes,
+// v_{j+1}, column j of Ht, and the estimate over the check set.
+void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, int n_tau, double tol,
+                      int m_max, hipStream_t st)
+{
+    const int64_t n = wk.n;
+    double* V = wk.V.as<double>();
+    dev_solve(F, shift, V + int64_t(j) * n, F.d_cperm.as<double>(), wk.w.as<double>(),
+              wk.tmp.as<double>(), wk.upd.as<double>(), wk.done(), st);
+    launch_gs_dots(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
+    launch_gs_update(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
+    launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.kst(), wk.done(), st);
+    launch_checks(wk.kst(), F.gammas[shift], wk.taus.as<double>(), n_tau, tol, wk.u.as<double>(),
+                  wk.est.as<double>(), m_max, 1, st);
+}
+
+// Runs Alg. 1 from the (already normalised) V_0 until the device says done.
+// Returns the final host view of the state.
+KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, double tol, int m_max,
+                   int m_guess, KsHost* pinned, hipStream_t st)
+{
+    KsHost h = read_state(wk, pinned, st);
+    int j = 0;
+    int chunk = std::max(1, std::min(m_guess, m_max));
+    while (!h.done && j < m_max) {
+        int stop = std::min(m_max, j + chunk);
+        for (; j < stop; ++j) krylov_iteration(F, shift, wk, j, n_tau, tol, m_max, st);
+        h = read_state(wk, pinned, st);
+        chunk = 1;
+    }
+    return h;
+}
+
+int64_t checked_size(int64_t a) { return a < 0 ? 0 : a; }
+
+}  // namespace
+
+// --------------------------------------------------------------------- ABI
+
+extern "C" {
+
+const char* matex_version(void) { return "matex-mi355x 0.1 (gfx950, fp64)"; }
+
+size_t matex_last_error(char* buf, size_t len)
+{
+    if (!buf || len == 0) return g_err.size();
+    size_t k = std::min(len - 1, g_err.size());
+    std::memcpy(buf, g_err.data(), k);
+    buf[k] = 0;
+    return g_err.size();
+}
+
+matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_factor_opts* opts,
+                          void* stream, matex_factor_t* out)
+{
+    (void)stream;
+    if (!nl || !out) return fail(MATEX_E_INVALID, "null argument");
+    *out = nullptr;
+    const int64_t n = nl->n;
+    if (n <= 0 || n > INT32_MAX - 1) return fail(MATEX_E_INVALID, "n out of range");
+    if (!(gamma > 0.0)) return fail(MATEX_E_INVALID, "gamma must be > 0");
+    if (nl->n_branch < 0 || nl->n_pad < 0) return fail(MATEX_E_INVALID, "negative count");
+    if ((nl->n_branch && (!nl->br_a || !nl->br_b || !nl->br_g)) || !nl->c_node ||
+        (nl->n_pad && (!nl->pad_node || !nl->pad_g)))
+        return fail(MATEX_E_INVALID, "null array");
+    for (int64_t k = 0; k < nl->n_branch; ++k) {
+        if (nl->br_a[k] < 0 || nl->br_a[k] >= n || nl->br_b[k] < 0 || nl->br_b[k] >= n ||
+            nl->br_a[k] == nl->br_b[k])
+            return fail(MATEX_E_INVALID, "branch " + std::to_string(k) + " has a bad node id");
+        if (!(nl->br_g[k] > 0.0)) return fail(MATEX_E_INVALID, "branch conductance must be > 0");
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (!(nl->c_node[i] > 0.0)) return fail(MATEX_E_INVALID, "capacitance must be > 0");
+    for (int32_t k = 0; k < nl->n_pad; ++k) {
+        if (nl->pad_node[k] < 0 || nl->pad_node[k] >= n) return fail(MATEX_E_INVALID, "pad node id");
+        if (!(nl->pad_g[k] > 0.0)) return fail(MATEX_E_INVALID, "pad conductance must be > 0");
+    }
+    int n_shifts = (opts && opts->n_shifts > 0) ? opts->n_shifts : 4;
+    int leaf = (opts && opts->leaf_max > 0) ? opts->leaf_max : 16;
+    if (n_shifts > 12) return fail(MATEX_E_INVALID, "n_shifts must be <= 12");
+    try {
+        auto F = std::make_unique<matex_factor_s>();
+        HIPCHK(hipGetDevice(&F->device));
+        F->gamma = gamma;
+        F->vdd = nl->vdd;
+        for (int k = 0; k < n_shifts; ++k) F->gammas.push_back(gamma * std::pow(10.0, -k));
+        double t0 = now_s();
+        Csr G = assemble_g(n, nl->n_branch, nl->br_a, nl->br_b, nl->br_g, nl->n_pad,
+                           nl->pad_node, nl->pad_g);
+        F->sym = analyse(G, nl->coord, leaf);
+        const Symbolic& s = F->sym;
+        if (int64_t(s.max_nr) * 8 > 60 * 1024)
+            return fail(MATEX_E_UNSUPPORTED, "a supernode has more rows than the sweep kernels stage in LDS");
+        double t1 = now_s();
+        // numeric: all shifts and G in parallel host threads
+        std::vector<std::vector<double>> Wh(n_shifts + 1);
+        std::vector<int64_t> bad(n_shifts + 1, 0);
+        std::vector<double> zero(n, 0.0);
+        std::vector<std::thread> th;
+        for (int k = 0; k <= n_shifts; ++k) {
+            th.emplace_back([&, k]() {
+                if (k < n_shifts) bad[k] = factor_panels(s, G, F->gammas[k], nl->c_node, Wh[k], 1);
+                else bad[k] = factor_panels(s, G, 1.0, zero.data(), Wh[k], 1);
+            });
+        }
+        for (auto& t : th) t.join();
+        for (int k = 0; k <= n_shifts; ++k)
+            if (bad[k])
+                return fail(MATEX_E_NOT_SPD, std::string(k < n_shifts ? "C + gamma G" : "G") +
+                                                 " is not positive definite (pivot at column " +
+                                                 std::to_string(bad[k] - 1) + ")");
+        double t2 = now_s();
+        // upload
+        std::vector<int32_t> c0, nc, nr;
+        std::vector<int64_t> roff, w, u;
+        for (auto& q : s.sn) {
+            c0.push_back(q.c0); nc.push_back(q.nc); nr.push_back(q.nr);
+            roff.push_back(q.roff); w.push_back(q.w); u.push_back(q.u);
+        }
+        F->d_c0 = upload(c0); F->d_nc = upload(nc); F->d_nr = upload(nr);
+        F->d_roff = upload(roff); F->d_w = upload(w); F->d_u = upload(u);
+        F->d_rows = upload(s.rows.empty() ? std::vector<int32_t>{0} : s.rows);
+        F->d_upd_ptr = upload(s.upd_ptr);
+        F->d_upd_idx = upload(s.upd_idx.empty() ? std::vector<int64_t>{0} : s.upd_idx);
+        F->d_perm = upload(s.perm);
+        F->d_iperm = upload(s.iperm);
+        std::vector<double> cperm(n);
+        for (int64_t k = 0; k < n; ++k) cperm[k] = nl->c_node[s.perm[k]];
+        F->d_cperm = upload(cperm);
+        for (int k = 0; k <= n_shifts; ++k) {
+            F->d_W.push_back(upload(Wh[k]));
+            std::vector<double>().swap(Wh[k]);
+        }
+        F->dsym = DevSym{n, F->d_c0.as<int32_t>(), F->d_nc.as<int32_t>(), F->d_nr.as<int32_t>(),
+                         F->d_roff.as<int64_t>(), F->d_w.as<int64_t>(), F->d_u.as<int64_t>(),
+                         F->d_rows.as<int32_t>(), F->d_upd_ptr.as<int64_t>(),
+                         F->d_upd_idx.as<int64_t>()};
+        build_tasks(*F);
+        matex_factor_info& I = F->info;
+        I.n = n;
+        I.nnz_l = s.nnz_l;
+        I.panel_doubles = s.n_w;
+        I.n_supernodes = int32_t(s.sn.size());
+        I.n_levels = s.n_levels;
+        I.n_shifts = n_shifts;
+        I.max_nr = s.max_nr;
+        I.gamma = gamma;
+        I.seconds_analyse = t1 - t0;
+        I.seconds_numeric = t2 - t1;
+        I.device_bytes = int64_t(sizeof(double)) * s.n_w * (n_shifts + 1) +
+                         int64_t(sizeof(int64_t)) * (s.upd_idx.size() + s.upd_ptr.size()) +
+                         int64_t(sizeof(int32_t)) * (s.rows.size() + 3 * n);
+        *out = F.release();
+        return MATEX_OK;
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return fail(MATEX_E_OOM, "host allocation failed");
+    }
+}
+
+matex_status matex_factor_free(matex_factor_t f)
+{
+    delete f;
+    return MATEX_OK;
+}
+
+matex_status matex_factor_get_info(matex_factor_t f, matex_factor_info* info)
+{
+    if (!f || !info) return fail(MATEX_E_INVALID, "null argument");
+    *info = f->info;
+    return MATEX_OK;
+}
+
+matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const double* d_b,
+                         const double* d_scale, double* d_x, void* stream)
+{
+    if (!f || !d_b || !d_x || nrhs < 0) return fail(MATEX_E_INVALID, "bad argument");
+    const int n_shifts = int(f->gammas.size());
+    if (which < -1 || which >= n_shifts) return fail(MATEX_E_INVALID, "factor index out of range");
+    if (d_b == d_x) return fail(MATEX_E_INVALID, "d_b and d_x may not alias");
+    const int idx = which < 0 ? n_shifts : which;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = f->sym.n;
+    try {
+        DevMem bp(sizeof(double) * n), xp(sizeof(double) * n), tmp(sizeof(double) * n),
+            upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd)), sc;
+        const double* scale_p = nullptr;
+        if (d_scale) {
+            sc = DevMem(sizeof(double) * n);
+            launch_gather_perm(n, f->d_perm.as<int32_t>(), d_scale, sc.as<double>(), n, n, 1, st);
+            scale_p = sc.as<double>();
+        }
+        for (int r = 0; r < nrhs; ++r) {
+            launch_gather_perm(n, f->d_perm.as<int32_t>(), d_b + int64_t(r) * n, bp.as<double>(), n,
+                               n, 1, st);
+            dev_solve(*f, idx, bp.as<double>(), scale_p, xp.as<double>(), tmp.as<double>(),
+                      upd.as<double>(), nullptr, st);
+            launch_scatter_perm(n, f->d_perm.as<int32_t>(), xp.as<double>(), d_x + int64_t(r) * n,
+                                n, n, 1, st);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        return MATEX_OK;
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+}
+
+matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, const double* d_v,
+                               int32_t n_tau, const double* tau, int32_t m_max, double tol,
+                               double* d_out, int32_t* m_used, double* est, void* stream)
+{
+    if (!f || !d_v || !d_out || !tau || nrhs < 0 || n_tau <= 0)
+        return fail(MATEX_E_INVALID, "bad argument");
+    if (shift < 0 || shift >= int(f->gammas.size())) return fail(MATEX_E_INVALID, "shift out of range");
+    if (m_max < 1 || m_max > MAXM) return fail(MATEX_E_INVALID, "m_max must be in 1..32");
+    if (!(tol >= 0.0)) return fail(MATEX_E_INVALID, "tol must be >= 0");
+    for (int k = 0; k < n_tau; ++k)
+        if (!(tau[k] > 0.0)) return fail(MATEX_E_INVALID, "tau must be > 0");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = f->sym.n;
+    bool all_conv = true;
+    try {
+        Work wk(*f, n_tau);
+        PinnedMem pin(256);
+        DevMem zero(sizeof(double) * n), acc(sizeof(double) * n);
+        HIPCHK(hipMemsetAsync(zero.p, 0, zero.bytes, st));
+        HIPCHK(hipMemcpyAsync(wk.taus.p, tau, sizeof(double) * n_tau, hipMemcpyHostToDevice, st));
+        double* V = wk.V.as<double>();
+        for (int r = 0; r < nrhs; ++r) {
+            // V_0 = P v_r / ||v_r|| (setup with y0 = z2 = 0)
+            launch_gather_perm(n, f->d_perm.as<int32_t>(), d_v + int64_t(r) * n, acc.as<double>(),
+                               n, n, 1, st);
+            launch_setup_v(n, acc.as<double>(), zero.as<double>(), zero.as<double>(), V,
+                           wk.partial.as<double>(), wk.kst(), st);
+            launch_normalize_v(n, V, wk.kst(), st);
+            KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, 6, pin.as<KsHost>(), st);
+            if (!h.converged) all_conv = false;
+            if (m_used) m_used[r] = h.m;
+            if (est) est[r] = read_est(wk, pin.as<double>() + 8, st);
+            for (int k = 0; k < n_tau; ++k) {
+                // out = beta V u(tau_k), reconstructed with y0 = z1 = z2 = 0
+                launch_recon_full(n, 0.0, wk.u.as<double>() + int64_t(k) * MAXM, wk.kst(), V, n,
+                                  acc.as<double>(), zero.as<double>(), zero.as<double>(),
+                                  zero.as<double>(), st);
+                launch_scatter_perm(n, f->d_perm.as<int32_t>(), acc.as<double>(),
+                                    d_out + n * (r + int64_t(nrhs) * k), n, n, 1, st);
+            }
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    if (!all_conv) return fail(MATEX_E_NOCONV, "estimate >= tol at m_max");
+    return MATEX_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ transient
+
+namespace {
+
+constexpr double FS = 1e-15;
+
+struct Segment {
+    // planner output for one transition spot: slope changes at that time
+    int64_t t;
+    std::vector<int32_t> node;   // permuted rows
+    std::vector<double> dslope;  // A/s
+};
+
+// Transition spots of one subtask and the slope changes of its sources at
+// each (Sec. 2.2: the input is linear between spots; Sec. 3.1: LTS).
+std::vector<Segment> plan_spots(const matex_problem* p, const std::vector<int32_t>& srcs,
+                                const std::vector<int32_t>& iperm)
+{
+    std::map<int64_t, std::map<int32_t, double>> ev;
+    ev[0];
+    ev[p->t_end];
+    for (int32_t k : srcs) {
+        const int64_t d = p->delay[k], r = p->rise[k], w = p->width[k], f = p->fall[k];
+        const double a = p->amp[k];
+        const int32_t row = iperm[p->node[k]];
+        const int64_t t[4] = {d, d + r, d + r + w, d + r + w + f};
+        const double ds[4] = {a / (double(r) * FS), -a / (double(r) * FS), -a / (double(f) * FS),
+                              a / (double(f) * FS)};
+        for (int q = 0; q < 4; ++q)
+            if (t[q] >= 0 && t[q] < p->t_end) ev[t[q]][row] += ds[q];
+    }
+    std::vector<Segment> out;
+    for (auto& kv : ev) {
+        Segment s;
+        s.t = kv.first;
+        for (auto& e : kv.second) {
+            s.node.push_back(e.first);
+            s.dslope.push_back(e.second);
+        }
+        out.push_back(std::move(s));
+    }
+    return out;
+}
+
+}  // namespace
+
+extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p,
+                                        const matex_run_opts* o, double* d_probe_out,
+                                        double* d_final, matex_stats* stats, void* stream)
+{
+    const double t_start = now_s();
+    if (!f || !p || !o || !d_probe_out) return fail(MATEX_E_INVALID, "null argument");
+    const int64_t n = f->sym.n;
+    if (p->n_src < 0 || p->n_out <= 0 || p->n_probe < 0 || p->t_end <= 0)
+        return fail(MATEX_E_INVALID, "bad sizes");
+    if (p->n_src > 0 && (!p->node || !p->amp || !p->delay || !p->rise || !p->width || !p->fall))
+        return fail(MATEX_E_INVALID, "null source array");
+    if (!p->t_out || (p->n_probe > 0 && !p->probe)) return fail(MATEX_E_INVALID, "null array");
+    if (o->mode != MATEX_PLAIN) return fail(MATEX_E_UNSUPPORTED, "only MATEX_PLAIN is implemented");
+    if (o->m_max < 1 || o->m_max > MAXM) return fail(MATEX_E_INVALID, "m_max must be in 1..32");
+    if (!(o->tol > 0.0)) return fail(MATEX_E_INVALID, "tol must be > 0");
+    const int64_t h_min = std::max<int64_t>(1, o->h_min);
+    for (int32_t k = 0; k < p->n_src; ++k) {
+        if (p->node[k] < 0 || p->node[k] >= n) return fail(MATEX_E_INVALID, "source node out of range");
+        if (p->delay[k] < 0 || p->rise[k] <= 0 || p->fall[k] <= 0 || p->width[k] < 0)
+            return fail(MATEX_E_INVALID, "pulse timing out of range");
+        if (p->group && p->group[k] < 0) return fail(MATEX_E_INVALID, "negative group");
+    }
+    for (int32_t k = 0; k < p->n_out; ++k) {
+        if (p->t_out[k] < 0 || p->t_out[k] > p->t_end) return fail(MATEX_E_INVALID, "t_out outside [0, t_end]");
+        if (k && p->t_out[k] <= p->t_out[k - 1]) return fail(MATEX_E_INVALID, "t_out not increasing");
+    }
+    for (int32_t k = 0; k < p->n_probe; ++k)
+        if (p->probe[k] < 0 || p->probe[k] >= n) return fail(MATEX_E_INVALID, "probe out of range");
+
+    // subtasks (Sec. 3.1)
+    std::map<int32_t, std::vector<int32_t>> groups;
+    for (int32_t k = 0; k < p->n_src; ++k) groups[p->group ? p->group[k] : 0].push_back(k);
+    if (groups.empty()) groups[0];
+
+    matex_stats S{};
+    const char* trace_env = std::getenv("MATEX_TRACE");
+    const bool trace = trace_env && trace_env[0] == '1';
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int n_shifts = int(f->gammas.size());
+    const int32_t n_out = p->n_out, n_probe = p->n_probe;
+    try {
+        // largest check set: outputs inside one spot interval + 1
+        Work wk(*f, int64_t(n_out) + 1);
+        PinnedMem pin(4096);
+        KsHost* hks = pin.as<KsHost>();
+        double* hest = pin.as<double>() + 16;
+        int64_t stage_cap = 1 << 16;
+        std::unique_ptr<PinnedMem> stage(new PinnedMem(stage_cap));
+        DevMem d_ev(stage_cap);
+        DevMem y(sizeof(double) * n), y0(sizeof(double) * n), z1(sizeof(double) * n),
+            z2(sizeof(double) * n), sl(sizeof(double) * n), ysum(sizeof(double) * n);
+        DevMem probe_perm(sizeof(int32_t) * std::max(1, n_probe));
+        {
+            std::vector<int32_t> pp(n_probe);
+            for (int32_t k = 0; k < n_probe; ++k) pp[k] = f->sym.iperm[p->probe[k]];
+            if (n_probe)
+                HIPCHK(hipMemcpy(probe_perm.p, pp.data(), sizeof(int32_t) * n_probe, hipMemcpyHostToDevice));
+        }
+        HIPCHK(hipMemsetAsync(d_probe_out, 0, sizeof(double) * int64_t(n_probe) * n_out, st));
+        HIPCHK(hipMemsetAsync(ysum.p, 0, ysum.bytes, st));
+        const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
+        const double* cperm = f->d_cperm.as<double>();
+        double* V = wk.V.as<double>();
+        int m_guess = 6;
+
+        for (auto& grp : groups) {
+            S.subtasks++;
+            std::vector<Segment> spots = plan_spots(p, grp.second, f->sym.iperm);
+            for (DevMem* b : {&y, &y0, &z1, &z2, &sl}) HIPCHK(hipMemsetAsync(b->p, 0, b->bytes, st));
+            int64_t t_a = 0;
+            size_t k_spot = 0;
+            while (t_a < p->t_end) {
+                // new input slope at a transition spot: z1 = G^-1 s, z2 = G^-1 C z1
+                if (k_spot < spots.size() && spots[k_spot].t == t_a) {
+                    const Segment& sg = spots[k_spot];
+                    const int32_t cnt = int32_t(sg.node.size());
+                    if (cnt > 0) {
+                        size_t need = cnt * (sizeof(int32_t) + sizeof(double)) + 16;
+                        if (int64_t(need) > stage_cap) {
+                            HIPCHK(hipStreamSynchronize(st));
+                            stage_cap = int64_t(need) * 2;
+                            stage.reset(new PinnedMem(stage_cap));
+                            d_ev = DevMem(stage_cap);
+                        }
+                        HIPCHK(hipStreamSynchronize(st));   // staging buffer reuse
+                        double* hv = stage->as<double>();
+                        int32_t* hi = reinterpret_cast<int32_t*>(hv + cnt);
+                        std::memcpy(hv, sg.dslope.data(), sizeof(double) * cnt);
+                        std::memcpy(hi, sg.node.data(), sizeof(int32_t) * cnt);
+                        HIPCHK(hipMemcpyAsync(d_ev.p, stage->p, need, hipMemcpyHostToDevice, st));
+                        double* dv = d_ev.as<double>();
+                        launch_scatter_add(cnt, reinterpret_cast<int32_t*>(dv + cnt), dv, sl.as<double>(), st);
+                        dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
+                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
+                        dev_solve(*f, n_shifts, z1.as<double>(), cperm, z2.as<double>(),
+                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
+                        S.solve_pairs_g += 2;
+                    }
+                    k_spot++;
+                }
+                const int64_t t_b0 = spots[k_spot].t;   // next spot
+                // check offsets: outputs in (t_a, t_b] and the step end
+                auto lo = std::upper_bound(tout.begin(), tout.end(), t_a);
+                auto hi = std::upper_bound(tout.begin(), tout.end(), t_b0);
+                std::vector<int64_t> offs;
+                for (auto it = lo; it != hi; ++it) offs.push_back(*it - t_a);
+                if (offs.empty() || offs.back() != t_b0 - t_a) offs.push_back(t_b0 - t_a);
+                const int32_t snap0 = int32_t(lo - tout.begin());
+                // shift ladder
+                int ksh = n_shifts - 1;
+                for (int k = 0; k < n_shifts; ++k)
+                    if (double(offs[0]) * FS >= 0.1 * f->gammas[k]) { ksh = k; break; }
+                auto cut = [&](int k) {
+                    if (k == 0) return;
+                    const double lim = 10.0 * f->gammas[k];
+                    size_t cnt = 0;
+                    while (cnt < offs.size() && double(offs[cnt]) * FS <= lim) cnt++;
+                    offs.resize(std::max<size_t>(1, cnt));
+                };
+                cut(ksh);
+                KsHost h{};
+                while (true) {
+                    std::vector<double> taus(offs.size());
+                    for (size_t q = 0; q < offs.size(); ++q) taus[q] = double(offs[q]) * FS;
+                    HIPCHK(hipStreamSynchronize(st));
+                    std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
+                    HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
+                                          hipMemcpyHostToDevice, st));
+                    launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
+                                   wk.partial.as<double>(), wk.kst(), st);
+                    launch_normalize_v(n, V, wk.kst(), st);
+                    h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, m_guess, hks, st);
+                    S.bases++;
+                    S.solve_pairs_m += h.m;
+                    S.krylov_dims += h.m;
+                    S.m_peak = std::max(S.m_peak, h.m);
+                    if (h.m > 0) m_guess = h.m;
+                    if (h.converged || ksh + 1 == n_shifts) break;
+                    ksh++;
+                    S.shift_downs++;
+                    cut(ksh);
+                }
+                if (!h.converged) {
+                    // halve the step with the same basis until the checks pass
+                    int64_t hstep = offs.back();
+                    while (true) {
+                        hstep /= 2;
+                        S.halvings++;
+                        if (hstep < h_min)
+                            return fail(MATEX_E_NOCONV, "no convergence at t = " + std::to_string(t_a) + " fs");
+                        std::vector<int64_t> o2;
+                        for (int64_t v : offs)
+                            if (v < hstep) o2.push_back(v);
+                        o2.push_back(hstep);
+                        std::vector<double> taus(o2.size());
+                        for (size_t q = 0; q < o2.size(); ++q) taus[q] = double(o2[q]) * FS;
+                        HIPCHK(hipStreamSynchronize(st));
+                        std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
+                        HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
+                                              hipMemcpyHostToDevice, st));
+                        launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), int(taus.size()),
+                                      o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
+                        KsHost hh = read_state(wk, hks, st);
+                        if (hh.converged) { offs = o2; break; }
+                    }
+                }
+                const int64_t t_b = t_a + offs.back();
+                if (trace) {
+                    const double e = read_est(wk, hest, st);
+                    fprintf(stderr, "[matex] seg t_a=%lld t_b=%lld shift=%d m=%d conv=%d est=%.3e checks=%zu\n",
+                            (long long)t_a, (long long)t_b, ksh, h.m, h.converged, e, offs.size());
+                }
+                // snapshots (Alg. 2 reuse) at the probes, then the full state at t_b
+                int n_snap = 0;
+                while (snap0 + n_snap < n_out && tout[snap0 + n_snap] <= t_b) n_snap++;
+                launch_recon_probes(n_probe, probe_perm.as<int32_t>(), n_snap, snap0, wk.taus.as<double>(),
+                                    wk.u.as<double>(), wk.kst(), V, n, y0.as<double>(), z1.as<double>(),
+                                    z2.as<double>(), d_probe_out, n_out, st);
+                launch_recon_full(n, double(offs.back()) * FS,
+                                  wk.u.as<double>() + int64_t(offs.size() - 1) * MAXM, wk.kst(), V, n,
+                                  y.as<double>(), y0.as<double>(), z1.as<double>(), z2.as<double>(), st);
+                S.segments++;
+                t_a = t_b;
+            }
+            launch_axpy_scaled(n, 1.0, y.as<double>(), ysum.as<double>(), st);
+        }
+        launch_vdd_minus(int64_t(n_probe) * n_out, f->vdd, d_probe_out, st);
+        if (d_final) {
+            launch_scatter_perm(n, f->d_perm.as<int32_t>(), ysum.as<double>(), d_final, n, n, 1, st);
+            launch_vdd_minus(n, f->vdd, d_final, st);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return fail(MATEX_E_OOM, "host allocation failed");
+    }
+    S.seconds = now_s() - t_start;
+    if (stats) *stats = S;
+    return MATEX_OK;
+}
+
+extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
+                                      const double* d_dJdx, double* d_grad_amp, double* d_grad_c,
+                                      void* stream)
+{
+    (void)f; (void)p; (void)o; (void)d_dJdx; (void)d_grad_amp; (void)d_grad_c; (void)stream;
+    return fail(MATEX_E_UNSUPPORTED, "matex_adjoint is not provided by this build");
+}

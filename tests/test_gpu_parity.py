@@ -1,0 +1,173 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Every input is a seeded synthetic grid; expected values come from the oracle
+(R-MATEX written from the paper, its sparse Cholesky, and the exact modal
+solution), never from the GPU path."""
+import numpy as np
+import pytest
+
+from oracle import circuit as C
+from oracle import reference as R
+from oracle import rmatex as RM
+from paper_1511_04519_amd import instances as I
+from paper_1511_04519_amd import matex as M
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+DEV = "cuda:0"
+GAMMA = 1e-11
+
+
+def _dev(a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def _note(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+# ------------------------------------------------------------------- solve
+
+@pytest.mark.parametrize("which", [-1, 0, 1, 3])
+@pytest.mark.parametrize("case", ["config0", "2x13x11", "3x9x20"])
+def test_solve_pair_matches_oracle(case, which):
+    """One forward/backward substitution pair (Alg. 1) on G or C + gamma_k G."""
+    _note(f"solve {case} which={which}")
+    if case == "config0":
+        p = I.config0()
+    else:
+        L, nx, ny = map(int, case.split("x"))
+        p = I.small(7, layers=L, nx=nx, ny=ny, n_src=3)
+    nl = p.netlist
+    F = M.matex_factor(nl, GAMMA, n_shifts=4)
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal((3, nl.n))
+    rp, ci, gv = C.assemble_G(nl)
+    if which < 0:
+        vals, scale = gv, None
+    else:
+        vals = C.csr_add_diag(rp, ci, gv, nl.c_node, alpha=GAMMA * 10.0 ** (-which))
+        scale = nl.c_node
+    ref = C.Cholesky(rp, ci, vals).solve((b * (scale if scale is not None else 1.0)).T).T
+    x = M.matex_solve(F, which, _dev(b), _dev(scale) if scale is not None else None)
+    x = x.cpu().numpy()
+    assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+# ------------------------------------------------------------ krylov step
+
+def test_krylov_step_matches_oracle_and_dense_expm():
+    _note("krylov_step config0")
+    import scipy.linalg
+    p = I.config0()
+    nl = p.netlist
+    F = M.matex_factor(nl, GAMMA)
+    rng = np.random.default_rng(5)
+    v = rng.random((2, nl.n)) * 1e-3
+    taus = np.array([2e-12, 7.5e-12, 3e-11, 2e-10])
+    tol = 1e-12
+    out, m_used, est, ok = M.matex_krylov_step(F, _dev(v), taus, shift=0, m_max=24, tol=tol)
+    out = out.cpu().numpy()
+    orc = RM.RMatex(nl, GAMMA)
+    rp, ci, gv = C.assemble_G(nl)
+    A = -C.csr_dense(rp, ci, gv) / nl.c_node[:, None]
+    assert ok
+    for r in range(2):
+        ref, m_ref, est_ref, ok_ref = orc.expv(v[r], taus, tol, 24)
+        assert ok_ref
+        assert abs(int(m_used[r]) - m_ref) <= 1
+        assert est[r] < tol
+        for k, t in enumerate(taus):
+            exact = scipy.linalg.expm(t * A) @ v[r]
+            # both within the tolerance of the exact value; same m -> rounding apart
+            assert np.linalg.norm(out[k, r] - exact) <= 2 * tol
+            assert np.linalg.norm(out[k, r] - ref[:, k]) <= (1e-13 if m_used[r] == m_ref else 3 * tol)
+
+
+def test_krylov_step_eigenvector_exact_at_m1():
+    """Lemma of Sec. 3.3.3: a generalized eigenvector gives e^{lam t} u, m = 1."""
+    _note("krylov_step eigenvector")
+    from tests.helpers import uniform_mesh
+    k, Rb, c, g0 = 9, 0.7, 3e-14, 0.02
+    nl = uniform_mesh(k, Rb, c, g0)
+    F = M.matex_factor(nl, GAMMA)
+    ii, jj = np.meshgrid(np.arange(k), np.arange(k), indexing="ij")
+    u = (np.cos(np.pi * 2 * (ii + 0.5) / k) * np.cos(np.pi * 5 * (jj + 0.5) / k)).ravel()
+    lam = -(g0 + (2 / Rb) * (2 - np.cos(np.pi * 2 / k) - np.cos(np.pi * 5 / k))) / c
+    taus = np.array([1e-13, 3e-12, 4e-11])
+    out, m_used, est, ok = M.matex_krylov_step(F, _dev(u), taus, tol=1e-14)
+    assert ok and m_used[0] == 1
+    for q, t in enumerate(taus):
+        assert np.abs(out[q, 0].cpu().numpy() - np.exp(lam * t) * u).max() <= 1e-13
+
+
+# -------------------------------------------------------------- transient
+
+SMALL = [(101, 1, 8, 8, 5), (102, 2, 13, 11, 9), (103, 1, 21, 17, 14), (104, 3, 9, 12, 7)]
+
+
+@pytest.mark.parametrize("seed,layers,nx,ny,nsrc", SMALL)
+def test_transient_small_matches_oracle_and_modal(seed, layers, nx, ny, nsrc):
+    _note(f"transient small seed={seed} {layers}x{nx}x{ny}")
+    p = I.small(seed, layers=layers, nx=nx, ny=ny, n_src=nsrc, t_end=3 * I.NS)
+    F = M.matex_factor(p.netlist, GAMMA)
+    x, xf, st = M.matex_transient(F, p, tol=1e-12, m_max=20)
+    x = x.cpu().numpy()
+    xo, yo_end = RM.RMatex(p.netlist, GAMMA).transient(p, tol=1e-12, m_max=20)
+    ym, ym_end = R.modal(p)
+    assert np.abs(x - (p.netlist.vdd - ym)).max() <= 1e-10
+    assert np.abs(x - xo).max() <= 1e-10
+    assert np.abs(xf.cpu().numpy() - (p.netlist.vdd - ym_end)).max() <= 1e-10
+    assert st["bases"] >= 1 and st["m_peak"] <= 20
+
+
+def test_transient_config0_matches_modal_truth():
+    """32x32 workload, full window and outputs: relative error <= 1e-9."""
+    _note("transient config0")
+    p = I.config0()
+    F = M.matex_factor(p.netlist, p.gamma)
+    x, xf, st = M.matex_transient(F, p, tol=1e-11, m_max=p.m_max)
+    x = x.cpu().numpy()
+    ym, _ = R.modal(p)
+    err = np.abs(x - (p.netlist.vdd - ym)).max() / np.abs(x).max()
+    print("config0 stats", st, "rel err", err, flush=True)
+    assert err <= 1e-9
+
+
+def test_transient_subtasks_superpose():
+    """Sec. 3.1: grouped subtasks summed equal the undivided run."""
+    _note("transient subtasks")
+    p = I.small(201, layers=2, nx=12, ny=10, n_src=16, t_end=3 * I.NS, n_groups=5)
+    F = M.matex_factor(p.netlist, GAMMA)
+    x_dec, _, st = M.matex_transient(F, p, tol=1e-12)
+    assert st["subtasks"] == len(np.unique(p.sources.group))
+    p.sources.group[:] = 0
+    x_one, _, st1 = M.matex_transient(F, p, tol=1e-12)
+    ym, _ = R.modal(p)
+    assert st1["subtasks"] == 1
+    assert np.abs(x_dec.cpu().numpy() - x_one.cpu().numpy()).max() <= 1e-10
+    assert np.abs(x_dec.cpu().numpy() - (1.0 - ym)).max() <= 1e-10
+
+
+def test_transient_edge_cases():
+    _note("transient edge cases")
+    p = I.small(301, nx=7, ny=5, n_src=3, t_end=1 * I.NS)
+    F = M.matex_factor(p.netlist, GAMMA)
+    # no sources: the grid stays at Vdd
+    q = I.Problem("empty", p.netlist, I.Sources(*(np.zeros(0, dt) for dt in
+                  (np.int32, float, np.int64, np.int64, np.int64, np.int64, np.int32))),
+                  p.t_end, p.t_out, p.probe)
+    x, xf, st = M.matex_transient(F, q)
+    assert np.array_equal(x.cpu().numpy(), np.full(x.shape, p.netlist.vdd))
+    # a single output time that is not 0, probes repeated and on pads
+    q = I.Problem("one-out", p.netlist, p.sources, p.t_end, np.array([p.t_end // 3]),
+                  np.array([0, 0, p.netlist.pad_node[0], 5], np.int32))
+    x, _, _ = M.matex_transient(F, q, tol=1e-12)
+    ym, _ = R.modal(q)
+    assert np.abs(x.cpu().numpy() - (1.0 - ym)).max() <= 1e-10
+    # invalid: decreasing output times
+    q = I.Problem("bad", p.netlist, p.sources, p.t_end, np.array([10, 5]), p.probe)
+    with pytest.raises(M.MatexError) as e:
+        M.matex_transient(F, q)
+    assert e.value.status == M.MATEX_E_INVALID
