@@ -1,0 +1,147 @@
+#!/usr/bin/env python
+"""Benchmark of the R-MATEX transient on one MI355X.
+
+One step = one full transient (every step of the hot path: segment planning,
+G solves for the F/P terms of Eq. 6, rational Arnoldi with substitution pairs
+on C + gamma_k G, Gram-Schmidt, the small Pade exponential, reconstruction at
+the output times) of the 2 x 300 x 300 grid (180,000 nodes, 400 pads, 2000
+pulse sources, 20 ns window, 2001 output times at 512 probe rows), inputs
+resident on the device. Factorisation is set-up and excluded, as the paper
+excludes LU from its transient times.
+
+metric value: node-steps/s = n * N_out / transient seconds.
+roofline: the substitution-pair sweeps (the dominant kernels), algorithmic
+bytes per pair over the event-timed mean pair duration, against 8 TB/s.
+cpu_baseline: the CPU oracle, single-threaded, on the first part of the same
+window (a bounded sample), scaled to node-steps/s.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "SpTRSV HBM GB/s + transient node·steps/s, batched vs plain, at 1e-9 rel err"
+
+
+def cpu_baseline(prob, tol, window_fs, threads=1):
+    """Oracle R-MATEX on [0, window_fs] of the same workload, in a child
+    process pinned to `threads` BLAS threads; returns a dict."""
+    code = f"""
+import os, sys, time, json
+sys.path.insert(0, {ROOT!r})
+import numpy as np
+from paper_1511_04519_amd import instances as I
+from oracle import rmatex as RM
+p = I.config1()
+T = {int(window_fs)}
+q = I.Problem('head', p.netlist, p.sources, T, p.t_out[p.t_out <= T], p.probe)
+t0 = time.time(); s = RM.RMatex(p.netlist, p.gamma); tf = time.time() - t0
+t0 = time.time(); s.transient(q, tol={tol!r}, m_max=p.m_max); tt = time.time() - t0
+print(json.dumps(dict(factor_s=tf, transient_s=tt, n=p.netlist.n, n_out=int(q.t_out.size),
+                      bases=s.stats.bases, pairs=s.stats.solve_pairs_M + s.stats.solve_pairs_G)))
+"""
+    env = dict(os.environ, OPENBLAS_NUM_THREADS=str(threads), OMP_NUM_THREADS=str(threads),
+               MKL_NUM_THREADS=str(threads))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
+                         timeout=900)
+    if out.returncode != 0:
+        raise RuntimeError(out.stderr[-2000:])
+    d = json.loads(out.stdout.strip().splitlines()[-1])
+    d["value"] = d["n"] * d["n_out"] / d["transient_s"]
+    return d
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--window-ps", type=int, default=0, help="shorten the window (0 = full)")
+    ap.add_argument("--cpu-window-ps", type=int, default=30)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_1511_04519_amd import instances as I
+    from paper_1511_04519_amd import matex as M
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    M.lib()   # fails loudly if libmatex.so is missing
+    p = I.config1()
+    if args.window_ps:
+        T = args.window_ps * I.PS
+        p = I.Problem(p.name + f" (first {args.window_ps} ps)", p.netlist, p.sources, T,
+                      p.t_out[p.t_out <= T], p.probe)
+    n, n_out = p.netlist.n, p.t_out.size
+    t0 = time.time()
+    F = M.matex_factor(p.netlist, p.gamma)
+    factor_s = time.time() - t0
+    print(f"[bench] factor {factor_s:.2f} s (host analyse {F.info['seconds_analyse']:.2f} s, "
+          f"numeric {F.info['seconds_numeric']:.2f} s), nnz(L) {F.info['nnz_l']}, "
+          f"levels {F.info['n_levels']}", flush=True)
+
+    for w in range(args.warmup):
+        M.matex_transient(F, p, tol=args.tol, m_max=p.m_max)
+        print(f"[bench] warmup {w + 1}/{args.warmup} done", flush=True)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for k in range(args.steps):
+        x, xf, st = M.matex_transient(F, p, tol=args.tol, m_max=p.m_max)
+        print(f"[bench] step {k + 1}/{args.steps}: {st['seconds']:.2f} s, segments {st['segments']}, "
+              f"bases {st['bases']}, pairs {st['solve_pairs_m']}+{st['solve_pairs_g']}", flush=True)
+    torch.cuda.synchronize()
+    dt = (time.time() - t0) / args.steps
+    value = n * n_out / dt
+
+    # parity spot check against the oracle's stored head of the window
+    gold = np.load(os.path.join(ROOT, "tests/golden/config1_head.npz"))
+    k_head = int((p.t_out <= int(gold["t_end"])).sum())
+    err_head = float(np.abs(x[:, :k_head].cpu().numpy() - gold["x"][:, :k_head]).max())
+
+    # live roofline of the substitution-pair sweeps (event-timed)
+    pair_s, pair_b = M.matex_time_solves(F, which=0, reps=50)
+    achieved = pair_b / pair_s / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+                "kernel": "substitution pair (forward+backward sweeps, C + gamma G)",
+                "pair_us": round(pair_s * 1e6, 2), "pair_bytes": int(pair_b)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        d = cpu_baseline(p, args.tol, args.cpu_window_ps * I.PS)
+        cpu = {"value": d["value"], "unit": "node*steps/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle R-MATEX, same grid and tol, window [0, {args.cpu_window_ps} ps] "
+                         f"({d['n_out']} outputs, {d['bases']} bases, {d['pairs']} solve pairs, "
+                         f"{d['transient_s']:.1f} s; factor {d['factor_s']:.1f} s excluded)"}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "node*steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded 2x300x300 RC grid, 2000 pulse sources)",
+        "config": {"workload": p.name, "n": n, "n_out": int(n_out), "n_probe": int(p.probe.size),
+                   "mode": "plain", "tol": args.tol, "gamma": p.gamma, "m_max": p.m_max,
+                   "factor_s": round(factor_s, 2), "segments": st["segments"],
+                   "bases": st["bases"], "solve_pairs": st["solve_pairs_m"] + st["solve_pairs_g"],
+                   "max_abs_err_vs_oracle_head": err_head},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -160,6 +160,8 @@ typedef struct {
     int32_t m_max;           /* largest Krylov dimension, 1..32                  */
     int32_t mode;            /* MATEX_PLAIN: subtasks one after another          */
     int64_t h_min;           /* smallest step after halving (fs), >= 1           */
+    double shift_ratio;      /* ladder rule: a step uses the largest gamma_k with
+                                tau_1 >= shift_ratio * gamma_k (0 = default 1.0)  */
 } matex_run_opts;
 
 typedef struct {
@@ -185,7 +187,7 @@ typedef struct {
  * Step rule: a basis is built at every transition spot of the subtask and
  * reused for the output times before the next spot; the shift of the ladder
  * is chosen from the first check offset tau_1 of the step (the largest
- * gamma_k with tau_1 >= gamma_k/10; below the top shift the step ends at
+ * gamma_k with tau_1 >= shift_ratio * gamma_k; below the top shift the step ends at
  * the last check offset <= 10 gamma_k); without convergence at m_max the
  * step is retried one shift lower, and with the smallest shift it is halved
  * down to h_min. Stats may be NULL.
@@ -204,6 +206,17 @@ matex_status matex_transient(matex_factor_t f, const matex_problem* p, const mat
 matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
                            const double* d_dJdx, double* d_grad_amp, double* d_grad_c,
                            void* stream);
+
+/*
+ * matex_time_solves - `reps` substitution pairs (Alg. 1, U \ (L \ (C v)))
+ * with factor `which` (as in matex_solve), back to back on `stream`, on
+ * library-owned device vectors, timed with HIP events recorded on that
+ * stream around the batch. Writes the mean seconds per pair to *seconds and
+ * the algorithmic bytes of one pair (panel values and indices read once per
+ * sweep, plus the vectors) to *bytes. For measurement only.
+ */
+matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t reps, double* seconds,
+                               double* bytes, void* stream);
 
 /* Copies the calling thread's last error text (NUL-terminated) into buf. */
 size_t matex_last_error(char* buf, size_t len);

@@ -42,10 +42,10 @@ Readings where the paper is silent:
     two transition spots a few fs apart, or an output time just after a spot,
     ask for far shorter steps. So C + gamma_k G is factored once for each
     gamma_k = gamma * 10^-k, k < K (no refactorisation in the time loop). A
-    segment uses the largest gamma_k with tau_1 >= gamma_k / 10, tau_1 being
-    its first check offset; with k > 0 the segment is cut after the last
-    check offset <= 10 gamma_k and the rest starts a new segment (same input
-    slope).
+    segment uses the largest gamma_k with tau_1 >= rho * gamma_k, tau_1 being
+    its first check offset (rho = 1 by default: gamma near the step, as
+    Sec. 3.3.2 advises); with k > 0 the segment is cut after the last check
+    offset <= 10 gamma_k and the rest starts a new segment (same input slope).
   * If m_max is reached without convergence, the segment is tried again with
     the next smaller shift (cut as above). With the smallest shift, the
     segment end is halved (in whole fs) until the checks that remain pass with
@@ -68,17 +68,17 @@ class NoConvergence(RuntimeError):
     pass
 
 
-LADDER_LO = 0.1    # a shift serves check offsets tau >= LADDER_LO * gamma_k
+LADDER_LO = 1.0    # a shift serves check offsets tau >= LADDER_LO * gamma_k
 LADDER_HI = 10.0   # ... and, below the top shift, tau <= LADDER_HI * gamma_k
 
 
-def pick_shift(gammas, offsets_fs):
+def pick_shift(gammas, offsets_fs, lo=LADDER_LO):
     """Index of the shift for a segment whose sorted check offsets (fs) are
     given, and how many leading offsets it may cover."""
     tau1 = offsets_fs[0] * FS
     k = len(gammas) - 1
     for i, g in enumerate(gammas):
-        if tau1 >= LADDER_LO * g:
+        if tau1 >= lo * g:
             k = i
             break
     if k == 0:
@@ -201,19 +201,24 @@ class RMatex:
 
     # ---------------------------------------------------------- Alg. 2
     def subtask(self, src, idx, t_end: int, t_out: np.ndarray, probe, tol: float,
-                m_max: int, safety: float = 1.0, h_min: int = 1):
+                m_max: int, safety: float = 1.0, h_min: int = 1, shift_ratio: float = LADDER_LO,
+                t_start: int = 0):
         """Transient of one subtask (sources `idx`). Returns (y at probe rows for
-        every t_out [n_probe x n_out], y(t_end) [n])."""
+        every t_out [n_probe x n_out], y(t_end) [n]). The run starts at t_start
+        from the quasi-static state G^-1 i(t_start), which is exact at 0 (no
+        source draws current before its delay) and otherwise forgets its error
+        at the rate of the slowest mode; outputs before t_start stay 0."""
         n = self.n
         ts = transition_spots(src, idx, t_end)
-        y = self.Gf.solve(current(src, idx, n, 0))       # Local_Initial_Solution
+        ts = np.unique(np.concatenate([[t_start], ts[ts > t_start]]))
+        y = self.Gf.solve(current(src, idx, n, t_start))  # Local_Initial_Solution
         self.stats.solve_pairs_G += 1
         out = np.zeros((len(probe), t_out.size))
-        k_out = 0
-        while k_out < t_out.size and t_out[k_out] <= 0:
+        k_out = int(np.searchsorted(t_out, t_start, side="left"))
+        while k_out < t_out.size and t_out[k_out] <= t_start:
             out[:, k_out] = y[probe]
             k_out += 1
-        t_a = 0
+        t_a = t_start
         while t_a < t_end:
             t_b = int(ts[np.searchsorted(ts, t_a, side="right")])
             i_a = current(src, idx, n, t_a)
@@ -225,7 +230,7 @@ class RMatex:
             v = y - y0 + z2                                # x(t) + F(t, h)
             snaps = t_out[(t_out > t_a) & (t_out <= t_b)]
             offs = np.unique(np.concatenate([snaps, [t_b]]) - t_a)
-            k, cnt = pick_shift(self.gammas, offs)
+            k, cnt = pick_shift(self.gammas, offs, shift_ratio)
             while True:
                 if cnt < offs.size:                        # ladder cut
                     t_b = int(t_a + offs[cnt - 1])
@@ -269,7 +274,8 @@ class RMatex:
         return out, y
 
     def transient(self, prob, tol: float, m_max: int | None = None,
-                  decompose: bool = True, safety: float = 1.0, h_min: int = 1):
+                  decompose: bool = True, safety: float = 1.0, h_min: int = 1,
+                  shift_ratio: float = LADDER_LO, t_start: int = 0):
         """Full run with superposition over subtasks (Sec. 3.1-3.2). Returns
         (x at probes x t_out, y(t_end) summed)."""
         m_max = m_max or prob.m_max
@@ -279,7 +285,7 @@ class RMatex:
         y_end = np.zeros(self.n)
         for idx in groups:
             o, ye = self.subtask(src, idx, prob.t_end, prob.t_out, prob.probe, tol,
-                                 m_max, safety, h_min)
+                                 m_max, safety, h_min, shift_ratio, t_start)
             y_out += o
             y_end += ye
         return self.nl.vdd - y_out, y_end

@@ -19,6 +19,7 @@
 #include <cstring>
 #include <functional>
 #include <numeric>
+#include <stdexcept>
 #include <thread>
 
 namespace matex {
@@ -229,16 +230,42 @@ Symbolic analyse(const Csr& g, const int32_t* coord, int32_t leaf_max)
     s.n_w = w;
     s.n_upd = u;
     s.nnz_l = nnz;
-    // per-row lists of update slots (for the forward gather)
-    s.upd_ptr.assign(n + 1, 0);
-    for (auto& q : s.sn)
-        for (int32_t t = 0; t < q.nr - q.nc; ++t) s.upd_ptr[s.rows[q.roff + t] + 1]++;
-    for (int64_t i = 0; i < n; ++i) s.upd_ptr[i + 1] += s.upd_ptr[i];
-    s.upd_idx.assign(s.upd_ptr[n], 0);
-    std::vector<int64_t> fill(s.upd_ptr.begin(), s.upd_ptr.end() - 1);
-    for (auto& q : s.sn)
-        for (int32_t t = 0; t < q.nr - q.nc; ++t)
-            s.upd_idx[fill[s.rows[q.roff + t]]++] = q.u + t;
+    // children lists and each off-diagonal row's place among the parent's rows
+    s.child_ptr.assign(nsn + 1, 0);
+    for (int32_t k = 0; k < nsn; ++k)
+        if (s.sn[k].parent >= 0) s.child_ptr[s.sn[k].parent + 1]++;
+    for (int32_t k = 0; k < nsn; ++k) s.child_ptr[k + 1] += s.child_ptr[k];
+    s.child_idx.assign(s.child_ptr[nsn], 0);
+    {
+        std::vector<int32_t> fill(s.child_ptr.begin(), s.child_ptr.end() - 1);
+        for (int32_t k = 0; k < nsn; ++k)
+            if (s.sn[k].parent >= 0) s.child_idx[fill[s.sn[k].parent]++] = k;
+    }
+    s.relidx.assign(s.n_upd, 0);
+    for (int32_t k = 0; k < nsn; ++k) {
+        const Supernode& q = s.sn[k];
+        const int32_t no = q.nr - q.nc;
+        if (q.parent < 0) {
+            if (no != 0) throw std::logic_error("a root supernode has off-diagonal rows");
+            continue;
+        }
+        const Supernode& pq = s.sn[q.parent];
+        const int32_t* prow = s.rows.data() + pq.roff;
+        const int32_t pno = pq.nr - pq.nc;
+        for (int32_t t = 0; t < no; ++t) {
+            const int32_t r = s.rows[q.roff + t];
+            int32_t pos;
+            if (r >= pq.c0 && r < pq.c0 + pq.nc) {
+                pos = r - pq.c0;
+            } else {
+                const int32_t* it = std::lower_bound(prow, prow + pno, r);
+                if (it == prow + pno || *it != r)
+                    throw std::logic_error("off-diagonal row missing from the parent's rows");
+                pos = pq.nc + int32_t(it - prow);
+            }
+            s.relidx[q.u + t] = pos;
+        }
+    }
     return s;
 }
 

@@ -41,8 +41,12 @@ struct Symbolic {
     std::vector<int32_t> iperm;   // old -> new
     std::vector<Supernode> sn;    // postorder
     std::vector<int32_t> rows;    // concatenated off-diagonal rows (new ordering)
-    std::vector<int64_t> upd_ptr; // n+1: per row (new ordering) its update slots
-    std::vector<int64_t> upd_idx; // slot ids, into a buffer of n_upd doubles
+    // Forward-sweep assembly: supernode s owns update slots [u, u + nr - nc)
+    // holding its subtree's accumulated contribution to its off-diagonal
+    // rows. relidx[u + q] is the position of off-diagonal row q of s among
+    // the panel rows of its parent ([parent columns ; parent off rows]).
+    std::vector<int32_t> relidx;  // n_upd
+    std::vector<int32_t> child_ptr, child_idx;   // children of each supernode
     int64_t n_upd = 0;            // sum of off-diagonal row counts
     int64_t n_w = 0;              // total panel entries (sum nr*nc)
     int64_t nnz_l = 0;            // entries of L in the stored panels (lower part)

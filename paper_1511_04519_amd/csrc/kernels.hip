@@ -46,43 +46,52 @@ __global__ __launch_bounds__(256) void k_forward(DevSym s, const int32_t* __rest
 {
     if (done && *done) return;
     extern __shared__ double lds[];
-    double* bt = lds;
-    double* part = lds + lds_nc;
+    double* bt = lds;                       // btilde over the supernode's columns
+    double* acc_off = lds + lds_nc;         // children's updates on this task's off rows
+    double* part = acc_off + FWD_ROWS;      // k-slice partial sums
     const int sn = tsn[blockIdx.x];
     const int r0 = tfirst[blockIdx.x];
     const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
     for (int k = threadIdx.x; k < nc; k += 256) {
-        const int r = c0 + k;
-        double v = b[r];
-        if (scale) v *= scale[r];
-        const int64_t p1 = s.upd_ptr[r + 1];
-        for (int64_t p = s.upd_ptr[r]; p < p1; ++p) v -= upd[s.upd_idx[p]];
-        bt[k] = v;
+        const double v = b[c0 + k];
+        bt[k] = scale ? v * scale[c0 + k] : v;
     }
+    if (threadIdx.x < FWD_ROWS) acc_off[threadIdx.x] = 0.0;
     __syncthreads();
-    const int lane = threadIdx.x & 63, ks = threadIdx.x >> 6;
+    // assemble the children's subtree updates (one child at a time: two
+    // children may touch the same row, one child never touches a row twice)
+    const int cp1 = s.child_ptr[sn + 1];
+    for (int cp = s.child_ptr[sn]; cp < cp1; ++cp) {
+        const int c = s.child_idx[cp];
+        const int64_t uc = s.u[c];
+        const int noc = s.nr[c] - s.nc[c];
+        for (int q = threadIdx.x; q < noc; q += 256) {
+            const int pos = s.relidx[uc + q];
+            const double val = upd[uc + q];
+            if (pos < nc) bt[pos] -= val;
+            else if (pos >= r0 && pos < r0 + FWD_ROWS) acc_off[pos - r0] += val;
+        }
+        __syncthreads();
+    }
+    const int lane = threadIdx.x & (FWD_ROWS - 1), ks = threadIdx.x / FWD_ROWS;
     const int row = r0 + lane;
     double acc = 0.0;
     if (row < nr) {
         const int kmax = row < nc ? row + 1 : nc;
         const double* wr = W + s.w[sn] + row;
         int k = ks;
-        for (; k + 3 * FWD_KSPLIT < kmax; k += 4 * FWD_KSPLIT) {
-            const double a0 = wr[int64_t(k) * nr];
-            const double a1 = wr[int64_t(k + FWD_KSPLIT) * nr];
-            const double a2 = wr[int64_t(k + 2 * FWD_KSPLIT) * nr];
-            const double a3 = wr[int64_t(k + 3 * FWD_KSPLIT) * nr];
-            acc += a0 * bt[k] + a1 * bt[k + FWD_KSPLIT] + a2 * bt[k + 2 * FWD_KSPLIT]
-                 + a3 * bt[k + 3 * FWD_KSPLIT];
-        }
-        for (; k < kmax; k += FWD_KSPLIT) acc += wr[int64_t(k) * nr] * bt[k];
+        for (; k + FWD_KSPLIT < kmax; k += 2 * FWD_KSPLIT)
+            acc += wr[int64_t(k) * nr] * bt[k] + wr[int64_t(k + FWD_KSPLIT) * nr] * bt[k + FWD_KSPLIT];
+        if (k < kmax) acc += wr[int64_t(k) * nr] * bt[k];
     }
     part[threadIdx.x] = acc;
     __syncthreads();
-    if (ks == 0 && row < nr) {
-        const double v = (part[lane] + part[64 + lane]) + (part[128 + lane] + part[192 + lane]);
+    if (threadIdx.x < FWD_ROWS && row < nr) {
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < FWD_KSPLIT; ++q) v += part[q * FWD_ROWS + lane];
         if (row < nc) y[c0 + row] = v;
-        else upd[s.u[sn] + row - nc] = v;
+        else upd[s.u[sn] + row - nc] = acc_off[lane] + v;
     }
 }
 
@@ -152,6 +161,28 @@ constexpr int NVMAX = MAXM + 1;
 // KState scratch for the reductions lives after the struct in one buffer:
 // partials of the current pass, [RED_BLOCKS][NVMAX + 1].
 
+// Sums acc[0..cnt) over the block with one barrier: wavefront shuffles, then
+// the four wavefront partials of value i are added by thread i. Result in
+// out[i] (LDS) for i < cnt. red: LDS scratch of 4 * (NVMAX + 1) doubles.
+template <int N>
+__device__ inline void block_sums(const double (&acc)[N], int cnt, double* red, double* out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (i < cnt) {
+            const double t = wave_sum(acc[i]);
+            if (lane == 0) red[wv * (NVMAX + 1) + i] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+        const int i = threadIdx.x;
+        out[i] = (red[i] + red[(NVMAX + 1) + i]) + (red[2 * (NVMAX + 1) + i] + red[3 * (NVMAX + 1) + i]);
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void k_gs_dots(int64_t n, const double* __restrict__ V,
                                                  int64_t ldv, int nv,
                                                  const double* __restrict__ w,
@@ -159,8 +190,8 @@ __global__ __launch_bounds__(256) void k_gs_dots(int64_t n, const double* __rest
                                                  const int32_t* done)
 {
     if (done && *done) return;
-    __shared__ double red[4];
-    __shared__ double vals[NVMAX];
+    __shared__ double red[4 * (NVMAX + 1)];
+    __shared__ double vals[NVMAX + 1];
     double acc[NVMAX];
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
@@ -170,14 +201,7 @@ __global__ __launch_bounds__(256) void k_gs_dots(int64_t n, const double* __rest
         for (int i = 0; i < NVMAX; ++i)
             if (i < nv) acc[i] += wr * V[r + i * ldv];
     }
-#pragma unroll
-    for (int i = 0; i < NVMAX; ++i) {
-        if (i < nv) {
-            const double t = block_sum(acc[i], red);
-            if (threadIdx.x == 0) vals[i] = t;
-        }
-    }
-    __syncthreads();
+    block_sums(acc, nv, red, vals);
     if (threadIdx.x < nv) partial[int64_t(blockIdx.x) * NVMAX + threadIdx.x] = vals[threadIdx.x];
     if (last_block(&ks->counter)) {
         if (threadIdx.x < nv) {
@@ -188,6 +212,7 @@ __global__ __launch_bounds__(256) void k_gs_dots(int64_t n, const double* __rest
     }
 }
 
+// w' = w - V h1 in place; partial dots V^T w' and ||w'||^2 (entry nv).
 __global__ __launch_bounds__(256) void k_gs_update(int64_t n, const double* __restrict__ V,
                                                    int64_t ldv, int nv, double* w,
                                                    double* partial, KState* ks,
@@ -195,33 +220,27 @@ __global__ __launch_bounds__(256) void k_gs_update(int64_t n, const double* __re
 {
     if (done && *done) return;
     __shared__ double h[NVMAX];
-    __shared__ double red[4];
+    __shared__ double red[4 * (NVMAX + 1)];
     __shared__ double vals[NVMAX + 1];
     if (threadIdx.x < nv) h[threadIdx.x] = ks->h1[threadIdx.x];
     __syncthreads();
-    double acc[NVMAX + 1];
+    // nv <= MAXM, so the dots (slots 0..nv-1) and ||w'||^2 (slot nv) fit NVMAX
+    double acc[NVMAX];
 #pragma unroll
-    for (int i = 0; i <= NVMAX; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
     for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256) {
-        double vr[NVMAX];
         double wr = w[r];
 #pragma unroll
         for (int i = 0; i < NVMAX; ++i)
-            if (i < nv) { vr[i] = V[r + i * ldv]; wr -= h[i] * vr[i]; }
+            if (i < nv) wr -= h[i] * V[r + i * ldv];
         w[r] = wr;
 #pragma unroll
-        for (int i = 0; i < NVMAX; ++i)
-            if (i < nv) acc[i] += wr * vr[i];
-        acc[NVMAX] += wr * wr;
-    }
-#pragma unroll
-    for (int i = 0; i <= NVMAX; ++i) {
-        if (i < nv || i == NVMAX) {
-            const double t = block_sum(acc[i], red);
-            if (threadIdx.x == 0) vals[i == NVMAX ? nv : i] = t;
+        for (int i = 0; i < NVMAX; ++i) {
+            if (i < nv) acc[i] += wr * V[r + i * ldv];
+            else if (i == nv) acc[i] += wr * wr;
         }
     }
-    __syncthreads();
+    block_sums(acc, nv + 1, red, vals);
     if (threadIdx.x <= nv) partial[int64_t(blockIdx.x) * (NVMAX + 1) + threadIdx.x] = vals[threadIdx.x];
     if (last_block(&ks->counter)) {
         if (threadIdx.x <= nv) {
@@ -628,7 +647,7 @@ void launch_forward(const DevSym& s, const LevelTasks& lv, const double* W, cons
                     const double* scale, double* y, double* upd, const int32_t* done,
                     hipStream_t st)
 {
-    const size_t lds = sizeof(double) * (size_t(lv.lds_doubles) + 256);
+    const size_t lds = sizeof(double) * (size_t(lv.lds_doubles) + FWD_ROWS + 256);
     k_forward<<<lv.count, 256, lds, st>>>(s, lv.sn, lv.first, lv.lds_doubles, W, b, scale, y, upd,
                                           done);
 }

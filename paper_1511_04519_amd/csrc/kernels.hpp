@@ -8,8 +8,8 @@
 namespace matex {
 
 constexpr int MAXM = 32;          // largest Krylov dimension supported
-constexpr int FWD_ROWS = 64;      // rows of a forward task (one per lane)
-constexpr int FWD_KSPLIT = 4;     // k-slices of a forward task (one per wavefront)
+constexpr int FWD_ROWS = 16;      // panel rows of a forward task
+constexpr int FWD_KSPLIT = 16;    // column slices of a forward task (16 x 16 = 256 threads)
 constexpr int BWD_COLS = 4;       // columns of a backward task (one per wavefront)
 constexpr int RED_BLOCKS = 256;   // blocks of the vector reductions
 
@@ -23,8 +23,9 @@ struct DevSym {
     const int64_t* w;
     const int64_t* u;
     const int32_t* rows;
-    const int64_t* upd_ptr;
-    const int64_t* upd_idx;
+    const int32_t* child_ptr;
+    const int32_t* child_idx;
+    const int32_t* relidx;
 };
 
 // One level's task list: task t covers supernode sn[t] starting at first[t]

@@ -99,7 +99,7 @@ struct matex_factor_s {
     double vdd = 1.0;
     int device = 0;
     // device structure
-    DevMem d_c0, d_nc, d_nr, d_roff, d_w, d_u, d_rows, d_upd_ptr, d_upd_idx;
+    DevMem d_c0, d_nc, d_nr, d_roff, d_w, d_u, d_rows, d_child_ptr, d_child_idx, d_relidx;
     DevMem d_perm, d_iperm, d_cperm;
     std::vector<DevMem> d_W;          // [n_shifts] M factors, then G
     DevMem d_fwd_sn, d_fwd_first, d_bwd_sn, d_bwd_first;
@@ -225,7 +225,19 @@ KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, doub
     return h;
 }
 
-int64_t checked_size(int64_t a) { return a < 0 ? 0 : a; }
+// Algorithmic bytes of one substitution pair on the stored structure: every
+// panel entry of the lower triangle is read once per sweep (8 B value; the
+// panel layout needs no per-entry index), each sweep reads its right-hand
+// side and writes its result once (8 B per row), the forward sweep also
+// reads the diagonal scale when there is one, each update slot is written
+// once and read once by the parent with its 4 B relative index, and the
+// backward sweep reads the 4 B off-diagonal row list once.
+int64_t solve_pair_bytes(const Symbolic& s, bool scaled)
+{
+    const int64_t vec = 8 * s.n;
+    return 2 * 8 * s.nnz_l + 4 * vec + (scaled ? vec : 0) + s.n_upd * (8 + 8 + 4) +
+           int64_t(s.rows.size()) * 4;
+}
 
 }  // namespace
 
@@ -314,8 +326,9 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         F->d_c0 = upload(c0); F->d_nc = upload(nc); F->d_nr = upload(nr);
         F->d_roff = upload(roff); F->d_w = upload(w); F->d_u = upload(u);
         F->d_rows = upload(s.rows.empty() ? std::vector<int32_t>{0} : s.rows);
-        F->d_upd_ptr = upload(s.upd_ptr);
-        F->d_upd_idx = upload(s.upd_idx.empty() ? std::vector<int64_t>{0} : s.upd_idx);
+        F->d_child_ptr = upload(s.child_ptr);
+        F->d_child_idx = upload(s.child_idx.empty() ? std::vector<int32_t>{0} : s.child_idx);
+        F->d_relidx = upload(s.relidx.empty() ? std::vector<int32_t>{0} : s.relidx);
         F->d_perm = upload(s.perm);
         F->d_iperm = upload(s.iperm);
         std::vector<double> cperm(n);
@@ -327,8 +340,8 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         }
         F->dsym = DevSym{n, F->d_c0.as<int32_t>(), F->d_nc.as<int32_t>(), F->d_nr.as<int32_t>(),
                          F->d_roff.as<int64_t>(), F->d_w.as<int64_t>(), F->d_u.as<int64_t>(),
-                         F->d_rows.as<int32_t>(), F->d_upd_ptr.as<int64_t>(),
-                         F->d_upd_idx.as<int64_t>()};
+                         F->d_rows.as<int32_t>(), F->d_child_ptr.as<int32_t>(),
+                         F->d_child_idx.as<int32_t>(), F->d_relidx.as<int32_t>()};
         build_tasks(*F);
         matex_factor_info& I = F->info;
         I.n = n;
@@ -342,8 +355,8 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         I.seconds_analyse = t1 - t0;
         I.seconds_numeric = t2 - t1;
         I.device_bytes = int64_t(sizeof(double)) * s.n_w * (n_shifts + 1) +
-                         int64_t(sizeof(int64_t)) * (s.upd_idx.size() + s.upd_ptr.size()) +
-                         int64_t(sizeof(int32_t)) * (s.rows.size() + 3 * n);
+                         int64_t(sizeof(int32_t)) * (s.relidx.size() + s.child_idx.size() +
+                                                     s.rows.size() + 3 * n);
         *out = F.release();
         return MATEX_OK;
     } catch (const HipError& e) {
@@ -395,6 +408,43 @@ matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const do
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
+        return MATEX_OK;
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+}
+
+matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t reps, double* seconds,
+                               double* bytes, void* stream)
+{
+    if (!f || !seconds || !bytes || reps <= 0) return fail(MATEX_E_INVALID, "bad argument");
+    const int n_shifts = int(f->gammas.size());
+    if (which < -1 || which >= n_shifts) return fail(MATEX_E_INVALID, "factor index out of range");
+    const int idx = which < 0 ? n_shifts : which;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = f->sym.n;
+    try {
+        DevMem b(sizeof(double) * n), x(sizeof(double) * n), tmp(sizeof(double) * n),
+            upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd));
+        HIPCHK(hipMemsetAsync(b.p, 0, b.bytes, st));
+        const double* sc = idx < n_shifts ? f->d_cperm.as<double>() : nullptr;
+        dev_solve(*f, idx, b.as<double>(), sc, x.as<double>(), tmp.as<double>(), upd.as<double>(),
+                  nullptr, st);   // warm
+        hipEvent_t e0, e1;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        HIPCHK(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r)
+            dev_solve(*f, idx, b.as<double>(), sc, x.as<double>(), tmp.as<double>(), upd.as<double>(),
+                      nullptr, st);
+        HIPCHK(hipEventRecord(e1, st));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        *seconds = 1e-3 * double(ms) / reps;
+        *bytes = double(solve_pair_bytes(f->sym, idx < n_shifts));
         return MATEX_OK;
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -515,6 +565,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     if (o->m_max < 1 || o->m_max > MAXM) return fail(MATEX_E_INVALID, "m_max must be in 1..32");
     if (!(o->tol > 0.0)) return fail(MATEX_E_INVALID, "tol must be > 0");
     const int64_t h_min = std::max<int64_t>(1, o->h_min);
+    const double shift_ratio = o->shift_ratio > 0.0 ? o->shift_ratio : 1.0;
     for (int32_t k = 0; k < p->n_src; ++k) {
         if (p->node[k] < 0 || p->node[k] >= n) return fail(MATEX_E_INVALID, "source node out of range");
         if (p->delay[k] < 0 || p->rise[k] <= 0 || p->fall[k] <= 0 || p->width[k] < 0)
@@ -610,7 +661,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                 // shift ladder
                 int ksh = n_shifts - 1;
                 for (int k = 0; k < n_shifts; ++k)
-                    if (double(offs[0]) * FS >= 0.1 * f->gammas[k]) { ksh = k; break; }
+                    if (double(offs[0]) * FS >= shift_ratio * f->gammas[k]) { ksh = k; break; }
                 auto cut = [&](int k) {
                     if (k == 0) return;
                     const double lim = 10.0 * f->gammas[k];

@@ -54,7 +54,8 @@ class Problem(ctypes.Structure):
 
 
 class RunOpts(ctypes.Structure):
-    _fields_ = [("tol", _f64), ("m_max", _i32), ("mode", _i32), ("h_min", _i64)]
+    _fields_ = [("tol", _f64), ("m_max", _i32), ("mode", _i32), ("h_min", _i64),
+                ("shift_ratio", _f64)]
 
 
 class Stats(ctypes.Structure):
@@ -68,8 +69,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
-           "matex_krylov_step", "matex_transient", "matex_adjoint", "matex_last_error",
-           "matex_version"]
+           "matex_krylov_step", "matex_transient", "matex_adjoint", "matex_time_solves",
+           "matex_last_error", "matex_version"]
 
 _lib = None
 
@@ -92,11 +93,13 @@ def lib():
                                       _vp, ctypes.POINTER(Stats), _vp]
         L.matex_adjoint.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(RunOpts), _vp,
                                     _vp, _vp, _vp]
+        L.matex_time_solves.argtypes = [_vp, _i32, _i32, _pf64, _pf64, _vp]
         L.matex_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.matex_last_error.restype = ctypes.c_size_t
         L.matex_version.restype = ctypes.c_char_p
         for name in ("matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
-                     "matex_krylov_step", "matex_transient", "matex_adjoint"):
+                     "matex_krylov_step", "matex_transient", "matex_adjoint",
+                     "matex_time_solves"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -220,7 +223,8 @@ def _problem_struct(prob, keep):
 
 
 def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
-                    mode: int = MATEX_PLAIN, h_min: int = 1, device="cuda", final: bool = True):
+                    mode: int = MATEX_PLAIN, h_min: int = 1, device="cuda", final: bool = True,
+                    shift_ratio: float = 1.0):
     """Alg. 2 over every subtask, summed. Returns (x at probes (n_probe, n_out),
     x(t_end) (n,) or None, stats dict)."""
     import torch
@@ -229,10 +233,20 @@ def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
     out = torch.empty((prob.probe.size, prob.t_out.size), dtype=torch.float64, device=device)
     fin = torch.empty(f.info["n"], dtype=torch.float64, device=device) if final else None
     st = Stats()
-    opts = RunOpts(float(tol), int(m_max), int(mode), int(h_min))
+    opts = RunOpts(float(tol), int(m_max), int(mode), int(h_min), float(shift_ratio))
     _check(lib().matex_transient(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(out), _ptr(fin),
                                  ctypes.byref(st), _stream()))
     return out, fin, st.as_dict()
+
+
+def matex_time_solves(f: FactorHandle, which: int = 0, reps: int = 50):
+    """Mean seconds of one substitution pair (event-timed on the current
+    stream) and its algorithmic bytes."""
+    sec = ctypes.c_double()
+    byt = ctypes.c_double()
+    _check(lib().matex_time_solves(f.handle, which, reps, ctypes.byref(sec), ctypes.byref(byt),
+                                   _stream()))
+    return sec.value, byt.value
 
 
 def matex_adjoint(f: FactorHandle, prob, dJdx, tol: float = 1e-11, m_max: int = 20):
@@ -242,7 +256,7 @@ def matex_adjoint(f: FactorHandle, prob, dJdx, tol: float = 1e-11, m_max: int = 
     pr = _problem_struct(prob, keep)
     ga = torch.empty(prob.sources.n_src, dtype=torch.float64, device=dJdx.device)
     gc = torch.empty(f.info["n"], dtype=torch.float64, device=dJdx.device)
-    opts = RunOpts(float(tol), int(m_max), MATEX_PLAIN, 1)
+    opts = RunOpts(float(tol), int(m_max), MATEX_PLAIN, 1, 1.0)
     _check(lib().matex_adjoint(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(dJdx), _ptr(ga),
                                _ptr(gc), _stream()))
     return ga, gc

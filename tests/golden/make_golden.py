@@ -8,7 +8,13 @@ stored so a test can tell that it rebuilt the same instance.
                     its first 500 ps: x at the 512 probe rows for t = 0..500 ps
                     every 10 ps, and x(500 ps) at every node. Oracle R-MATEX,
                     tol 1e-13 (every basis) with the 4-shift ladder.
-Run:  python tests/golden/make_golden.py
+  config1_mid.npz   the same workload around 3 ns, where transition spots are
+                    densest: x at the probes for t in [2.9, 3.0] ns. The oracle
+                    starts at 2.6 ns from the quasi-static state G^-1 i(2.6 ns);
+                    the grid forgets that start within tens of ps (its slowest
+                    time constant is a few ps), which check_warm_start()
+                    confirms on the head window against the run from 0.
+Run:  OPENBLAS_NUM_THREADS=1 python tests/golden/make_golden.py [head|mid|check]
 """
 import os
 import sys
@@ -38,5 +44,39 @@ def config1_head(t_end=500 * I.PS):
                         tol=1e-13)
 
 
+def windowed(t0, t1, t2, tol=1e-12):
+    """Oracle x at the probes for t_out in [t1, t2], started at t0."""
+    p = I.config1()
+    sel = (p.t_out >= t1) & (p.t_out <= t2)
+    q = I.Problem(p.name + " (window)", p.netlist, p.sources, t2, p.t_out[p.t_out <= t2], p.probe)
+    s = RM.RMatex(p.netlist, p.gamma)
+    t = time.time()
+    x, _ = s.transient(q, tol=tol, m_max=p.m_max, t_start=t0)
+    print(f"window [{t0}, {t2}] fs: {time.time() - t:.1f} s, bases {s.stats.bases}", flush=True)
+    return p, x[:, sel[p.t_out <= t2]], p.t_out[sel]
+
+
+def check_warm_start():
+    """The windowed start reproduces the run from 0 on the head window."""
+    g = np.load(os.path.join(HERE, "config1_head.npz"))
+    p, xw, tw = windowed(100 * I.PS, 400 * I.PS, 500 * I.PS, tol=1e-13)
+    k = (I.config1().t_out >= 400 * I.PS) & (I.config1().t_out <= 500 * I.PS)
+    err = np.abs(xw - g["x"][:, k[: g["x"].shape[1]]]).max()
+    print(f"warm start vs run from 0: max |dx| = {err:.3e} V", flush=True)
+    assert err < 1e-12
+
+
+def config1_mid():
+    p, x, t = windowed(2600 * I.PS, 2900 * I.PS, 3000 * I.PS)
+    np.savez_compressed(os.path.join(HERE, "config1_mid.npz"), x=x, t_out=t, digest=p.digest(),
+                        t_start=2600 * I.PS, tol=1e-12)
+
+
 if __name__ == "__main__":
-    config1_head()
+    what = sys.argv[1] if len(sys.argv) > 1 else "all"
+    if what in ("head", "all"):
+        config1_head()
+    if what in ("check", "all"):
+        check_warm_start()
+    if what in ("mid", "all"):
+        config1_mid()

@@ -72,20 +72,26 @@ int main(int argc, char** argv)
     // emulated sweeps in the new ordering
     std::vector<double> bb(n), y(n), x(n), upd(s.n_upd, 0.0);
     for (int64_t k = 0; k < n; ++k) bb[k] = rhs[s.perm[k]];
+    // forward: btilde = b_s - (children's updates mapped into s's columns);
+    // [y_s ; w] = W_s btilde; s's update = (children's updates mapped into s's
+    // off rows) + w
     for (int lv = 0; lv < s.n_levels; ++lv)
         for (int32_t k : s.level_sn[lv]) {
             const Supernode& q = s.sn[k];
-            std::vector<double> bt(q.nc);
-            for (int t = 0; t < q.nc; ++t) {
-                int32_t r = q.c0 + t;
-                double v = bb[r];
-                for (int64_t p = s.upd_ptr[r]; p < s.upd_ptr[r + 1]; ++p) v -= upd[s.upd_idx[p]];
-                bt[t] = v;
+            std::vector<double> f(q.nr, 0.0);
+            for (int t = 0; t < q.nc; ++t) f[t] = bb[q.c0 + t];
+            for (int32_t cp = s.child_ptr[k]; cp < s.child_ptr[k + 1]; ++cp) {
+                const Supernode& qc = s.sn[s.child_idx[cp]];
+                for (int t = 0; t < qc.nr - qc.nc; ++t) {
+                    const int32_t pos = s.relidx[qc.u + t];
+                    if (pos < q.nc) f[pos] -= upd[qc.u + t];
+                    else f[pos] += upd[qc.u + t];
+                }
             }
             for (int rr = 0; rr < q.nr; ++rr) {
                 double acc = 0;
-                for (int t = 0; t < q.nc; ++t) acc += W[q.w + rr + int64_t(t) * q.nr] * bt[t];
-                if (rr < q.nc) y[q.c0 + rr] = acc; else upd[q.u + rr - q.nc] = acc;
+                for (int t = 0; t < q.nc; ++t) acc += W[q.w + rr + int64_t(t) * q.nr] * f[t];
+                if (rr < q.nc) y[q.c0 + rr] = acc; else upd[q.u + rr - q.nc] = f[rr] + acc;
             }
         }
     for (int lv = s.n_levels - 1; lv >= 0; --lv)
