@@ -28,6 +28,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_pair_config1.md")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "kernels.hpp", "factor.cpp", "factor.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_1511_04519_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per substitution pair from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources (else None)."""
+    try:
+        txt = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(":", 1) for line in txt.splitlines()
+                  if line.startswith(("kernel-sources:", "traffic-bytes-per-pair:")))
+    if fields.get("kernel-sources", "").strip() != kernel_source_digest():
+        return None
+    return float(fields["traffic-bytes-per-pair"])
 METRIC = "SpTRSV HBM GB/s + transient node·steps/s, batched vs plain, at 1e-9 rel err"
 
 
@@ -107,18 +130,30 @@ def main():
     dt = (time.time() - t0) / args.steps
     value = n * n_out / dt
 
-    # parity spot check against the oracle's stored head of the window
+    # parity spot checks against the oracle's stored windows of this run
+    xs = x.cpu().numpy()
     gold = np.load(os.path.join(ROOT, "tests/golden/config1_head.npz"))
     k_head = int((p.t_out <= int(gold["t_end"])).sum())
-    err_head = float(np.abs(x[:, :k_head].cpu().numpy() - gold["x"][:, :k_head]).max())
+    err_head = float(np.abs(xs[:, :k_head] - gold["x"][:, :k_head]).max())
+    mid = np.load(os.path.join(ROOT, "tests/golden/config1_mid.npz"))
+    sel = np.isin(p.t_out, mid["t_out"])
+    err_mid = float(np.abs(xs[:, sel] - mid["x"][:, : int(sel.sum())]).max()) if sel.any() else None
 
-    # live roofline of the substitution-pair sweeps (event-timed)
+    # live roofline of the substitution-pair sweeps (event-timed on the
+    # library's stream): one pair = the forward and backward level sweeps
     pair_s, pair_b = M.matex_time_solves(F, which=0, reps=50)
     achieved = pair_b / pair_s / 1e9
+    traffic = measured_traffic()
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
-                "kernel": "substitution pair (forward+backward sweeps, C + gamma G)",
-                "pair_us": round(pair_s * 1e6, 2), "pair_bytes": int(pair_b)}
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                "traffic": traffic,
+                "kernel": "substitution pair: k_forward*/k_backward* level sweeps on C + gamma G",
+                "pair_us": round(pair_s * 1e6, 2), "pair_bytes": int(pair_b),
+                "kernel_sources": kernel_source_digest()}
+    # calibration copy for the hardware byte counters (256 MiB read + write)
+    a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    torch.empty_like(a).copy_(a)
+    torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -137,7 +172,8 @@ def main():
                    "mode": "plain", "tol": args.tol, "gamma": p.gamma, "m_max": p.m_max,
                    "factor_s": round(factor_s, 2), "segments": st["segments"],
                    "bases": st["bases"], "solve_pairs": st["solve_pairs_m"] + st["solve_pairs_g"],
-                   "max_abs_err_vs_oracle_head": err_head},
+                   "max_abs_err_vs_oracle_0_500ps": err_head,
+                   "max_abs_err_vs_oracle_2900_3000ps": err_mid},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -221,7 +221,7 @@ Symbolic analyse(const Csr& g, const int32_t* coord, int32_t leaf_max)
         q.w = w;
         q.u = u;
         int64_t off = q.nr - q.nc;
-        w += int64_t(q.nr) * q.nc;
+        w += int64_t(panel_ld(q.nr)) * q.nc;
         u += off;
         nnz += int64_t(q.nc) * (q.nc + 1) / 2 + off * q.nc;
         s.max_nr = std::max(s.max_nr, q.nr);
@@ -388,10 +388,11 @@ int64_t factor_panels(const Symbolic& s, const Csr& g, double alpha, const doubl
                 for (int64_t i = kk + 1; i < nc; ++i) x[i] -= lk[i] * xk;
             }
         }
-        // W = [Linv ; L21 Linv]
+        // W = [Linv ; L21 Linv], columns padded to panel_ld(nr)
         double* Wk = W.data() + q.w;
+        const int64_t ld = panel_ld(q.nr);
         for (int64_t j = 0; j < nc; ++j) {
-            double* wj = Wk + j * nr;
+            double* wj = Wk + j * ld;
             const double* lj = Linv.data() + j * nc;
             for (int64_t i = j; i < nc; ++i) wj[i] = lj[i];
             double* w2 = wj + nc;

@@ -22,6 +22,11 @@ struct Csr {
     std::vector<double> v;
 };
 
+// Panel columns are padded to whole 128-byte lines (16 doubles) so every
+// column starts on a line and a 16-row read touches exactly one line.
+constexpr int32_t PANEL_ALIGN = 16;
+inline int32_t panel_ld(int32_t nr) { return (nr + PANEL_ALIGN - 1) / PANEL_ALIGN * PANEL_ALIGN; }
+
 // One supernode = one node of the nested-dissection tree: a separator or a
 // leaf domain. Its columns are contiguous in the new ordering.
 struct Supernode {
@@ -31,7 +36,7 @@ struct Supernode {
     int32_t parent = -1;  // ND-tree parent (assembly tree)
     int32_t level = 0;    // height above the leaves (0 = leaf)
     int64_t roff = 0;     // offset of the off-diagonal row list in Symbolic::rows
-    int64_t w = 0;        // offset of the nr x nc panel in the value array
+    int64_t w = 0;        // offset of the panel (leading dimension panel_ld(nr)), 128 B aligned
     int64_t u = 0;        // offset of this supernode's forward update slots
 };
 
@@ -48,7 +53,7 @@ struct Symbolic {
     std::vector<int32_t> relidx;  // n_upd
     std::vector<int32_t> child_ptr, child_idx;   // children of each supernode
     int64_t n_upd = 0;            // sum of off-diagonal row counts
-    int64_t n_w = 0;              // total panel entries (sum nr*nc)
+    int64_t n_w = 0;              // total panel storage (sum panel_ld(nr) * nc)
     int64_t nnz_l = 0;            // entries of L in the stored panels (lower part)
     int32_t n_levels = 0;
     std::vector<std::vector<int32_t>> level_sn;   // supernodes per level
@@ -64,7 +69,8 @@ Csr assemble_g(int64_t n, int64_t n_branch, const int32_t* a, const int32_t* b,
 Symbolic analyse(const Csr& g, const int32_t* coord, int32_t leaf_max);
 
 // Numeric factor of (alpha * G + diag(d)) on the symbolic structure. Writes
-// the panels W_s = [L11^-1 ; L21 L11^-1] (column-major nr x nc) into w.
+// the panels W_s = [L11^-1 ; L21 L11^-1] (column-major nr x nc, leading
+// dimension panel_ld(nr), padding rows zero) into w.
 // Returns 0, or 1 + (new-ordering column) of a non-positive pivot.
 int64_t factor_panels(const Symbolic& s, const Csr& g, double alpha, const double* d,
                       std::vector<double>& w, int n_threads);

@@ -23,9 +23,14 @@
 
 #include <cmath>
 
+#include "factor.hpp"
+
 namespace matex {
 
 namespace {
+
+// Leading dimension of a panel with nr rows (device twin of panel_ld).
+__device__ inline int dpanel_ld(int nr) { return (nr + PANEL_ALIGN - 1) / PANEL_ALIGN * PANEL_ALIGN; }
 
 __device__ inline double wave_sum(double v)
 {
@@ -36,21 +41,15 @@ __device__ inline double wave_sum(double v)
 
 // ---------------------------------------------------------------- sweeps
 
-__global__ __launch_bounds__(256) void k_forward(DevSym s, const int32_t* __restrict__ tsn,
-                                                 const int32_t* __restrict__ tfirst,
-                                                 int32_t lds_nc, const double* __restrict__ W,
-                                                 const double* __restrict__ b,
-                                                 const double* __restrict__ scale,
-                                                 double* __restrict__ y, double* upd,
-                                                 const int32_t* done)
+// One forward task: panel rows [r0, r0 + FWD_ROWS) of supernode sn.
+// lds: lds_nc + FWD_ROWS + 256 doubles.
+__device__ inline void fwd_task(const DevSym& s, int sn, int r0, double* lds, int lds_nc,
+                                const double* W, const double* b, const double* scale,
+                                double* y, double* upd)
 {
-    if (done && *done) return;
-    extern __shared__ double lds[];
     double* bt = lds;                       // btilde over the supernode's columns
     double* acc_off = lds + lds_nc;         // children's updates on this task's off rows
     double* part = acc_off + FWD_ROWS;      // k-slice partial sums
-    const int sn = tsn[blockIdx.x];
-    const int r0 = tfirst[blockIdx.x];
     const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
     for (int k = threadIdx.x; k < nc; k += 256) {
         const double v = b[c0 + k];
@@ -78,11 +77,17 @@ __global__ __launch_bounds__(256) void k_forward(DevSym s, const int32_t* __rest
     double acc = 0.0;
     if (row < nr) {
         const int kmax = row < nc ? row + 1 : nc;
+        const int ld = dpanel_ld(nr);
         const double* wr = W + s.w[sn] + row;
         int k = ks;
-        for (; k + FWD_KSPLIT < kmax; k += 2 * FWD_KSPLIT)
-            acc += wr[int64_t(k) * nr] * bt[k] + wr[int64_t(k + FWD_KSPLIT) * nr] * bt[k + FWD_KSPLIT];
-        if (k < kmax) acc += wr[int64_t(k) * nr] * bt[k];
+        for (; k + 3 * FWD_KSPLIT < kmax; k += 4 * FWD_KSPLIT) {
+            const double a0 = wr[int64_t(k) * ld], a1 = wr[int64_t(k + FWD_KSPLIT) * ld];
+            const double a2 = wr[int64_t(k + 2 * FWD_KSPLIT) * ld];
+            const double a3 = wr[int64_t(k + 3 * FWD_KSPLIT) * ld];
+            acc += (a0 * bt[k] + a1 * bt[k + FWD_KSPLIT]) +
+                   (a2 * bt[k + 2 * FWD_KSPLIT] + a3 * bt[k + 3 * FWD_KSPLIT]);
+        }
+        for (; k < kmax; k += FWD_KSPLIT) acc += wr[int64_t(k) * ld] * bt[k];
     }
     part[threadIdx.x] = acc;
     __syncthreads();
@@ -95,6 +100,43 @@ __global__ __launch_bounds__(256) void k_forward(DevSym s, const int32_t* __rest
     }
 }
 
+// One backward task: columns [col0, col0 + BWD_COLS) of supernode sn, one
+// wavefront per column. lds: nr doubles.
+__device__ inline void bwd_task(const DevSym& s, int sn, int col0, double* g, const double* W,
+                                const double* y, double* x)
+{
+    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    const int32_t* roff = s.rows + s.roff[sn];
+    for (int k = threadIdx.x; k < nr; k += 256) g[k] = k < nc ? y[c0 + k] : -x[roff[k - nc]];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = col0 + wv;
+    if (col < nc) {
+        const double* wc = W + s.w[sn] + int64_t(col) * dpanel_ld(nr);
+        double acc = 0.0;
+        int k = col + lane;
+        for (; k + 192 < nr; k += 256)
+            acc += wc[k] * g[k] + wc[k + 64] * g[k + 64] + wc[k + 128] * g[k + 128]
+                 + wc[k + 192] * g[k + 192];
+        for (; k < nr; k += 64) acc += wc[k] * g[k];
+        acc = wave_sum(acc);
+        if (lane == 0) x[c0 + col] = acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_forward(DevSym s, const int32_t* __restrict__ tsn,
+                                                 const int32_t* __restrict__ tfirst,
+                                                 int32_t lds_nc, const double* __restrict__ W,
+                                                 const double* __restrict__ b,
+                                                 const double* __restrict__ scale,
+                                                 double* __restrict__ y, double* upd,
+                                                 const int32_t* done)
+{
+    if (done && *done) return;
+    extern __shared__ double lds[];
+    fwd_task(s, tsn[blockIdx.x], tfirst[blockIdx.x], lds, lds_nc, W, b, scale, y, upd);
+}
+
 __global__ __launch_bounds__(256) void k_backward(DevSym s, const int32_t* __restrict__ tsn,
                                                   const int32_t* __restrict__ tfirst,
                                                   const double* __restrict__ W,
@@ -103,24 +145,158 @@ __global__ __launch_bounds__(256) void k_backward(DevSym s, const int32_t* __res
 {
     if (done && *done) return;
     extern __shared__ double g[];
-    const int sn = tsn[blockIdx.x];
-    const int col0 = tfirst[blockIdx.x];
+    bwd_task(s, tsn[blockIdx.x], tfirst[blockIdx.x], g, W, y, x);
+}
+
+// Levels whose panels have at most 64 rows: one wavefront per supernode, four
+// supernodes per block (tsn lists the level's supernodes; no chunking).
+__global__ __launch_bounds__(256) void k_forward_small(DevSym s, const int32_t* __restrict__ tsn,
+                                                       int32_t count, const double* __restrict__ W,
+                                                       const double* __restrict__ b,
+                                                       const double* __restrict__ scale,
+                                                       double* __restrict__ y, double* upd,
+                                                       const int32_t* done)
+{
+    if (done && *done) return;
+    __shared__ double f_all[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wv;
+    if (idx >= count) return;      // no block barrier below: waves are independent
+    double* f = f_all[wv];
+    const int sn = tsn[idx];
+    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    // f over the panel rows: own columns from b, off rows start at 0
+    if (lane < nr) {
+        double v = 0.0;
+        if (lane < nc) {
+            v = b[c0 + lane];
+            if (scale) v *= scale[c0 + lane];
+        }
+        f[lane] = v;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int cp1 = s.child_ptr[sn + 1];
+    for (int cp = s.child_ptr[sn]; cp < cp1; ++cp) {
+        const int c = s.child_idx[cp];
+        const int64_t uc = s.u[c];
+        const int noc = s.nr[c] - s.nc[c];
+        if (lane < noc) {
+            const int pos = s.relidx[uc + lane];
+            const double val = upd[uc + lane];
+            f[pos] += pos < nc ? -val : val;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane < nr) {
+        const double* wr = W + s.w[sn] + lane;
+        const int kmax = lane < nc ? lane + 1 : nc;
+        const int ld = dpanel_ld(nr);
+        double acc = 0.0;
+        for (int k = 0; k < kmax; ++k) acc += wr[int64_t(k) * ld] * f[k];
+        if (lane < nc) y[c0 + lane] = acc;
+        else upd[s.u[sn] + lane - nc] = f[lane] + acc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_backward_small(DevSym s, const int32_t* __restrict__ tsn,
+                                                        int32_t count, const double* __restrict__ W,
+                                                        const double* __restrict__ y, double* x,
+                                                        const int32_t* done)
+{
+    if (done && *done) return;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wv;
+    if (idx >= count) return;
+    const int sn = tsn[idx];
     const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
     const int32_t* roff = s.rows + s.roff[sn];
-    for (int k = threadIdx.x; k < nr; k += 256) g[k] = k < nc ? y[c0 + k] : -x[roff[k - nc]];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int col = col0 + wv;
-    if (col >= nc) return;
-    const double* wc = W + s.w[sn] + int64_t(col) * nr;
-    double acc = 0.0;
-    int k = col + lane;
-    for (; k + 192 < nr; k += 256)
-        acc += wc[k] * g[k] + wc[k + 64] * g[k + 64] + wc[k + 128] * g[k + 128]
-             + wc[k + 192] * g[k + 192];
-    for (; k < nr; k += 64) acc += wc[k] * g[k];
-    acc = wave_sum(acc);
-    if (lane == 0) x[c0 + col] = acc;
+    // lane k holds g_k = y (own columns) or -x (off rows); column c of the
+    // panel is contiguous, so each column is one coalesced load per lane
+    double gk = 0.0;
+    if (lane < nr) gk = lane < nc ? y[c0 + lane] : -x[roff[lane - nc]];
+    const double* Ws = W + s.w[sn];
+    const int ld = dpanel_ld(nr);
+    int c = 0;
+    for (; c + 3 < nc; c += 4) {      // four columns' loads in flight
+        double v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            v[q] = (lane >= c + q && lane < nr) ? Ws[int64_t(c + q) * ld + lane] * gk : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const double t = wave_sum(v[q]);          // total in lane 0
+            if (lane == 0) x[c0 + c + q] = t;
+        }
+    }
+    for (; c < nc; ++c) {
+        const double v = (lane >= c && lane < nr) ? Ws[int64_t(c) * ld + lane] * gk : 0.0;
+        const double t = wave_sum(v);
+        if (lane == 0) x[c0 + c] = t;
+    }
+}
+
+// Whole substitution pair in one launch. Tasks are listed forward level 0 up
+// to the root, then backward from the root down. Blocks claim tasks in
+// increasing order from an atomic ticket counter. A task first waits until
+// every task it depends on (forward: the children's forward tasks; backward:
+// the parent's backward tasks, or for a root its own forward tasks) has
+// stamped its flag with this launch's epoch, then runs, publishes its results
+// (release fence) and stamps its own flag. Dependencies point only to smaller
+// task indices and a task is only ever claimed by a running block, so the
+// smallest unfinished claimed task can always proceed: no deadlock, and no
+// assumption about how many blocks are resident. The last block to leave
+// resets the two counters for the next launch. A wait longer than
+// `spin_limit` polls sets *err and abandons the launch instead of hanging.
+// ctr[0]: next ticket, ctr[1]: blocks that have left.
+__global__ __launch_bounds__(256) void k_sweep(DevSym s, SweepPlan P, int32_t lds_nc,
+                                               const double* W, const double* b,
+                                               const double* scale, double* y, double* x,
+                                               double* upd, int32_t* flags, int32_t epoch,
+                                               int32_t* err, int32_t spin_limit,
+                                               const int32_t* done, int32_t* ctr)
+{
+    if (done && *done) return;
+    extern __shared__ double lds[];
+    __shared__ int32_t bail, task;
+    if (threadIdx.x == 0) bail = 0;
+    while (true) {
+        if (threadIdx.x == 0)
+            task = __hip_atomic_fetch_add(&ctr[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int t = task;
+        if (t >= P.n_tasks) break;
+        const int d0 = P.dep_ptr[t], d1 = P.dep_ptr[t + 1];
+        for (int d = d0 + threadIdx.x; d < d1; d += 256) {
+            const int dep = P.dep_idx[d];
+            int32_t it = 0;
+            while (__hip_atomic_load(&flags[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+                if (++it > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    bail = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+        __syncthreads();
+        if (bail) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the producers' results
+        const int sn = P.task_sn[t], first = P.task_first[t];
+        if (t < P.n_fwd) fwd_task(s, sn, first, lds, lds_nc, W, b, scale, y, upd);
+        else bwd_task(s, sn, first, lds, W, y, x);
+        __threadfence();                           // publish this task's results
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_store(&flags[t], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x == 0) {
+        const int32_t left = __hip_atomic_fetch_add(&ctr[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (left == int32_t(gridDim.x) - 1) {
+            __hip_atomic_store(&ctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ------------------------------------------------------- reductions helpers
@@ -183,11 +359,24 @@ __device__ inline void block_sums(const double (&acc)[N], int cnt, double* red, 
     __syncthreads();
 }
 
+// In the last block: out[i] = sum_b partial[b * stride + i] for i < cnt,
+// b < nblk (<= 256), with one partial row per thread and one block reduction.
+__device__ inline void reduce_partials(const double* partial, int stride, int nblk, int cnt,
+                                       double* red, double* out)
+{
+    double acc[NVMAX];
+    const int b = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i)
+        acc[i] = (i < cnt && b < nblk) ? partial[int64_t(b) * stride + i] : 0.0;
+    block_sums(acc, cnt, red, out);
+}
+
+// Pass 1: per-block partial dots V_i^T w, i < nv, into partial[block][i].
 __global__ __launch_bounds__(256) void k_gs_dots(int64_t n, const double* __restrict__ V,
                                                  int64_t ldv, int nv,
                                                  const double* __restrict__ w,
-                                                 double* partial, KState* ks,
-                                                 const int32_t* done)
+                                                 double* partial, const int32_t* done)
 {
     if (done && *done) return;
     __shared__ double red[4 * (NVMAX + 1)];
@@ -202,28 +391,24 @@ __global__ __launch_bounds__(256) void k_gs_dots(int64_t n, const double* __rest
             if (i < nv) acc[i] += wr * V[r + i * ldv];
     }
     block_sums(acc, nv, red, vals);
-    if (threadIdx.x < nv) partial[int64_t(blockIdx.x) * NVMAX + threadIdx.x] = vals[threadIdx.x];
-    if (last_block(&ks->counter)) {
-        if (threadIdx.x < nv) {
-            double t = 0.0;
-            for (int b = 0; b < int(gridDim.x); ++b) t += partial[int64_t(b) * NVMAX + threadIdx.x];
-            ks->h1[threadIdx.x] = t;
-        }
-    }
+    if (threadIdx.x < nv) partial[int64_t(blockIdx.x) * (NVMAX + 1) + threadIdx.x] = vals[threadIdx.x];
 }
 
-// w' = w - V h1 in place; partial dots V^T w' and ||w'||^2 (entry nv).
+// Every block sums the previous kernel's partials itself (fixed order), so no
+// cross-block publication is needed inside a kernel. h1 = sum of pass-1
+// partials; w' = w - V h1 in place; pass-2 partials V^T w' and ||w'||^2
+// (slot nv) into partial_out.
 __global__ __launch_bounds__(256) void k_gs_update(int64_t n, const double* __restrict__ V,
                                                    int64_t ldv, int nv, double* w,
-                                                   double* partial, KState* ks,
-                                                   const int32_t* done)
+                                                   const double* partial_in, double* partial_out,
+                                                   KState* ks, const int32_t* done)
 {
     if (done && *done) return;
-    __shared__ double h[NVMAX];
+    __shared__ double h[NVMAX + 1];
     __shared__ double red[4 * (NVMAX + 1)];
     __shared__ double vals[NVMAX + 1];
-    if (threadIdx.x < nv) h[threadIdx.x] = ks->h1[threadIdx.x];
-    __syncthreads();
+    reduce_partials(partial_in, NVMAX + 1, gridDim.x, nv, red, h);
+    if (blockIdx.x == 0 && threadIdx.x < nv) ks->h1[threadIdx.x] = h[threadIdx.x];
     // nv <= MAXM, so the dots (slots 0..nv-1) and ||w'||^2 (slot nv) fit NVMAX
     double acc[NVMAX];
 #pragma unroll
@@ -241,37 +426,30 @@ __global__ __launch_bounds__(256) void k_gs_update(int64_t n, const double* __re
         }
     }
     block_sums(acc, nv + 1, red, vals);
-    if (threadIdx.x <= nv) partial[int64_t(blockIdx.x) * (NVMAX + 1) + threadIdx.x] = vals[threadIdx.x];
-    if (last_block(&ks->counter)) {
-        if (threadIdx.x <= nv) {
-            double t = 0.0;
-            for (int b = 0; b < int(gridDim.x); ++b)
-                t += partial[int64_t(b) * (NVMAX + 1) + threadIdx.x];
-            if (threadIdx.x < nv) ks->h2[threadIdx.x] = t;
-            else ks->nrm2 = t;
-        }
-    }
+    if (threadIdx.x <= nv) partial_out[int64_t(blockIdx.x) * (NVMAX + 1) + threadIdx.x] = vals[threadIdx.x];
 }
 
 // w'' = w' - V h2, ||w''||^2 = ||w'||^2 - ||h2||^2 (w' is already orthogonal
 // to working precision after the first pass, so there is no cancellation);
 // v_{j+1} = w'' / ||w''||, and column j of Ht = h1 + h2 with Ht(j+1,j) = ||w''||.
+// Every block sums the pass-2 partials itself; block 0 records the column.
 __global__ __launch_bounds__(256) void k_gs_finish(int64_t n, double* V, int64_t ldv, int nv,
-                                                   const double* __restrict__ w, KState* ks,
+                                                   const double* __restrict__ w,
+                                                   const double* partial_in, KState* ks,
                                                    const int32_t* done)
 {
     if (done && *done) return;
-    __shared__ double h[NVMAX];
+    __shared__ double h[NVMAX + 1];
+    __shared__ double red[4 * (NVMAX + 1)];
     __shared__ double sc;
-    if (threadIdx.x < nv) h[threadIdx.x] = ks->h2[threadIdx.x];
-    __syncthreads();
+    reduce_partials(partial_in, NVMAX + 1, gridDim.x, nv + 1, red, h);
     if (threadIdx.x == 0) {
         double s2 = 0.0, hmax = 0.0;
         for (int i = 0; i < nv; ++i) {
             s2 += h[i] * h[i];
             hmax = fmax(hmax, fabs(ks->h1[i] + h[i]));
         }
-        const double beta = sqrt(fmax(ks->nrm2 - s2, 0.0));
+        const double beta = sqrt(fmax(h[nv] - s2, 0.0));
         // happy breakdown: the space is invariant, the result is exact
         const bool brk = !(beta > 1e-14 * hmax);
         sc = brk ? 0.0 : 1.0 / beta;
@@ -524,7 +702,7 @@ __global__ __launch_bounds__(256) void k_checks(KState* ks, double gamma,
 __global__ __launch_bounds__(256) void k_setup_v(int64_t n, const double* __restrict__ y,
                                                  const double* __restrict__ y0,
                                                  const double* __restrict__ z2, double* v,
-                                                 double* partial, KState* ks)
+                                                 double* partial)
 {
     __shared__ double red[4];
     double acc = 0.0;
@@ -535,24 +713,30 @@ __global__ __launch_bounds__(256) void k_setup_v(int64_t n, const double* __rest
     }
     const double s = block_sum(acc, red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
-    if (last_block(&ks->counter)) {
-        if (threadIdx.x == 0) {
-            double t = 0.0;
-            for (int b = 0; b < int(gridDim.x); ++b) t += partial[b];
-            const double beta = sqrt(t);
-            ks->beta = beta;
+}
+
+// beta = ||v|| (every block sums the partials), v_1 = v / beta; block 0
+// resets the Krylov state for a new basis.
+__global__ __launch_bounds__(256) void k_normalize_v(int64_t n, double* v, const double* partial,
+                                                     int nblk, KState* ks)
+{
+    __shared__ double red[4];
+    __shared__ double sb;
+    const double mine = int(threadIdx.x) < nblk ? partial[threadIdx.x] : 0.0;
+    const double t = block_sum(mine, red);
+    if (threadIdx.x == 0) {
+        sb = sqrt(t);
+        if (blockIdx.x == 0) {
+            ks->beta = sb;
             ks->m = 0;
             ks->breakdown = 0;
-            ks->converged = beta == 0.0 ? 1 : 0;
-            ks->done = beta == 0.0 ? 1 : 0;
+            ks->converged = sb == 0.0 ? 1 : 0;
+            ks->done = sb == 0.0 ? 1 : 0;
             ks->est = 0.0;
         }
     }
-}
-
-__global__ __launch_bounds__(256) void k_normalize_v(int64_t n, double* v, KState* ks)
-{
-    const double beta = ks->beta;
+    __syncthreads();
+    const double beta = sb;
     if (beta == 0.0) return;
     const double inv = 1.0 / beta;
     for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256)
@@ -647,6 +831,11 @@ void launch_forward(const DevSym& s, const LevelTasks& lv, const double* W, cons
                     const double* scale, double* y, double* upd, const int32_t* done,
                     hipStream_t st)
 {
+    if (lv.small) {
+        k_forward_small<<<(lv.count + 3) / 4, 256, 0, st>>>(s, lv.sn, lv.count, W, b, scale, y, upd,
+                                                            done);
+        return;
+    }
     const size_t lds = sizeof(double) * (size_t(lv.lds_doubles) + FWD_ROWS + 256);
     k_forward<<<lv.count, 256, lds, st>>>(s, lv.sn, lv.first, lv.lds_doubles, W, b, scale, y, upd,
                                           done);
@@ -655,26 +844,54 @@ void launch_forward(const DevSym& s, const LevelTasks& lv, const double* W, cons
 void launch_backward(const DevSym& s, const LevelTasks& lv, const double* W, const double* y,
                      double* x, const int32_t* done, hipStream_t st)
 {
+    if (lv.small) {
+        k_backward_small<<<(lv.count + 3) / 4, 256, 0, st>>>(s, lv.sn, lv.count, W, y, x, done);
+        return;
+    }
     const size_t lds = sizeof(double) * size_t(lv.lds_doubles);
     k_backward<<<lv.count, 256, lds, st>>>(s, lv.sn, lv.first, W, y, x, done);
+}
+
+int sweep_max_blocks(size_t lds_bytes)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep, 256, lds_bytes) != hipSuccess)
+        return 0;
+    return cus * per;
+}
+
+hipError_t launch_sweep(const DevSym& s, const SweepPlan& P, int blocks, const double* W,
+                        const double* b, const double* scale, double* y, double* x, double* upd,
+                        int32_t* flags, int32_t epoch, int32_t* err, int32_t spin_limit,
+                        const int32_t* done, int32_t* ctr, hipStream_t st)
+{
+    const size_t lds = sizeof(double) * size_t(P.lds_doubles);
+    k_sweep<<<blocks, 256, lds, st>>>(s, P, P.lds_nc, W, b, scale, y, x, upd, flags, epoch, err,
+                                      spin_limit, done, ctr);
+    return hipGetLastError();
 }
 
 void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const double* w,
                     double* partial, KState* ks, const int32_t* done, hipStream_t st)
 {
-    k_gs_dots<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial, ks, done);
+    (void)ks;
+    k_gs_dots<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial, done);
 }
 
 void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w,
                       double* partial, KState* ks, const int32_t* done, hipStream_t st)
 {
-    k_gs_update<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial, ks, done);
+    const int64_t half = int64_t(RED_BLOCKS) * (MAXM + 2);
+    k_gs_update<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial, partial + half, ks, done);
 }
 
-void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w, KState* ks,
-                      const int32_t* done, hipStream_t st)
+void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w,
+                      const double* partial, KState* ks, const int32_t* done, hipStream_t st)
 {
-    k_gs_finish<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, ks, done);
+    const int64_t half = int64_t(RED_BLOCKS) * (MAXM + 2);
+    k_gs_finish<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial + half, ks, done);
 }
 
 size_t checks_lds_bytes() { return sizeof(double) * (7 * MAXM * LD + 2 * MAXM); }
@@ -689,12 +906,13 @@ void launch_checks(KState* ks, double gamma, const double* tau, int n_tau, doubl
 void launch_setup_v(int64_t n, const double* y, const double* y0, const double* z2, double* v,
                     double* partial, KState* ks, hipStream_t st)
 {
-    k_setup_v<<<grid_for(n), 256, 0, st>>>(n, y, y0, z2, v, partial, ks);
+    (void)ks;
+    k_setup_v<<<grid_for(n), 256, 0, st>>>(n, y, y0, z2, v, partial);
 }
 
-void launch_normalize_v(int64_t n, double* v, KState* ks, hipStream_t st)
+void launch_normalize_v(int64_t n, double* v, const double* partial, KState* ks, hipStream_t st)
 {
-    k_normalize_v<<<grid_for(n), 256, 0, st>>>(n, v, ks);
+    k_normalize_v<<<grid_for(n), 256, 0, st>>>(n, v, partial, grid_for(n), ks);
 }
 
 void launch_scatter_add(int32_t count, const int32_t* idx, const double* val, double* dst,

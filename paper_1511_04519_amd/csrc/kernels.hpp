@@ -35,6 +35,20 @@ struct LevelTasks {
     const int32_t* first;
     int32_t count;
     int32_t lds_doubles;   // LDS the level needs (max nc fwd / max nr bwd)
+    int32_t small;         // every panel of the level has <= 64 rows: sn lists
+                           // the supernodes, one wavefront each (first unused)
+};
+
+// Task list of the one-launch substitution pair (see k_sweep).
+struct SweepPlan {
+    int32_t n_tasks;       // forward tasks then backward tasks
+    int32_t n_fwd;
+    const int32_t* task_sn;
+    const int32_t* task_first;
+    const int32_t* dep_ptr;  // [n_tasks + 1]
+    const int32_t* dep_idx;  // task ids each task waits for
+    int32_t lds_nc;          // forward staging (max nc)
+    int32_t lds_doubles;     // dynamic LDS of the launch
 };
 
 // Per-Krylov-process device state (one per instance).
@@ -60,14 +74,24 @@ void launch_forward(const DevSym& s, const LevelTasks& lv, const double* W, cons
 void launch_backward(const DevSym& s, const LevelTasks& lv, const double* W, const double* y,
                      double* x, const int32_t* done, hipStream_t st);
 
+// One launch per pair; any grid size works (tasks are claimed dynamically);
+// sweep_max_blocks(lds bytes) is the number that fits the device at once.
+// ctr: two int32 counters, zero before the first launch (each launch leaves
+// them at zero).
+int sweep_max_blocks(size_t lds_bytes);
+hipError_t launch_sweep(const DevSym& s, const SweepPlan& P, int blocks, const double* W,
+                        const double* b, const double* scale, double* y, double* x, double* upd,
+                        int32_t* flags, int32_t epoch, int32_t* err, int32_t spin_limit,
+                        const int32_t* done, int32_t* ctr, hipStream_t st);
+
 // ---- Gram-Schmidt (two classical passes) -----------------------------------
-// partial: RED_BLOCKS x (MAXM + 2) doubles of scratch.
+// partial: 2 * RED_BLOCKS * (MAXM + 2) doubles of scratch (two passes).
 void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const double* w,
                     double* partial, KState* ks, const int32_t* done, hipStream_t st);
 void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w,
                       double* partial, KState* ks, const int32_t* done, hipStream_t st);
-void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w, KState* ks,
-                      const int32_t* done, hipStream_t st);
+void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w,
+                      const double* partial, KState* ks, const int32_t* done, hipStream_t st);
 
 // ---- small dense part: H_m, exp(tau H_m) e1, estimates, decision ----------
 // One workgroup per check offset. u_buf[c*MAXM + i] = (e^{tau_c H_m} e1)_i;
@@ -79,7 +103,7 @@ size_t checks_lds_bytes();
 // ---- segment set-up and reconstruction ------------------------------------
 void launch_setup_v(int64_t n, const double* y, const double* y0, const double* z2, double* v,
                     double* partial, KState* ks, hipStream_t st);
-void launch_normalize_v(int64_t n, double* v, KState* ks, hipStream_t st);
+void launch_normalize_v(int64_t n, double* v, const double* partial, KState* ks, hipStream_t st);
 void launch_scatter_add(int32_t count, const int32_t* idx, const double* val, double* dst,
                         hipStream_t st);
 void launch_recon_probes(int n_probe, const int32_t* probe_perm, int n_snap, int32_t snap0,

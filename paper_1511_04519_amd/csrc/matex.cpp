@@ -104,6 +104,11 @@ struct matex_factor_s {
     std::vector<DevMem> d_W;          // [n_shifts] M factors, then G
     DevMem d_fwd_sn, d_fwd_first, d_bwd_sn, d_bwd_first;
     std::vector<LevelTasks> fwd, bwd;
+    // one-launch sweep
+    DevMem d_task_sn, d_task_first, d_dep_ptr, d_dep_idx;
+    SweepPlan plan{};
+    int sweep_blocks = 0;
+    bool use_levels = false;
     DevSym dsym{};
     matex_factor_info info{};
 };
@@ -116,11 +121,20 @@ void build_tasks(matex_factor_s& F)
     std::vector<int32_t> fsn, ffirst, bsn, bfirst;
     std::vector<int64_t> foff(s.n_levels + 1, 0), boff(s.n_levels + 1, 0);
     std::vector<int32_t> flds(s.n_levels, 1), blds(s.n_levels, 1);
+    std::vector<int32_t> small(s.n_levels, 0);
     for (int lv = 0; lv < s.n_levels; ++lv) {
+        int32_t mx = 0;
+        for (int32_t k : s.level_sn[lv]) mx = std::max(mx, s.sn[k].nr);
+        small[lv] = mx <= 64 ? 1 : 0;
         for (int32_t k : s.level_sn[lv]) {
             const Supernode& q = s.sn[k];
-            for (int32_t r = 0; r < q.nr; r += FWD_ROWS) { fsn.push_back(k); ffirst.push_back(r); }
-            for (int32_t c = 0; c < q.nc; c += BWD_COLS) { bsn.push_back(k); bfirst.push_back(c); }
+            if (small[lv]) {
+                fsn.push_back(k); ffirst.push_back(0);
+                bsn.push_back(k); bfirst.push_back(0);
+            } else {
+                for (int32_t r = 0; r < q.nr; r += FWD_ROWS) { fsn.push_back(k); ffirst.push_back(r); }
+                for (int32_t c = 0; c < q.nc; c += BWD_COLS) { bsn.push_back(k); bfirst.push_back(c); }
+            }
             flds[lv] = std::max(flds[lv], q.nc);
             blds[lv] = std::max(blds[lv], q.nr);
         }
@@ -133,22 +147,108 @@ void build_tasks(matex_factor_s& F)
     F.d_bwd_first = upload(bfirst);
     for (int lv = 0; lv < s.n_levels; ++lv) {
         LevelTasks f{F.d_fwd_sn.as<int32_t>() + foff[lv], F.d_fwd_first.as<int32_t>() + foff[lv],
-                     int32_t(foff[lv + 1] - foff[lv]), flds[lv]};
+                     int32_t(foff[lv + 1] - foff[lv]), flds[lv], small[lv]};
         LevelTasks b{F.d_bwd_sn.as<int32_t>() + boff[lv], F.d_bwd_first.as<int32_t>() + boff[lv],
-                     int32_t(boff[lv + 1] - boff[lv]), blds[lv]};
+                     int32_t(boff[lv + 1] - boff[lv]), blds[lv], small[lv]};
         F.fwd.push_back(f);
         F.bwd.push_back(b);
     }
+    // one-launch plan: forward tasks (levels up), then backward (levels down)
+    const int32_t nsn = int32_t(s.sn.size());
+    std::vector<int32_t> tsn, tfirst, fb(nsn), fe(nsn), bb(nsn), be(nsn);
+    for (int lv = 0; lv < s.n_levels; ++lv)
+        for (int32_t k : s.level_sn[lv]) {
+            fb[k] = int32_t(tsn.size());
+            for (int32_t r = 0; r < s.sn[k].nr; r += FWD_ROWS) { tsn.push_back(k); tfirst.push_back(r); }
+            fe[k] = int32_t(tsn.size());
+        }
+    const int32_t n_fwd = int32_t(tsn.size());
+    for (int lv = s.n_levels - 1; lv >= 0; --lv)
+        for (int32_t k : s.level_sn[lv]) {
+            bb[k] = int32_t(tsn.size());
+            for (int32_t c = 0; c < s.sn[k].nc; c += BWD_COLS) { tsn.push_back(k); tfirst.push_back(c); }
+            be[k] = int32_t(tsn.size());
+        }
+    std::vector<int32_t> dptr(1, 0), didx;
+    for (size_t t = 0; t < tsn.size(); ++t) {
+        const int32_t k = tsn[t];
+        if (int32_t(t) < n_fwd) {
+            for (int32_t cp = s.child_ptr[k]; cp < s.child_ptr[k + 1]; ++cp) {
+                const int32_t c = s.child_idx[cp];
+                for (int32_t d = fb[c]; d < fe[c]; ++d) didx.push_back(d);
+            }
+        } else {
+            const int32_t par = s.sn[k].parent;
+            const int32_t d0 = par >= 0 ? bb[par] : fb[k], d1 = par >= 0 ? be[par] : fe[k];
+            for (int32_t d = d0; d < d1; ++d) didx.push_back(d);
+        }
+        dptr.push_back(int32_t(didx.size()));
+    }
+    F.d_task_sn = upload(tsn);
+    F.d_task_first = upload(tfirst);
+    F.d_dep_ptr = upload(dptr);
+    F.d_dep_idx = upload(didx.empty() ? std::vector<int32_t>{0} : didx);
+    F.plan.n_tasks = int32_t(tsn.size());
+    F.plan.n_fwd = n_fwd;
+    F.plan.task_sn = F.d_task_sn.as<int32_t>();
+    F.plan.task_first = F.d_task_first.as<int32_t>();
+    F.plan.dep_ptr = F.d_dep_ptr.as<int32_t>();
+    F.plan.dep_idx = F.d_dep_idx.as<int32_t>();
+    F.plan.lds_nc = s.max_nc;
+    F.plan.lds_doubles = std::max(s.max_nc + FWD_ROWS + 256, s.max_nr);
+    const int maxb = sweep_max_blocks(sizeof(double) * size_t(F.plan.lds_doubles));
+    F.sweep_blocks = std::min(maxb, F.plan.n_tasks);
+    // The one-launch sweep is exact but its per-task release/acquire fences
+    // (an L2 write-back and invalidate each) cost more than the level
+    // launches they replace on this factor shape; it is used on request only.
+    const char* env = std::getenv("MATEX_SWEEP");
+    F.use_levels = !(env && std::string(env) == "persistent") || F.sweep_blocks <= 0;
 }
+
+// Completion flags, error word and launch epoch of the one-launch sweep,
+// owned by one caller (one stream) at a time.
+struct SweepSync {
+    DevMem flags, err;     // err: [0] error word, [1..2] task and exit counters
+    int32_t epoch = 0;
+    explicit SweepSync(const matex_factor_s& F) {
+        flags = DevMem(sizeof(int32_t) * std::max(1, F.plan.n_tasks));
+        err = DevMem(sizeof(int32_t) * 4);
+        HIPCHK(hipMemset(flags.p, 0, flags.bytes));
+        HIPCHK(hipMemset(err.p, 0, err.bytes));
+    }
+};
+
+constexpr int32_t SPIN_LIMIT = 1 << 22;   // polls before a dependency wait gives up
 
 // x = A_which^-1 (scale .* b), all in the permuted ordering. tmp: [n], upd: [n_upd].
 void dev_solve(const matex_factor_s& F, int which, const double* b, const double* scale,
-               double* x, double* tmp, double* upd, const int32_t* done, hipStream_t st)
+               double* x, double* tmp, double* upd, const int32_t* done, SweepSync& sy,
+               hipStream_t st)
 {
     const double* W = F.d_W[which].as<double>();
+    if (!F.use_levels) {
+        if (sy.epoch >= INT32_MAX - 1) {
+            HIPCHK(hipMemsetAsync(sy.flags.p, 0, sy.flags.bytes, st));
+            sy.epoch = 0;
+        }
+        ++sy.epoch;
+        HIPCHK(launch_sweep(F.dsym, F.plan, F.sweep_blocks, W, b, scale, tmp, x, upd,
+                            sy.flags.as<int32_t>(), sy.epoch, sy.err.as<int32_t>(), SPIN_LIMIT, done,
+                            sy.err.as<int32_t>() + 1, st));
+        return;
+    }
     const int L = F.sym.n_levels;
     for (int lv = 0; lv < L; ++lv) launch_forward(F.dsym, F.fwd[lv], W, b, scale, tmp, upd, done, st);
     for (int lv = L - 1; lv >= 0; --lv) launch_backward(F.dsym, F.bwd[lv], W, tmp, x, done, st);
+}
+
+// Raises if a one-launch sweep gave up waiting (reads the error word).
+void check_sweep(SweepSync& sy, hipStream_t st)
+{
+    int32_t e = 0;
+    HIPCHK(hipMemcpyAsync(&e, sy.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (e) throw HipError{hipErrorLaunchFailure, "substitution sweep: a dependency wait timed out"};
 }
 
 // Scratch of one Krylov process.
@@ -156,13 +256,14 @@ struct Work {
     int64_t n = 0;
     DevMem V, w, tmp, upd, partial, ks, u, est, taus;
     int64_t max_checks = 0;
-    Work(const matex_factor_s& F, int64_t max_chk) {
+    SweepSync sync;
+    Work(const matex_factor_s& F, int64_t max_chk) : sync(F) {
         n = F.sym.n;
         V = DevMem(sizeof(double) * n * (MAXM + 1));
         w = DevMem(sizeof(double) * n);
         tmp = DevMem(sizeof(double) * n);
         upd = DevMem(sizeof(double) * std::max<int64_t>(1, F.sym.n_upd));
-        partial = DevMem(sizeof(double) * RED_BLOCKS * (MAXM + 3));
+        partial = DevMem(sizeof(double) * 2 * RED_BLOCKS * (MAXM + 2));
         ks = DevMem(sizeof(KState));
         HIPCHK(hipMemset(ks.p, 0, sizeof(KState)));
         max_checks = std::max<int64_t>(1, max_chk);
@@ -200,10 +301,10 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, int n
     const int64_t n = wk.n;
     double* V = wk.V.as<double>();
     dev_solve(F, shift, V + int64_t(j) * n, F.d_cperm.as<double>(), wk.w.as<double>(),
-              wk.tmp.as<double>(), wk.upd.as<double>(), wk.done(), st);
+              wk.tmp.as<double>(), wk.upd.as<double>(), wk.done(), wk.sync, st);
     launch_gs_dots(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_update(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
-    launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.kst(), wk.done(), st);
+    launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_checks(wk.kst(), F.gammas[shift], wk.taus.as<double>(), n_tau, tol, wk.u.as<double>(),
                   wk.est.as<double>(), m_max, 1, st);
 }
@@ -392,6 +493,7 @@ matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const do
     try {
         DevMem bp(sizeof(double) * n), xp(sizeof(double) * n), tmp(sizeof(double) * n),
             upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd)), sc;
+        SweepSync sy(*f);
         const double* scale_p = nullptr;
         if (d_scale) {
             sc = DevMem(sizeof(double) * n);
@@ -402,12 +504,12 @@ matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const do
             launch_gather_perm(n, f->d_perm.as<int32_t>(), d_b + int64_t(r) * n, bp.as<double>(), n,
                                n, 1, st);
             dev_solve(*f, idx, bp.as<double>(), scale_p, xp.as<double>(), tmp.as<double>(),
-                      upd.as<double>(), nullptr, st);
+                      upd.as<double>(), nullptr, sy, st);
             launch_scatter_perm(n, f->d_perm.as<int32_t>(), xp.as<double>(), d_x + int64_t(r) * n,
                                 n, n, 1, st);
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(st));
+        check_sweep(sy, st);
         return MATEX_OK;
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -426,19 +528,21 @@ matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t reps, do
     try {
         DevMem b(sizeof(double) * n), x(sizeof(double) * n), tmp(sizeof(double) * n),
             upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd));
+        SweepSync sy(*f);
         HIPCHK(hipMemsetAsync(b.p, 0, b.bytes, st));
         const double* sc = idx < n_shifts ? f->d_cperm.as<double>() : nullptr;
         dev_solve(*f, idx, b.as<double>(), sc, x.as<double>(), tmp.as<double>(), upd.as<double>(),
-                  nullptr, st);   // warm
+                  nullptr, sy, st);   // warm
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, st));
         for (int r = 0; r < reps; ++r)
             dev_solve(*f, idx, b.as<double>(), sc, x.as<double>(), tmp.as<double>(), upd.as<double>(),
-                      nullptr, st);
+                      nullptr, sy, st);
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
+        check_sweep(sy, st);
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
@@ -478,7 +582,7 @@ matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, co
                                n, n, 1, st);
             launch_setup_v(n, acc.as<double>(), zero.as<double>(), zero.as<double>(), V,
                            wk.partial.as<double>(), wk.kst(), st);
-            launch_normalize_v(n, V, wk.kst(), st);
+            launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
             KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, 6, pin.as<KsHost>(), st);
             if (!h.converged) all_conv = false;
             if (m_used) m_used[r] = h.m;
@@ -493,7 +597,7 @@ matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, co
             }
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(st));
+        check_sweep(wk.sync, st);
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
     }
@@ -643,9 +747,9 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                         double* dv = d_ev.as<double>();
                         launch_scatter_add(cnt, reinterpret_cast<int32_t*>(dv + cnt), dv, sl.as<double>(), st);
                         dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
-                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
+                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
                         dev_solve(*f, n_shifts, z1.as<double>(), cperm, z2.as<double>(),
-                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
+                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
                         S.solve_pairs_g += 2;
                     }
                     k_spot++;
@@ -680,7 +784,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                                           hipMemcpyHostToDevice, st));
                     launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
                                    wk.partial.as<double>(), wk.kst(), st);
-                    launch_normalize_v(n, V, wk.kst(), st);
+                    launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
                     h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, m_guess, hks, st);
                     S.bases++;
                     S.solve_pairs_m += h.m;
@@ -742,7 +846,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
             launch_vdd_minus(n, f->vdd, d_final, st);
         }
         HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(st));
+        check_sweep(wk.sync, st);
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
     } catch (const std::bad_alloc&) {

@@ -90,7 +90,7 @@ int main(int argc, char** argv)
             }
             for (int rr = 0; rr < q.nr; ++rr) {
                 double acc = 0;
-                for (int t = 0; t < q.nc; ++t) acc += W[q.w + rr + int64_t(t) * q.nr] * f[t];
+                for (int t = 0; t < q.nc; ++t) acc += W[q.w + rr + int64_t(t) * panel_ld(q.nr)] * f[t];
                 if (rr < q.nc) y[q.c0 + rr] = acc; else upd[q.u + rr - q.nc] = f[rr] + acc;
             }
         }
@@ -101,7 +101,7 @@ int main(int argc, char** argv)
                 double acc = 0;
                 for (int rr = 0; rr < q.nr; ++rr) {
                     double gv = rr < q.nc ? y[q.c0 + rr] : -x[s.rows[q.roff + rr - q.nc]];
-                    acc += W[q.w + rr + int64_t(t) * q.nr] * gv;
+                    acc += W[q.w + rr + int64_t(t) * panel_ld(q.nr)] * gv;
                 }
                 x[q.c0 + t] = acc;
             }

@@ -171,3 +171,41 @@ def test_transient_edge_cases():
     with pytest.raises(M.MatexError) as e:
         M.matex_transient(F, q)
     assert e.value.status == M.MATEX_E_INVALID
+
+
+# ------------------------------------------------- full-size config 1 grid
+
+@pytest.fixture(scope="module")
+def config1_factor():
+    p = I.config1()
+    return p, M.matex_factor(p.netlist, p.gamma)
+
+
+def test_config1_instance_is_the_stored_one(config1_factor):
+    p, _ = config1_factor
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    for name in ("config1_head.npz", "config1_mid.npz"):
+        assert str(np.load(os.path.join(here, name))["digest"]) == p.digest()
+
+
+@pytest.mark.parametrize("which", ["head", "mid"])
+def test_config1_matches_oracle_windows(config1_factor, which):
+    """2 x 300 x 300 grid (180k nodes, 2000 sources), bench tolerance; the
+    oracle's stored windows: [0, 500] ps from t = 0, and [2.9, 3.0] ns (the
+    densest stretch of transition spots) from a start at 2.6 ns."""
+    import os
+    p, F = config1_factor
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", f"config1_{which}.npz"))
+    t_end = int(g["t_end"]) if which == "head" else int(g["t_out"][-1])
+    _note(f"config1 {which} window up to {t_end} fs")
+    q = I.Problem(p.name, p.netlist, p.sources, t_end, p.t_out[p.t_out <= t_end], p.probe)
+    x, xf, st = M.matex_transient(F, q, tol=1e-10, m_max=p.m_max)
+    x = x.cpu().numpy()
+    if which == "head":
+        err = np.abs(x - g["x"]).max()
+    else:
+        sel = np.isin(q.t_out, g["t_out"])
+        err = np.abs(x[:, sel] - g["x"]).max()
+    print(f"config1 {which}: max |x_gpu - x_oracle| = {err:.3e} V, stats {st}", flush=True)
+    assert err <= 1e-9
