@@ -10,7 +10,8 @@ OBJ = os.path.join(HERE, "_build")
 
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-SOURCES = [("kernels.hip", True), ("matex.cpp", True), ("factor.cpp", False)]
+SOURCES = [("kernels.hip", True), ("batched.hip", True), ("matex.cpp", True),
+           ("factor.cpp", False)]
 
 
 def build(verbose: bool = False) -> str:

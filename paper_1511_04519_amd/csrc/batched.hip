@@ -1,0 +1,576 @@
+// Batched R-MATEX kernels: R <= 64 subtasks (Sec. 3.1) advanced together.
+//
+// Every per-subtask n-vector is stored row-interleaved, x[i * R + r], so a
+// wavefront reads one row of all subtasks in one coalesced access; lane r of
+// a wavefront owns subtask r.
+//
+//  * Multi-right-hand-side substitution pair (Alg. 1's step, for all
+//    subtasks at once). Forward, per level: kb_assemble forms
+//    btilde_s = b_s - (children's updates) for every subtask and seeds the
+//    supernode's update slots with the children's off-row contributions;
+//    kb_fwd then computes [y_s ; delta_s] += W_s * btilde_s, 64 panel rows per
+//    block (16 per wavefront), the panel entry W[row, k] being the same for
+//    all lanes (one scalar load feeds 64 subtasks) and btilde staged in LDS
+//    tiles. Backward, per level: kb_bwd computes x_s = W_s^T [y_s ; -x_off],
+//    64 panel columns per block. Each panel entry is read once per sweep for
+//    all R subtasks.
+//  * Gram-Schmidt per subtask (two classical passes): 256-thread blocks
+//    (lane = subtask, four wavefronts on interleaved rows) write per-block
+//    partial sums per subtask; kb_col_reduce (one block per subtask) sums
+//    them in a fixed order and updates that subtask's state.
+//  * Checks: one block per (subtask, check offset), the plain path's
+//    small-dense routine with the subtask's own state and decision.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "batched.hpp"
+#include "device_common.hpp"
+
+namespace matex {
+
+namespace {
+
+using namespace dev;
+
+constexpr int NVB = MAXM + 1;
+
+// ------------------------------------------------------------- sweeps
+
+__global__ __launch_bounds__(256) void kb_assemble(DevSym s, const int32_t* __restrict__ list,
+                                                   int R, const double* __restrict__ B,
+                                                   const double* __restrict__ scale, double* T,
+                                                   double* U)
+{
+    const int sn = list[blockIdx.x];
+    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    const int64_t u = s.u[sn];
+    for (int idx = threadIdx.x; idx < nc * R; idx += 256) {
+        const int k = idx / R, r = idx - (idx / R) * R;
+        const int64_t o = int64_t(c0 + k) * R + r;
+        T[o] = scale ? B[o] * scale[c0 + k] : B[o];
+    }
+    for (int idx = threadIdx.x; idx < (nr - nc) * R; idx += 256) U[u * R + idx] = 0.0;
+    __syncthreads();
+    const int cp1 = s.child_ptr[sn + 1];
+    for (int cp = s.child_ptr[sn]; cp < cp1; ++cp) {
+        const int c = s.child_idx[cp];
+        const int64_t uc = s.u[c];
+        const int noc = s.nr[c] - s.nc[c];
+        for (int idx = threadIdx.x; idx < noc * R; idx += 256) {
+            const int q = idx / R, r = idx - (idx / R) * R;
+            const int pos = s.relidx[uc + q];
+            const double val = U[(uc + q) * R + r];
+            if (pos < nc) T[int64_t(c0 + pos) * R + r] -= val;
+            else U[(u + pos - nc) * R + r] += val;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_fwd(DevSym s, const int32_t* __restrict__ tsn,
+                                              const int32_t* __restrict__ tfirst, int R,
+                                              const double* __restrict__ W, const double* T,
+                                              double* y, double* U)
+{
+    __shared__ double tile[BKT][RMAX];
+    const int sn = tsn[blockIdx.x], r0 = tfirst[blockIdx.x];
+    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    const int ld = dpanel_ld(nr);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rbase = __builtin_amdgcn_readfirstlane(r0 + wv * 16);
+    const double* Ws = W + s.w[sn];
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    const int kend = min(nc, r0 + BR);   // diagonal rows need k <= row
+    for (int kt = 0; kt < kend; kt += BKT) {
+        const int kn = min(BKT, kend - kt);
+        for (int idx = threadIdx.x; idx < kn * RMAX; idx += 256) {
+            const int kk = idx / RMAX, r = idx - (idx / RMAX) * RMAX;
+            tile[kk][r] = r < R ? T[int64_t(c0 + kt + kk) * R + r] : 0.0;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kn; ++kk) {
+            const int k = kt + kk;
+            const double tv = tile[kk][lane];
+            const double* wk = Ws + int64_t(k) * ld + rbase;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int row = rbase + i;
+                if (row < nr && (row >= nc || k <= row)) acc[i] += wk[i] * tv;
+            }
+        }
+        __syncthreads();
+    }
+    if (lane < R) {
+        const int64_t u = s.u[sn];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int row = rbase + i;
+            if (row >= nr) break;
+            if (row < nc) y[int64_t(c0 + row) * R + lane] = acc[i];
+            else U[(u + row - nc) * R + lane] += acc[i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_bwd(DevSym s, const int32_t* __restrict__ tsn,
+                                              const int32_t* __restrict__ tfirst, int R,
+                                              const double* __restrict__ W, const double* y,
+                                              double* x)
+{
+    __shared__ double tile[BKT][RMAX];
+    const int sn = tsn[blockIdx.x], col0 = tfirst[blockIdx.x];
+    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    const int ld = dpanel_ld(nr);
+    const int32_t* roff = s.rows + s.roff[sn];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int cbase = __builtin_amdgcn_readfirstlane(col0 + wv * 16);
+    const double* Ws = W + s.w[sn];
+    double acc[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
+    for (int kt = col0; kt < nr; kt += BKT) {
+        const int kn = min(BKT, nr - kt);
+        for (int idx = threadIdx.x; idx < kn * RMAX; idx += 256) {
+            const int kk = idx / RMAX, r = idx - (idx / RMAX) * RMAX;
+            const int k = kt + kk;
+            double g = 0.0;
+            if (r < R) g = k < nc ? y[int64_t(c0 + k) * R + r] : -x[int64_t(roff[k - nc]) * R + r];
+            tile[kk][r] = g;
+        }
+        __syncthreads();
+        for (int kk = 0; kk < kn; ++kk) {
+            const int k = kt + kk;
+            const double gv = tile[kk][lane];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int c = cbase + i;
+                if (c < nc && k >= c) acc[i] += Ws[int64_t(c) * ld + k] * gv;
+            }
+        }
+        __syncthreads();
+    }
+    if (lane < R) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int c = cbase + i;
+            if (c < nc) x[int64_t(c0 + c) * R + lane] = acc[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------- Gram-Schmidt
+
+// Sums acc[0..cnt) of lane r over the block's four wavefronts; the result
+// is valid in wavefront 0. buf: 2 * N * 64 doubles of LDS.
+template <int N>
+__device__ inline void combine_waves(double (&acc)[N], int cnt, double* buf)
+{
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (wv >= 2) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (i < cnt) buf[((wv - 2) * N + i) * 64 + lane] = acc[i];
+    }
+    __syncthreads();
+    if (wv < 2) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (i < cnt) acc[i] += buf[(wv * N + i) * 64 + lane];
+    }
+    __syncthreads();
+    if (wv == 1) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (i < cnt) buf[i * 64 + lane] = acc[i];
+    }
+    __syncthreads();
+    if (wv == 0) {
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if (i < cnt) acc[i] += buf[i * 64 + lane];
+    }
+}
+
+// Pass 1: per-block partial dots V_i^T w per subtask, i < nv, into
+// partial[(block * R + r) * (NVB + 1) + i]. Lane = subtask, the block's four
+// wavefronts take interleaved rows.
+__global__ __launch_bounds__(256) void kb_gs_dots(int64_t n, int R, const double* __restrict__ V,
+                                                  int nv, const double* __restrict__ w,
+                                                  double* partial, const KState* ks)
+{
+    __shared__ double buf[2 * NVB * 64];
+    const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool on = r < R && !ks[r < R ? r : 0].done;
+    double acc[NVB];
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) acc[i] = 0.0;
+    if (on) {
+        for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
+            const double wr = w[row * R + r];
+#pragma unroll
+            for (int i = 0; i < NVB; ++i)
+                if (i < nv) acc[i] += wr * V[int64_t(i) * n * R + row * R + r];
+        }
+    }
+    combine_waves(acc, nv, buf);
+    if (wv == 0 && r < R) {
+        double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
+#pragma unroll
+        for (int i = 0; i < NVB; ++i)
+            if (i < nv) out[i] = acc[i];
+    }
+}
+
+// Pass 2: w' = w - V h1 (h1 per subtask from its state), partial dots
+// V^T w' and ||w'||^2 (slot nv; nv <= MAXM so it fits NVB slots).
+__global__ __launch_bounds__(256) void kb_gs_update(int64_t n, int R, const double* __restrict__ V,
+                                                    int nv, double* w, double* partial,
+                                                    const KState* ks)
+{
+    __shared__ double buf[2 * NVB * 64];
+    const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const bool on = r < R && !ks[r < R ? r : 0].done;
+    double h[NVB];
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) h[i] = (on && i < nv) ? ks[r].h1[i] : 0.0;
+    double acc[NVB];
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) acc[i] = 0.0;
+    if (on) {
+        for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
+            double wr = w[row * R + r];
+#pragma unroll
+            for (int i = 0; i < NVB; ++i)
+                if (i < nv) wr -= h[i] * V[int64_t(i) * n * R + row * R + r];
+            w[row * R + r] = wr;
+#pragma unroll
+            for (int i = 0; i < NVB; ++i) {
+                if (i < nv) acc[i] += wr * V[int64_t(i) * n * R + row * R + r];
+                else if (i == nv) acc[i] += wr * wr;
+            }
+        }
+    }
+    combine_waves(acc, nv + 1, buf);
+    if (wv == 0 && r < R) {
+        double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
+#pragma unroll
+        for (int i = 0; i < NVB; ++i)
+            if (i <= nv) out[i] = acc[i];
+    }
+}
+
+// One block per subtask: sums the nblk partial rows of pass `mode`.
+// mode 0: h1 (nv values). mode 1: h2 and ||w'||^2, then the new Hessenberg
+// column, m, breakdown and the normalisation scale of v_{j+1}. mode 2: the
+// squared norm of v (setup): beta, and a reset of the state for a new basis
+// (only for subtasks with active[r]; others are marked done).
+__global__ __launch_bounds__(256) void kb_col_reduce(int R, int nblk, const double* partial,
+                                                     int stride, int nv, int mode, KState* ks,
+                                                     const int32_t* active)
+{
+    const int r = blockIdx.x;
+    KState* k = ks + r;
+    if (mode < 2 && k->done) return;
+    __shared__ double red[4 * (NVMAX + 1)];
+    __shared__ double vals[NVMAX + 1];
+    const int cnt = mode == 0 ? nv : (mode == 1 ? nv + 1 : 1);
+    double acc[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) {
+        const double* p = partial + (int64_t(b) * R + r) * stride;
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i)
+            if (i < cnt) acc[i] += p[i];
+    }
+    block_sums(acc, cnt, red, vals);
+    if (threadIdx.x != 0) return;
+    if (mode == 0) {
+        for (int i = 0; i < nv; ++i) k->h1[i] = vals[i];
+    } else if (mode == 1) {
+        double s2 = 0.0, hmax = 0.0;
+        for (int i = 0; i < nv; ++i) {
+            k->h2[i] = vals[i];
+            s2 += vals[i] * vals[i];
+            hmax = fmax(hmax, fabs(k->h1[i] + vals[i]));
+        }
+        const double beta = sqrt(fmax(vals[nv] - s2, 0.0));
+        const bool brk = !(beta > 1e-14 * hmax);   // happy breakdown: exact
+        const int j = nv - 1;
+        for (int i = 0; i < nv; ++i) k->Ht[i + j * (MAXM + 1)] = k->h1[i] + k->h2[i];
+        k->Ht[nv + j * (MAXM + 1)] = beta;
+        k->m = nv;
+        k->breakdown = brk ? 1 : 0;
+        k->vscale = brk ? 0.0 : 1.0 / beta;
+    } else {
+        if (!active[r]) {
+            k->done = 1;
+            k->converged = 1;
+            return;
+        }
+        const double beta = sqrt(vals[0]);
+        k->beta = beta;
+        k->m = 0;
+        k->breakdown = 0;
+        k->converged = beta == 0.0 ? 1 : 0;
+        k->done = beta == 0.0 ? 1 : 0;
+        k->est = 0.0;
+        k->vscale = beta == 0.0 ? 0.0 : 1.0 / beta;
+    }
+}
+
+// v_{j+1} = (w' - V h2) * vscale per subtask.
+__global__ __launch_bounds__(256) void kb_gs_finish(int64_t n, int R, double* V, int nv,
+                                                    const double* __restrict__ w,
+                                                    const KState* ks)
+{
+    const int r = threadIdx.x & 63;
+    if (r >= R || ks[r].done) return;
+    double h[NVB];
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) h[i] = i < nv ? ks[r].h2[i] : 0.0;
+    const double sc = ks[r].vscale;
+    double* vout = V + int64_t(nv) * n * R;
+    for (int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); row < n; row += int64_t(gridDim.x) * 4) {
+        double wr = w[row * R + r];
+#pragma unroll
+        for (int i = 0; i < NVB; ++i)
+            if (i < nv) wr -= h[i] * V[int64_t(i) * n * R + row * R + r];
+        vout[row * R + r] = wr * sc;
+    }
+}
+
+// -------------------------------------------------------------- checks
+
+// blocks: (subtask chk_col[b], check chk_idx[b]); the subtask's offsets are
+// taus[tau_off[r] .. + tau_cnt[r]], its u vectors and estimates sit in its
+// fixed region of `cap` checks (u_buf + r * cap * MAXM, est_buf + r * cap).
+__global__ __launch_bounds__(256) void kb_checks(KState* ks, double gamma, const double* taus,
+                                                 const int32_t* tau_off, const int32_t* tau_cnt,
+                                                 int cap, const int32_t* chk_col,
+                                                 const int32_t* chk_idx, double tol, double* u_buf,
+                                                 double* est_buf, int m_max, int update_state)
+{
+    const int r = chk_col[blockIdx.x], c = chk_idx[blockIdx.x];
+    KState* k = ks + r;
+    if (update_state && k->done) return;
+    extern __shared__ double sm[];
+    const int64_t reg = int64_t(r) * cap;
+    check_block(k, gamma, taus + tau_off[r], c, tau_cnt[r], tol, u_buf + reg * MAXM, est_buf + reg,
+                m_max, update_state, sm);
+}
+
+// ---------------------------------------------------- set-up and outputs
+
+// v = y - y0 + z2 into V_0, partial squared norms per subtask.
+__global__ __launch_bounds__(256) void kb_setup_v(int64_t n, int R, const double* y,
+                                                  const double* y0, const double* z2, double* v,
+                                                  double* partial, const int32_t* active)
+{
+    __shared__ double buf[2 * 64];
+    const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    double acc[1] = {0.0};
+    if (r < R && active[r]) {
+        for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
+            const int64_t o = row * R + r;
+            const double t = y[o] - y0[o] + z2[o];
+            v[o] = t;
+            acc[0] += t * t;
+        }
+    }
+    combine_waves(acc, 1, buf);
+    if (wv == 0 && r < R) partial[(int64_t(blockIdx.x) * R + r) * 2] = acc[0];
+}
+
+__global__ __launch_bounds__(256) void kb_scale_v(int64_t n, int R, double* v, const KState* ks,
+                                                  const int32_t* active)
+{
+    const int r = threadIdx.x & 63;
+    if (r >= R || !active[r] || ks[r].done) return;
+    const double sc = ks[r].vscale;
+    for (int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); row < n; row += int64_t(gridDim.x) * 4)
+        v[row * R + r] *= sc;
+}
+
+// Yout[(r * n_probe + p) * n_out + tidx] for every (subtask, snapshot) entry.
+__global__ __launch_bounds__(256) void kb_recon_probes(int64_t n, int R, int n_probe,
+                                                       const int32_t* probe_perm, int n_ent,
+                                                       const int32_t* ent_col,
+                                                       const int32_t* ent_t,
+                                                       const double* ent_tau,
+                                                       const int32_t* ent_u, const double* u_buf,
+                                                       const KState* ks, const double* V,
+                                                       const double* y0, const double* z1,
+                                                       const double* z2, double* Yout, int n_out)
+{
+    const int64_t id = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (id >= int64_t(n_ent) * n_probe) return;
+    const int e = int(id / n_probe), p = int(id % n_probe);
+    const int r = ent_col[e];
+    const int64_t o = int64_t(probe_perm[p]) * R + r;
+    const int m = ks[r].m;
+    const double* u = u_buf + int64_t(ent_u[e]) * MAXM;
+    double acc = 0.0;
+    for (int k = 0; k < m; ++k) acc += V[int64_t(k) * n * R + o] * u[k];
+    acc *= ks[r].beta;
+    const double t = ent_tau[e];
+    Yout[(int64_t(r) * n_probe + p) * n_out + ent_t[e]] = acc + y0[o] + t * z1[o] - z2[o];
+}
+
+// Step end per active subtask: y = beta V u + y0 + tau z1 - z2, y0 += tau z1.
+__global__ __launch_bounds__(256) void kb_recon_full(int64_t n, int R, const double* col_tau,
+                                                     const int32_t* col_u, const double* u_buf,
+                                                     const KState* ks, const int32_t* active,
+                                                     const double* V, double* y, double* y0,
+                                                     const double* z1, const double* z2)
+{
+    const int r = threadIdx.x & 63;
+    if (r >= R || !active[r]) return;
+    const int m = ks[r].m;
+    const double beta = ks[r].beta, tau = col_tau[r];
+    const double* u = u_buf + int64_t(col_u[r]) * MAXM;
+    for (int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); row < n; row += int64_t(gridDim.x) * 4) {
+        const int64_t o = row * R + r;
+        double acc = 0.0;
+        for (int k = 0; k < m; ++k) acc += V[int64_t(k) * n * R + o] * u[k];
+        const double a = y0[o], b = z1[o];
+        y[o] = beta * acc + a + tau * b - z2[o];
+        y0[o] = a + tau * b;
+    }
+}
+
+// s[row * R + col] += d for the events of this generation ((row, col) unique).
+__global__ void kb_events(int cnt, int R, const int32_t* row, const int32_t* col, const double* d,
+                          double* s)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < cnt) s[int64_t(row[k]) * R + col[k]] += d[k];
+}
+
+// Superposition of one batch (Sec. 3.1): out[p, t] -= sum_r Yout[r, p, t];
+// final[perm[i]] -= sum_r y[i, r] (the outputs start at Vdd).
+__global__ void kb_sum_out(int64_t count, int R, const double* Yout, double* out)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += int64_t(gridDim.x) * 256) {
+        double acc = 0.0;
+        for (int r = 0; r < R; ++r) acc += Yout[int64_t(r) * count + i];
+        out[i] -= acc;
+    }
+}
+
+__global__ void kb_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double* out)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        double acc = 0.0;
+        for (int r = 0; r < R; ++r) acc += y[i * R + r];
+        out[perm[i]] -= acc;
+    }
+}
+
+__global__ void kb_fill(int64_t count, double v, double* x)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += int64_t(gridDim.x) * 256)
+        x[i] = v;
+}
+
+inline int grid_rows(int64_t n, int per_block) { return int(std::min<int64_t>((n + per_block - 1) / per_block, 4096)); }
+
+}  // namespace
+
+void launch_b_forward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
+                      const double* B, const double* scale, double* T, double* y, double* U,
+                      hipStream_t st)
+{
+    kb_assemble<<<lv.n_sn, 256, 0, st>>>(s, lv.sn_list, R, B, scale, T, U);
+    kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, lv.fwd_sn, lv.fwd_first, R, W, T, y, U);
+}
+
+void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
+                       const double* y, double* x, hipStream_t st)
+{
+    kb_bwd<<<lv.n_bwd, 256, 0, st>>>(s, lv.bwd_sn, lv.bwd_first, R, W, y, x);
+}
+
+void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial, KState* ks,
+                 hipStream_t st)
+{
+    const int nb = B_RED_BLOCKS;
+    const int stride = NVB + 1;
+    kb_gs_dots<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
+    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 0, ks, nullptr);
+    kb_gs_update<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
+    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 1, ks, nullptr);
+    kb_gs_finish<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks);
+}
+
+void launch_b_checks(KState* ks, double gamma, const double* taus, const int32_t* tau_off,
+                     const int32_t* tau_cnt, int cap, const int32_t* chk_col,
+                     const int32_t* chk_idx, int n_chk, double tol, double* u_buf, double* est_buf,
+                     int m_max, int update_state, hipStream_t st)
+{
+    if (n_chk <= 0) return;
+    kb_checks<<<n_chk, 256, checks_lds_bytes(), st>>>(ks, gamma, taus, tau_off, tau_cnt, cap, chk_col,
+                                                      chk_idx, tol, u_buf, est_buf, m_max,
+                                                      update_state);
+}
+
+void launch_b_setup(int64_t n, int R, const double* y, const double* y0, const double* z2,
+                    double* V, double* partial, KState* ks, const int32_t* active, hipStream_t st)
+{
+    const int nb = B_RED_BLOCKS;
+    kb_setup_v<<<nb, 256, 0, st>>>(n, R, y, y0, z2, V, partial, active);
+    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, 2, 0, 2, ks, active);
+    kb_scale_v<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, ks, active);
+}
+
+void launch_b_recon_probes(int64_t n, int R, int n_probe, const int32_t* probe_perm, int n_ent,
+                           const int32_t* ent_col, const int32_t* ent_t, const double* ent_tau,
+                           const int32_t* ent_u, const double* u_buf, const KState* ks,
+                           const double* V, const double* y0, const double* z1, const double* z2,
+                           double* Yout, int n_out, hipStream_t st)
+{
+    const int64_t tot = int64_t(n_ent) * n_probe;
+    if (tot == 0) return;
+    kb_recon_probes<<<int((tot + 255) / 256), 256, 0, st>>>(n, R, n_probe, probe_perm, n_ent, ent_col,
+                                                            ent_t, ent_tau, ent_u, u_buf, ks, V, y0,
+                                                            z1, z2, Yout, n_out);
+}
+
+void launch_b_recon_full(int64_t n, int R, const double* col_tau, const int32_t* col_u,
+                         const double* u_buf, const KState* ks, const int32_t* active,
+                         const double* V, double* y, double* y0, const double* z1, const double* z2,
+                         hipStream_t st)
+{
+    kb_recon_full<<<grid_rows(n, 4), 256, 0, st>>>(n, R, col_tau, col_u, u_buf, ks, active, V, y, y0,
+                                                   z1, z2);
+}
+
+void launch_b_events(int cnt, int R, const int32_t* row, const int32_t* col, const double* d,
+                     double* s, hipStream_t st)
+{
+    if (cnt <= 0) return;
+    kb_events<<<(cnt + 255) / 256, 256, 0, st>>>(cnt, R, row, col, d, s);
+}
+
+void launch_b_sum_out(int64_t count, int R, const double* Yout, double* out, hipStream_t st)
+{
+    if (count <= 0) return;
+    kb_sum_out<<<grid_rows(count, 256), 256, 0, st>>>(count, R, Yout, out);
+}
+
+void launch_b_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double* out,
+                        hipStream_t st)
+{
+    kb_sum_final<<<grid_rows(n, 256), 256, 0, st>>>(n, R, perm, y, out);
+}
+
+void launch_b_fill(int64_t count, double v, double* x, hipStream_t st)
+{
+    if (count <= 0) return;
+    kb_fill<<<grid_rows(count, 256), 256, 0, st>>>(count, v, x);
+}
+
+}  // namespace matex

@@ -1,0 +1,328 @@
+// Device helpers shared by the plain and the batched kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "factor.hpp"
+#include "kernels.hpp"
+
+namespace matex {
+namespace dev {
+
+// Leading dimension of a panel with nr rows (device twin of panel_ld).
+__device__ inline int dpanel_ld(int nr) { return (nr + PANEL_ALIGN - 1) / PANEL_ALIGN * PANEL_ALIGN; }
+
+__device__ inline double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    return v;
+}
+
+// Block-wide sum of one value per thread (256 threads); result valid in thread 0.
+__device__ inline double block_sum(double v, double* red)
+{
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = (red[0] + red[1]) + (red[2] + red[3]);
+    return r;
+}
+
+// Marks this block done among `total` cooperating blocks; returns true in
+// exactly one of them (the last to arrive), which also resets the counter.
+__device__ inline bool last_of(int32_t* counter, int32_t total)
+{
+    __shared__ int32_t is_last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int32_t prev = atomicAdd(counter, 1);
+        is_last = (prev == total - 1);
+        if (is_last) *counter = 0;
+    }
+    __syncthreads();
+    if (is_last) __threadfence();
+    return is_last != 0;
+}
+
+__device__ inline bool last_block(int32_t* counter) { return last_of(counter, int32_t(gridDim.x)); }
+
+constexpr int NVMAX = MAXM + 1;
+
+// Sums acc[0..cnt) over the block with one barrier: wavefront shuffles, then
+// the four wavefront partials of value i are added by thread i. Result in
+// out[i] (LDS) for i < cnt. red: LDS scratch of 4 * (NVMAX + 1) doubles.
+template <int N>
+__device__ inline void block_sums(const double (&acc)[N], int cnt, double* red, double* out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        if (i < cnt) {
+            const double t = wave_sum(acc[i]);
+            if (lane == 0) red[wv * (NVMAX + 1) + i] = t;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < cnt) {
+        const int i = threadIdx.x;
+        out[i] = (red[i] + red[(NVMAX + 1) + i]) + (red[2 * (NVMAX + 1) + i] + red[3 * (NVMAX + 1) + i]);
+    }
+    __syncthreads();
+}
+
+// In the last block: out[i] = sum_b partial[b * stride + i] for i < cnt,
+// b < nblk (<= 256), with one partial row per thread and one block reduction.
+__device__ inline void reduce_partials(const double* partial, int stride, int nblk, int cnt,
+                                       double* red, double* out)
+{
+    double acc[NVMAX];
+    const int b = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i)
+        acc[i] = (i < cnt && b < nblk) ? partial[int64_t(b) * stride + i] : 0.0;
+    block_sums(acc, cnt, red, out);
+}
+
+// Pass 1: per-block partial dots V_i^T w, i < nv, into partial[block][i].
+
+constexpr int LD = MAXM + 1;   // LDS row stride (avoids bank conflicts)
+
+// Higham (2005): numerator coefficients of the [13/13] Pade approximant and
+// the largest 1-norm at which it meets double-precision backward error.
+static __constant__ double PADE13[14] = {
+    64764752532480000.0, 32382376266240000.0, 7771770303897600.0, 1187353796428800.0,
+    129060195264000.0,   10559470521600.0,    670442572800.0,     33522128640.0,
+    1323241920.0,        40840800.0,          960960.0,           16380.0,
+    182.0,               1.0};
+constexpr double THETA13 = 5.371920351148152;
+
+// C = A * B (m x m, row-major, stride LD) by the whole block.
+__device__ inline void mm(const double* A, const double* B, double* C, int m)
+{
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx - (idx / m) * m;
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += A[i * LD + k] * B[k * LD + j];
+        C[i * LD + j] = s;
+    }
+    __syncthreads();
+}
+
+// Solve Q X = P in place (X overwrites P) by Gaussian elimination with partial
+// pivoting; Q is destroyed. Whole block.
+__device__ inline void solve_inplace(double* Q, double* P, int m, int ncol)
+{
+    __shared__ int piv;
+    for (int k = 0; k < m; ++k) {
+        if (threadIdx.x == 0) {
+            int p = k;
+            double best = fabs(Q[k * LD + k]);
+            for (int i = k + 1; i < m; ++i)
+                if (fabs(Q[i * LD + k]) > best) { best = fabs(Q[i * LD + k]); p = i; }
+            piv = p;
+        }
+        __syncthreads();
+        const int p = piv;
+        if (p != k) {
+            for (int j = threadIdx.x; j < m; j += blockDim.x) {
+                const double t = Q[k * LD + j]; Q[k * LD + j] = Q[p * LD + j]; Q[p * LD + j] = t;
+            }
+            for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
+                const double t = P[k * LD + j]; P[k * LD + j] = P[p * LD + j]; P[p * LD + j] = t;
+            }
+        }
+        __syncthreads();
+        const double dk = Q[k * LD + k];
+        const int rows = m - k - 1;
+        for (int idx = threadIdx.x; idx < rows * (m - k + ncol); idx += blockDim.x) {
+            const int i = k + 1 + idx / (m - k + ncol);
+            const int c = idx % (m - k + ncol);
+            const double f = Q[i * LD + k] / dk;
+            if (c < m - k) { if (c > 0) Q[i * LD + k + c] -= f * Q[k * LD + k + c]; }
+            else P[i * LD + (c - (m - k))] -= f * P[k * LD + (c - (m - k))];
+        }
+        __syncthreads();
+        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) Q[i * LD + k] = 0.0;
+        __syncthreads();
+    }
+    // back substitution, one column per thread
+    for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
+        for (int i = m - 1; i >= 0; --i) {
+            double s = P[i * LD + j];
+            for (int k = i + 1; k < m; ++k) s -= Q[i * LD + k] * P[k * LD + j];
+            P[i * LD + j] = s / Q[i * LD + i];
+        }
+    }
+    __syncthreads();
+}
+
+// H = (I - Ht_m^-1) / gamma into H (row-major, stride LD); uses T1, T2.
+__device__ inline void form_h(const KState* ks, int m, double gamma, double* H, double* T1)
+{
+    for (int idx = threadIdx.x; idx < m * LD; idx += blockDim.x) {
+        const int i = idx / LD, j = idx % LD;
+        T1[idx] = (j < m) ? ks->Ht[i + j * (MAXM + 1)] : 0.0;
+        H[idx] = (j < m && i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    solve_inplace(T1, H, m, m);           // H = Ht^-1
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m;
+        H[i * LD + j] = ((i == j ? 1.0 : 0.0) - H[i * LD + j]) / gamma;
+    }
+    __syncthreads();
+}
+
+// u = e^{tau H} e1 (m entries). Uses 6 matrices of MAXM x LD in `buf`; H is
+// overwritten (its storage holds V of the approximant once A = tau H / 2^s).
+__device__ inline void expm_e1(double* H, int m, double tau, double* buf, double* u)
+{
+    double* A = buf;
+    double* A2 = A + MAXM * LD;
+    double* A4 = A2 + MAXM * LD;
+    double* A6 = A4 + MAXM * LD;
+    double* T = A6 + MAXM * LD;
+    double* Um = T + MAXM * LD;
+    double* Vm = H;
+    __shared__ double nrm;
+    __shared__ int sq;
+    // 1-norm of tau H
+    if (threadIdx.x == 0) {
+        double best = 0.0;
+        for (int j = 0; j < m; ++j) {
+            double c = 0.0;
+            for (int i = 0; i < m; ++i) c += fabs(H[i * LD + j]);
+            best = fmax(best, c);
+        }
+        nrm = best * tau;
+        int s = 0;
+        if (nrm > THETA13) s = int(ceil(log2(nrm / THETA13)));
+        sq = s;
+    }
+    __syncthreads();
+    const double scl = tau * ldexp(1.0, -sq);
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m;
+        A[i * LD + j] = H[i * LD + j] * scl;
+    }
+    __syncthreads();
+    mm(A, A, A2, m);
+    mm(A2, A2, A4, m);
+    mm(A4, A2, A6, m);
+    const double* b = PADE13;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m, o = i * LD + j;
+        T[o] = b[13] * A6[o] + b[11] * A4[o] + b[9] * A2[o];
+    }
+    __syncthreads();
+    mm(A6, T, Um, m);
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m, o = i * LD + j;
+        T[o] = Um[o] + b[7] * A6[o] + b[5] * A4[o] + b[3] * A2[o] + (i == j ? b[1] : 0.0);
+    }
+    __syncthreads();
+    mm(A, T, Um, m);                        // U
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m, o = i * LD + j;
+        T[o] = b[12] * A6[o] + b[10] * A4[o] + b[8] * A2[o];
+    }
+    __syncthreads();
+    mm(A6, T, Vm, m);
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m, o = i * LD + j;
+        const double v = Vm[o] + b[6] * A6[o] + b[4] * A4[o] + b[2] * A2[o] + (i == j ? b[0] : 0.0);
+        const double uu = Um[o];
+        A2[o] = v - uu;   // Q
+        A4[o] = v + uu;   // P
+    }
+    __syncthreads();
+    solve_inplace(A2, A4, m, m);            // R = Q^-1 P in A4
+    double* R = A4;
+    double* S = A6;
+    for (int k = 0; k < sq; ++k) {
+        mm(R, R, S, m);
+        double* t = R; R = S; S = t;
+    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) u[i] = R[i * LD];
+    __syncthreads();
+}
+
+
+// One check offset of one Krylov process (block-wide): H_m from Ht, u =
+// e^{tau H_m} e1 into u_buf[c], the estimate into est_buf[c]; the last of
+// the process's n_tau blocks takes the maximum and decides. update_state:
+// iterating (u_buf[c] holds the previous dimension's vector and the decision
+// may end the process) or only evaluating a new check set on a fixed basis.
+// sm: 7 * MAXM * LD + 2 * MAXM doubles.
+__device__ inline void check_block(KState* ks, double gamma, const double* taus, int c, int n_tau,
+                                   double tol, double* u_buf, double* est_buf, int m_max,
+                                   int update_state, double* sm)
+{
+    double* H = sm;                          // MAXM x LD
+    double* buf = H + MAXM * LD;             // 6 matrices
+    double* u = buf + 6 * MAXM * LD;         // MAXM
+    double* up = u + MAXM;                   // MAXM
+    __shared__ double red[4];
+    const int m = ks->m;
+    const double tau = taus[c];
+    form_h(ks, m, gamma, H, buf);
+    expm_e1(H, m, tau, buf, u);
+    // previous-dimension vector: from the buffer when iterating, recomputed
+    // when only evaluating (the basis is unchanged)
+    if (m == 1) {
+        if (threadIdx.x == 0) up[0] = 1.0;
+    } else if (update_state) {
+        for (int i = threadIdx.x; i < m - 1; i += blockDim.x) up[i] = u_buf[c * MAXM + i];
+    } else {
+        form_h(ks, m - 1, gamma, H, buf);
+        expm_e1(H, m - 1, tau, buf, up);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double beta = ks->beta;
+        const double hnext = ks->Ht[m + (m - 1) * (MAXM + 1)];
+        const double paper = beta * hnext * fabs(u[m - 1]);
+        // change from the dimension m-1 approximation [u_{m-1}; 0]; for m = 1
+        // that approximation is v itself, u_0 = 1
+        double d2 = 0.0;
+        for (int i = 0; i < m; ++i) {
+            const double prev = (m == 1) ? 1.0 : (i < m - 1 ? up[i] : 0.0);
+            const double d = u[i] - prev;
+            d2 += d * d;
+        }
+        const double est = ks->breakdown ? 0.0 : fmax(paper, beta * sqrt(d2));
+        est_buf[c] = est;
+    }
+    for (int i = threadIdx.x; i < m; i += blockDim.x) u_buf[c * MAXM + i] = u[i];
+    if (last_of(&ks->counter, n_tau)) {
+        double e = 0.0;
+        for (int k = threadIdx.x; k < n_tau; k += blockDim.x) e = fmax(e, est_buf[k]);
+        // block maximum through the sum helper's layout
+        e = -e;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) e = fmin(e, __shfl_down(e, o, 64));
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        __syncthreads();
+        if (lane == 0) red[wv] = -e;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double mx = 0.0;
+            for (int q = 0; q < int(blockDim.x + 63) / 64; ++q) mx = fmax(mx, red[q]);
+            ks->est = mx;
+            const int conv = (mx < tol) || ks->breakdown;
+            ks->converged = conv;
+            if (update_state && (conv || m >= m_max)) ks->done = 1;
+        }
+    }
+}
+
+}  // namespace dev
+}  // namespace matex

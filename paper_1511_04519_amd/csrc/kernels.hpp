@@ -62,6 +62,7 @@ struct KState {
     double beta;           // ||v||
     double est;            // max estimate over the check set at dimension m
     double nrm2;           // ||w'||^2 after the first Gram-Schmidt pass
+    double vscale;         // 1 / ||w''|| for the next basis vector (0 at breakdown)
     double h1[MAXM + 1];   // first Gram-Schmidt pass coefficients
     double h2[MAXM + 1];   // second pass
     double Ht[(MAXM + 1) * MAXM];   // column-major (MAXM+1) x MAXM

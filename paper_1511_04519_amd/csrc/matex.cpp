@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/matex.h"
+#include "batched.hpp"
 #include "factor.hpp"
 #include "kernels.hpp"
 
@@ -109,6 +110,9 @@ struct matex_factor_s {
     SweepPlan plan{};
     int sweep_blocks = 0;
     bool use_levels = false;
+    // batched (multi-subtask) sweeps
+    DevMem d_b_list, d_b_fsn, d_b_ffirst, d_b_bsn, d_b_bfirst;
+    std::vector<BatchLevel> blevels;
     DevSym dsym{};
     matex_factor_info info{};
 };
@@ -152,6 +156,36 @@ void build_tasks(matex_factor_s& F)
                      int32_t(boff[lv + 1] - boff[lv]), blds[lv], small[lv]};
         F.fwd.push_back(f);
         F.bwd.push_back(b);
+    }
+    // batched sweeps: per level, the supernodes, 64-row forward tasks and
+    // 64-column backward tasks
+    {
+        std::vector<int32_t> lst, fsn2, ff2, bsn2, bf2;
+        std::vector<int64_t> lo(s.n_levels + 1), fo(s.n_levels + 1), bo(s.n_levels + 1);
+        for (int lv = 0; lv < s.n_levels; ++lv) {
+            lo[lv] = int64_t(lst.size()); fo[lv] = int64_t(fsn2.size()); bo[lv] = int64_t(bsn2.size());
+            for (int32_t k : s.level_sn[lv]) {
+                lst.push_back(k);
+                for (int32_t r = 0; r < s.sn[k].nr; r += BR) { fsn2.push_back(k); ff2.push_back(r); }
+                for (int32_t c = 0; c < s.sn[k].nc; c += BR) { bsn2.push_back(k); bf2.push_back(c); }
+            }
+        }
+        lo[s.n_levels] = int64_t(lst.size()); fo[s.n_levels] = int64_t(fsn2.size());
+        bo[s.n_levels] = int64_t(bsn2.size());
+        F.d_b_list = upload(lst); F.d_b_fsn = upload(fsn2); F.d_b_ffirst = upload(ff2);
+        F.d_b_bsn = upload(bsn2); F.d_b_bfirst = upload(bf2);
+        for (int lv = 0; lv < s.n_levels; ++lv) {
+            BatchLevel b;
+            b.sn_list = F.d_b_list.as<int32_t>() + lo[lv];
+            b.n_sn = int32_t(lo[lv + 1] - lo[lv]);
+            b.fwd_sn = F.d_b_fsn.as<int32_t>() + fo[lv];
+            b.fwd_first = F.d_b_ffirst.as<int32_t>() + fo[lv];
+            b.n_fwd = int32_t(fo[lv + 1] - fo[lv]);
+            b.bwd_sn = F.d_b_bsn.as<int32_t>() + bo[lv];
+            b.bwd_first = F.d_b_bfirst.as<int32_t>() + bo[lv];
+            b.n_bwd = int32_t(bo[lv + 1] - bo[lv]);
+            F.blevels.push_back(b);
+        }
     }
     // one-launch plan: forward tasks (levels up), then backward (levels down)
     const int32_t nsn = int32_t(s.sn.size());
@@ -240,6 +274,18 @@ void dev_solve(const matex_factor_s& F, int which, const double* b, const double
     const int L = F.sym.n_levels;
     for (int lv = 0; lv < L; ++lv) launch_forward(F.dsym, F.fwd[lv], W, b, scale, tmp, upd, done, st);
     for (int lv = L - 1; lv >= 0; --lv) launch_backward(F.dsym, F.bwd[lv], W, tmp, x, done, st);
+}
+
+// Multi-subtask pair: x = A_which^-1 (scale .* B) for R row-interleaved
+// right-hand sides (n x R). T, yf: n x R scratch; U: n_upd x R scratch.
+void dev_solve_batched(const matex_factor_s& F, int which, int R, const double* B,
+                       const double* scale, double* x, double* T, double* yf, double* U,
+                       hipStream_t st)
+{
+    const double* W = F.d_W[which].as<double>();
+    const int L = F.sym.n_levels;
+    for (int lv = 0; lv < L; ++lv) launch_b_forward(F.dsym, F.blevels[lv], R, W, B, scale, T, yf, U, st);
+    for (int lv = L - 1; lv >= 0; --lv) launch_b_backward(F.dsym, F.blevels[lv], R, W, yf, x, st);
 }
 
 // Raises if a one-launch sweep gave up waiting (reads the error word).
@@ -651,6 +697,425 @@ std::vector<Segment> plan_spots(const matex_problem* p, const std::vector<int32_
     return out;
 }
 
+// Check offsets of a step from t_a towards the next spot t_next: the output
+// times in (t_a, t_next] and the spot itself (Alg. 2 reuses one basis for
+// every snapshot before the next spot). *snap0: index of the first output
+// after t_a.
+std::vector<int64_t> step_offsets(const std::vector<int64_t>& tout, int64_t t_a, int64_t t_next,
+                                  int32_t* snap0)
+{
+    auto lo = std::upper_bound(tout.begin(), tout.end(), t_a);
+    auto hi = std::upper_bound(tout.begin(), tout.end(), t_next);
+    std::vector<int64_t> offs;
+    for (auto it = lo; it != hi; ++it) offs.push_back(*it - t_a);
+    if (offs.empty() || offs.back() != t_next - t_a) offs.push_back(t_next - t_a);
+    *snap0 = int32_t(lo - tout.begin());
+    return offs;
+}
+
+// Shift ladder: the largest gamma_k with tau_1 >= ratio * gamma_k, else the
+// smallest shift.
+int ladder_shift(const std::vector<double>& gammas, int64_t off0, double ratio)
+{
+    for (size_t k = 0; k < gammas.size(); ++k)
+        if (double(off0) * FS >= ratio * gammas[k]) return int(k);
+    return int(gammas.size()) - 1;
+}
+
+// Below the top shift a step ends at its last check offset <= 10 gamma_k.
+void ladder_cut(std::vector<int64_t>& offs, const std::vector<double>& gammas, int k)
+{
+    if (k == 0) return;
+    const double lim = 10.0 * gammas[k];
+    size_t cnt = 0;
+    while (cnt < offs.size() && double(offs[cnt]) * FS <= lim) cnt++;
+    offs.resize(std::max<size_t>(1, cnt));
+}
+
+// Offsets of a halved step: those below hstep, then hstep.
+std::vector<int64_t> halved_offsets(const std::vector<int64_t>& offs, int64_t hstep)
+{
+    std::vector<int64_t> o2;
+    for (int64_t v : offs)
+        if (v < hstep) o2.push_back(v);
+    o2.push_back(hstep);
+    return o2;
+}
+
+struct NoConv {
+    std::string msg;
+};
+
+// ------------------------------------------------- batched subtasks
+
+// Host staging of one device table: consecutive typed arrays packed into a
+// pinned buffer and uploaded with one copy; the device copy has the same
+// layout.
+struct Packer {
+    char* h;
+    char* d;
+    size_t size, off = 0;
+    Packer(const PinnedMem& hm, const DevMem& dm, size_t sz)
+        : h(hm.as<char>()), d(static_cast<char*>(dm.p)), size(sz) {}
+    template <class T> T* take(size_t count, T** dev) {
+        off = (off + 15) & ~size_t(15);
+        if (off + sizeof(T) * count > size) throw HipError{hipErrorInvalidValue, "staging table overflow"};
+        T* hp = reinterpret_cast<T*>(h + off);
+        *dev = reinterpret_cast<T*>(d + off);
+        off += sizeof(T) * count;
+        return hp;
+    }
+    void upload(hipStream_t st) {
+        if (off) HIPCHK(hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, st));
+    }
+};
+
+// Per-subtask planner state.
+struct BCol {
+    std::vector<Segment> spots;
+    size_t k_spot = 0;
+    int64_t t_a = 0;
+    std::vector<int64_t> offs, cand;
+    int32_t snap0 = 0;
+    int ksh = 0;
+    int64_t hstep = 0;
+};
+
+// Buffers of one batch of up to RMAX subtasks; n x R arrays row-interleaved.
+struct BatchWork {
+    int64_t n;
+    int Rmax, cap;
+    DevMem V, w, T, yf, U, partial, ks, y, y0, z1, z2, s, u, est, Yout, probe_perm;
+    size_t tab_bytes, ev_bytes;
+    PinnedMem h_pre, h_post, h_ks;
+    DevMem d_pre, d_post;
+    std::unique_ptr<PinnedMem> h_ev;
+    DevMem d_ev;
+    static size_t table_bytes(int R, int cap) {
+        const size_t e = size_t(R) * cap;
+        return e * (2 * sizeof(double) + 3 * sizeof(int32_t)) + size_t(R) * 8 * sizeof(double) + 16 * 16;
+    }
+    BatchWork(const matex_factor_s& F, int Rmax_, int cap_, int64_t n_po)
+        : n(F.sym.n), Rmax(Rmax_), cap(cap_), tab_bytes(table_bytes(Rmax_, cap_)), ev_bytes(1 << 16),
+          h_pre(tab_bytes), h_post(tab_bytes), h_ks(sizeof(KState) * RMAX)
+    {
+        const size_t nr = sizeof(double) * size_t(n) * Rmax;
+        V = DevMem(nr * (MAXM + 1));
+        HIPCHK(hipMemset(V.p, 0, V.bytes));
+        w = DevMem(nr); T = DevMem(nr); yf = DevMem(nr);
+        U = DevMem(sizeof(double) * std::max<int64_t>(1, F.sym.n_upd) * Rmax);
+        partial = DevMem(sizeof(double) * size_t(B_RED_BLOCKS) * Rmax * (MAXM + 2));
+        ks = DevMem(sizeof(KState) * Rmax);
+        HIPCHK(hipMemset(ks.p, 0, ks.bytes));
+        y = DevMem(nr); y0 = DevMem(nr); z1 = DevMem(nr); z2 = DevMem(nr); s = DevMem(nr);
+        u = DevMem(sizeof(double) * size_t(Rmax) * cap * MAXM);
+        est = DevMem(sizeof(double) * size_t(Rmax) * cap);
+        Yout = DevMem(sizeof(double) * std::max<int64_t>(1, n_po) * Rmax);
+        d_pre = DevMem(tab_bytes);
+        d_post = DevMem(tab_bytes);
+        h_ev.reset(new PinnedMem(ev_bytes));
+        d_ev = DevMem(ev_bytes);
+    }
+    double* Vd() const { return V.as<double>(); }
+    KState* kst() const { return ks.as<KState>(); }
+};
+
+std::vector<KsHost> read_states(const BatchWork& bw, int R, hipStream_t st)
+{
+    KsHost* h = bw.h_ks.as<KsHost>();
+    HIPCHK(hipMemcpy2DAsync(h, sizeof(KsHost), bw.ks.p, sizeof(KState), sizeof(KsHost), R,
+                            hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return std::vector<KsHost>(h, h + R);
+}
+
+// Checks table of the columns in `cols_in` with offsets off_of(r).
+struct CheckTab {
+    double* taus = nullptr;
+    int32_t *off = nullptr, *cnt = nullptr, *active = nullptr, *col = nullptr, *idx = nullptr;
+    int n_chk = 0;
+};
+
+template <class OffsOf>
+CheckTab build_checks(BatchWork& bw, int R, const std::vector<int>& cols_in, OffsOf off_of,
+                      hipStream_t st)
+{
+    size_t tot = 0;
+    for (int r : cols_in) tot += off_of(r).size();
+    Packer pk(bw.h_pre, bw.d_pre, bw.tab_bytes);
+    CheckTab t;
+    double* ht = pk.take<double>(std::max<size_t>(1, tot), &t.taus);
+    int32_t* hoff = pk.take<int32_t>(R, &t.off);
+    int32_t* hcnt = pk.take<int32_t>(R, &t.cnt);
+    int32_t* hact = pk.take<int32_t>(R, &t.active);
+    int32_t* hcol = pk.take<int32_t>(std::max<size_t>(1, tot), &t.col);
+    int32_t* hidx = pk.take<int32_t>(std::max<size_t>(1, tot), &t.idx);
+    std::fill(hoff, hoff + R, 0);
+    std::fill(hcnt, hcnt + R, 0);
+    std::fill(hact, hact + R, 0);
+    size_t q = 0;
+    for (int r : cols_in) {
+        const std::vector<int64_t>& of = off_of(r);
+        hoff[r] = int32_t(q);
+        hcnt[r] = int32_t(of.size());
+        hact[r] = 1;
+        for (size_t c = 0; c < of.size(); ++c, ++q) {
+            ht[q] = double(of[c]) * FS;
+            hcol[q] = r;
+            hidx[q] = int32_t(c);
+        }
+    }
+    t.n_chk = int(q);
+    pk.upload(st);
+    return t;
+}
+
+// One lockstep pass of Alg. 1 with shift k for the subtasks in grp (the
+// others inactive): one multi-right-hand-side substitution pair per Krylov
+// iteration for the whole batch, then per-subtask Gram-Schmidt and checks.
+std::vector<KsHost> run_pass(const matex_factor_s& F, BatchWork& bw, int R, int k,
+                             const std::vector<int>& grp, std::vector<BCol>& cols, double tol,
+                             int m_max, int& m_guess, matex_stats& S, hipStream_t st)
+{
+    const int64_t n = bw.n;
+    CheckTab t = build_checks(bw, R, grp, [&](int r) -> const std::vector<int64_t>& { return cols[r].offs; }, st);
+    double* V = bw.Vd();
+    launch_b_setup(n, R, bw.y.as<double>(), bw.y0.as<double>(), bw.z2.as<double>(), V,
+                   bw.partial.as<double>(), bw.kst(), t.active, st);
+    std::vector<KsHost> hs = read_states(bw, R, st);
+    auto all_done = [&]() {
+        for (int r : grp)
+            if (!hs[r].done) return false;
+        return true;
+    };
+    int j = 0, chunk = std::max(1, std::min(m_guess, m_max));
+    while (!all_done() && j < m_max) {
+        const int stop = std::min(m_max, j + chunk);
+        for (; j < stop; ++j) {
+            dev_solve_batched(F, k, R, V + int64_t(j) * n * R, F.d_cperm.as<double>(), bw.w.as<double>(),
+                              bw.T.as<double>(), bw.yf.as<double>(), bw.U.as<double>(), st);
+            launch_b_gs(n, R, V, j + 1, bw.w.as<double>(), bw.partial.as<double>(), bw.kst(), st);
+            launch_b_checks(bw.kst(), F.gammas[k], t.taus, t.off, t.cnt, bw.cap, t.col, t.idx, t.n_chk, tol,
+                            bw.u.as<double>(), bw.est.as<double>(), m_max, 1, st);
+            S.solve_pairs_m++;
+        }
+        hs = read_states(bw, R, st);
+        chunk = 1;
+    }
+    int mx = 0;
+    for (int r : grp) {
+        S.bases++;
+        S.krylov_dims += hs[r].m;
+        S.m_peak = std::max(S.m_peak, hs[r].m);
+        mx = std::max(mx, hs[r].m);
+    }
+    if (mx > 0) m_guess = mx;
+    return hs;
+}
+
+// Snapshots at the probes and the step-end state of the subtasks in fin.
+void reconstruct(BatchWork& bw, int R, const std::vector<int>& fin, std::vector<BCol>& cols,
+                 const std::vector<int64_t>& tout, int n_probe, int n_out, matex_stats& S,
+                 hipStream_t st)
+{
+    size_t n_ent = 0;
+    for (int r : fin) {
+        const BCol& c = cols[r];
+        const int64_t t_b = c.t_a + c.offs.back();
+        for (int32_t q = c.snap0; q < int32_t(tout.size()) && tout[q] <= t_b; ++q) n_ent++;
+    }
+    Packer pk(bw.h_post, bw.d_post, bw.tab_bytes);
+    double *d_tau, *d_ctau;
+    int32_t *d_col, *d_t, *d_u, *d_cu, *d_fin;
+    double* h_tau = pk.take<double>(std::max<size_t>(1, n_ent), &d_tau);
+    double* h_ctau = pk.take<double>(R, &d_ctau);
+    int32_t* h_col = pk.take<int32_t>(std::max<size_t>(1, n_ent), &d_col);
+    int32_t* h_t = pk.take<int32_t>(std::max<size_t>(1, n_ent), &d_t);
+    int32_t* h_u = pk.take<int32_t>(std::max<size_t>(1, n_ent), &d_u);
+    int32_t* h_cu = pk.take<int32_t>(R, &d_cu);
+    int32_t* h_fin = pk.take<int32_t>(R, &d_fin);
+    std::fill(h_ctau, h_ctau + R, 0.0);
+    std::fill(h_cu, h_cu + R, 0);
+    std::fill(h_fin, h_fin + R, 0);
+    size_t e = 0;
+    for (int r : fin) {
+        const BCol& c = cols[r];
+        const int64_t t_b = c.t_a + c.offs.back();
+        for (int32_t q = c.snap0; q < int32_t(tout.size()) && tout[q] <= t_b; ++q, ++e) {
+            h_col[e] = r;
+            h_t[e] = q;
+            h_tau[e] = double(c.offs[q - c.snap0]) * FS;
+            h_u[e] = r * bw.cap + (q - c.snap0);
+        }
+        h_ctau[r] = double(c.offs.back()) * FS;
+        h_cu[r] = r * bw.cap + int32_t(c.offs.size()) - 1;
+        h_fin[r] = 1;
+    }
+    pk.upload(st);
+    launch_b_recon_probes(bw.n, R, n_probe, bw.probe_perm.as<int32_t>(), int(n_ent), d_col, d_t, d_tau, d_u,
+                          bw.u.as<double>(), bw.kst(), bw.Vd(), bw.y0.as<double>(), bw.z1.as<double>(),
+                          bw.z2.as<double>(), bw.Yout.as<double>(), n_out, st);
+    launch_b_recon_full(bw.n, R, d_ctau, d_cu, bw.u.as<double>(), bw.kst(), d_fin, bw.Vd(),
+                        bw.y.as<double>(), bw.y0.as<double>(), bw.z1.as<double>(), bw.z2.as<double>(), st);
+    for (int r : fin) {
+        cols[r].t_a += cols[r].offs.back();
+        S.segments++;
+    }
+}
+
+// Alg. 2 for all subtasks, up to RMAX at a time in lockstep generations: in
+// each generation every unfinished subtask takes one step. Subtasks that
+// ask for different shifts of the ladder run in separate passes (the
+// substitution pair of a pass uses one factor); a subtask's decisions
+// (offsets, shift, step-down, halving) are those of the one-subtask path.
+void transient_batched(const matex_factor_s& F, const matex_problem* p, const matex_run_opts* o,
+                       const std::vector<std::vector<int32_t>>& subtasks, int64_t h_min, double ratio,
+                       bool trace, double* d_probe_out, double* d_final, matex_stats& S, hipStream_t st)
+{
+    const int64_t n = F.sym.n;
+    const int n_shifts = int(F.gammas.size());
+    const int32_t n_out = p->n_out, n_probe = p->n_probe;
+    const int64_t npo = int64_t(n_probe) * n_out;
+    const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
+    const int G = int(subtasks.size());
+    BatchWork bw(F, std::min(RMAX, G), n_out + 1, npo);
+    {
+        std::vector<int32_t> pp(std::max(1, n_probe));
+        for (int32_t k = 0; k < n_probe; ++k) pp[k] = F.sym.iperm[p->probe[k]];
+        bw.probe_perm = upload(pp);
+    }
+    launch_b_fill(npo, F.vdd, d_probe_out, st);
+    if (d_final) launch_b_fill(n, F.vdd, d_final, st);
+    int m_guess = 6;
+    for (int b0 = 0; b0 < G; b0 += RMAX) {
+        const int R = std::min(RMAX, G - b0);
+        std::vector<BCol> cols(R);
+        for (int r = 0; r < R; ++r) {
+            cols[r].spots = plan_spots(p, subtasks[b0 + r], F.sym.iperm);
+            S.subtasks++;
+        }
+        const size_t nr = sizeof(double) * size_t(n) * R;
+        for (DevMem* b : {&bw.y, &bw.y0, &bw.z1, &bw.z2, &bw.s}) HIPCHK(hipMemsetAsync(b->p, 0, nr, st));
+        if (npo) HIPCHK(hipMemsetAsync(bw.Yout.p, 0, sizeof(double) * npo * R, st));
+        while (true) {
+            std::vector<int> act;
+            for (int r = 0; r < R; ++r)
+                if (cols[r].t_a < p->t_end) act.push_back(r);
+            if (act.empty()) break;
+            // new input slopes at transition spots: s += ds, then z1 = G^-1 s
+            // and z2 = G^-1 C z1 for the whole batch (unchanged columns
+            // reproduce their values)
+            size_t cnt = 0;
+            for (int r : act) {
+                const BCol& c = cols[r];
+                if (c.k_spot < c.spots.size() && c.spots[c.k_spot].t == c.t_a) cnt += c.spots[c.k_spot].node.size();
+            }
+            if (cnt > 0) {
+                const size_t need = cnt * (sizeof(double) + 2 * sizeof(int32_t)) + 64;
+                if (need > bw.ev_bytes) {
+                    HIPCHK(hipStreamSynchronize(st));
+                    bw.ev_bytes = need * 2;
+                    bw.h_ev.reset(new PinnedMem(bw.ev_bytes));
+                    bw.d_ev = DevMem(bw.ev_bytes);
+                }
+            }
+            Packer pk(*bw.h_ev, bw.d_ev, bw.ev_bytes);
+            double* d_d;
+            int32_t *d_row, *d_col;
+            double* h_d = pk.take<double>(std::max<size_t>(1, cnt), &d_d);
+            int32_t* h_row = pk.take<int32_t>(std::max<size_t>(1, cnt), &d_row);
+            int32_t* h_col = pk.take<int32_t>(std::max<size_t>(1, cnt), &d_col);
+            size_t e = 0;
+            for (int r : act) {
+                BCol& c = cols[r];
+                if (c.k_spot < c.spots.size() && c.spots[c.k_spot].t == c.t_a) {
+                    const Segment& sg = c.spots[c.k_spot];
+                    for (size_t q = 0; q < sg.node.size(); ++q, ++e) {
+                        h_d[e] = sg.dslope[q];
+                        h_row[e] = sg.node[q];
+                        h_col[e] = r;
+                    }
+                    c.k_spot++;
+                }
+            }
+            if (cnt > 0) {
+                pk.upload(st);
+                launch_b_events(int(cnt), R, d_row, d_col, d_d, bw.s.as<double>(), st);
+                dev_solve_batched(F, n_shifts, R, bw.s.as<double>(), nullptr, bw.z1.as<double>(),
+                                  bw.T.as<double>(), bw.yf.as<double>(), bw.U.as<double>(), st);
+                dev_solve_batched(F, n_shifts, R, bw.z1.as<double>(), F.d_cperm.as<double>(),
+                                  bw.z2.as<double>(), bw.T.as<double>(), bw.yf.as<double>(),
+                                  bw.U.as<double>(), st);
+                S.solve_pairs_g += 2;
+            }
+            // step plans
+            for (int r : act) {
+                BCol& c = cols[r];
+                c.offs = step_offsets(tout, c.t_a, c.spots[c.k_spot].t, &c.snap0);
+                c.ksh = ladder_shift(F.gammas, c.offs[0], ratio);
+                ladder_cut(c.offs, F.gammas, c.ksh);
+            }
+            std::vector<int> pending = act;
+            while (!pending.empty()) {
+                int k = n_shifts;
+                for (int r : pending) k = std::min(k, cols[r].ksh);
+                std::vector<int> grp, rest;
+                for (int r : pending) (cols[r].ksh == k ? grp : rest).push_back(r);
+                std::vector<KsHost> hs = run_pass(F, bw, R, k, grp, cols, o->tol, o->m_max, m_guess, S, st);
+                std::vector<int> fin, halve;
+                for (int r : grp) {
+                    if (hs[r].converged) {
+                        fin.push_back(r);
+                    } else if (k + 1 < n_shifts) {
+                        cols[r].ksh = k + 1;
+                        ladder_cut(cols[r].offs, F.gammas, k + 1);
+                        S.shift_downs++;
+                        rest.push_back(r);
+                    } else {
+                        cols[r].hstep = cols[r].offs.back();
+                        halve.push_back(r);
+                    }
+                }
+                // halve the step with the same basis until the checks pass
+                while (!halve.empty()) {
+                    for (int r : halve) {
+                        BCol& c = cols[r];
+                        c.hstep /= 2;
+                        S.halvings++;
+                        if (c.hstep < h_min)
+                            throw NoConv{"no convergence at t = " + std::to_string(c.t_a) + " fs (subtask " +
+                                         std::to_string(b0 + r) + ")"};
+                        c.cand = halved_offsets(c.offs, c.hstep);
+                    }
+                    CheckTab t = build_checks(bw, R, halve,
+                                              [&](int r) -> const std::vector<int64_t>& { return cols[r].cand; }, st);
+                    launch_b_checks(bw.kst(), F.gammas[k], t.taus, t.off, t.cnt, bw.cap, t.col, t.idx, t.n_chk,
+                                    o->tol, bw.u.as<double>(), bw.est.as<double>(), o->m_max, 0, st);
+                    std::vector<KsHost> hh = read_states(bw, R, st);
+                    std::vector<int> still;
+                    for (int r : halve) {
+                        if (hh[r].converged) {
+                            cols[r].offs = cols[r].cand;
+                            fin.push_back(r);
+                        } else {
+                            still.push_back(r);
+                        }
+                    }
+                    halve.swap(still);
+                }
+                if (trace)
+                    fprintf(stderr, "[matex] batch %d pass shift=%d cols=%zu fin=%zu\n", b0 / RMAX, k, grp.size(),
+                            fin.size());
+                reconstruct(bw, R, fin, cols, tout, n_probe, n_out, S, st);
+                pending.swap(rest);
+            }
+        }
+        launch_b_sum_out(npo, R, bw.Yout.as<double>(), d_probe_out, st);
+        if (d_final) launch_b_sum_final(n, R, F.d_perm.as<int32_t>(), bw.y.as<double>(), d_final, st);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+}
+
 }  // namespace
 
 extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p,
@@ -665,7 +1130,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     if (p->n_src > 0 && (!p->node || !p->amp || !p->delay || !p->rise || !p->width || !p->fall))
         return fail(MATEX_E_INVALID, "null source array");
     if (!p->t_out || (p->n_probe > 0 && !p->probe)) return fail(MATEX_E_INVALID, "null array");
-    if (o->mode != MATEX_PLAIN) return fail(MATEX_E_UNSUPPORTED, "only MATEX_PLAIN is implemented");
+    if (o->mode != MATEX_PLAIN && o->mode != MATEX_BATCHED) return fail(MATEX_E_INVALID, "unknown mode");
     if (o->m_max < 1 || o->m_max > MAXM) return fail(MATEX_E_INVALID, "m_max must be in 1..32");
     if (!(o->tol > 0.0)) return fail(MATEX_E_INVALID, "tol must be > 0");
     const int64_t h_min = std::max<int64_t>(1, o->h_min);
@@ -694,6 +1159,22 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int n_shifts = int(f->gammas.size());
     const int32_t n_out = p->n_out, n_probe = p->n_probe;
+    if (o->mode == MATEX_BATCHED) {
+        std::vector<std::vector<int32_t>> subs;
+        for (auto& g : groups) subs.push_back(g.second);
+        try {
+            transient_batched(*f, p, o, subs, h_min, shift_ratio, trace, d_probe_out, d_final, S, st);
+        } catch (const NoConv& e) {
+            return fail(MATEX_E_NOCONV, e.msg);
+        } catch (const HipError& e) {
+            return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+        } catch (const std::bad_alloc&) {
+            return fail(MATEX_E_OOM, "host allocation failed");
+        }
+        S.seconds = now_s() - t_start;
+        if (stats) *stats = S;
+        return MATEX_OK;
+    }
     try {
         // largest check set: outputs inside one spot interval + 1
         Work wk(*f, int64_t(n_out) + 1);
@@ -754,26 +1235,10 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                     }
                     k_spot++;
                 }
-                const int64_t t_b0 = spots[k_spot].t;   // next spot
-                // check offsets: outputs in (t_a, t_b] and the step end
-                auto lo = std::upper_bound(tout.begin(), tout.end(), t_a);
-                auto hi = std::upper_bound(tout.begin(), tout.end(), t_b0);
-                std::vector<int64_t> offs;
-                for (auto it = lo; it != hi; ++it) offs.push_back(*it - t_a);
-                if (offs.empty() || offs.back() != t_b0 - t_a) offs.push_back(t_b0 - t_a);
-                const int32_t snap0 = int32_t(lo - tout.begin());
-                // shift ladder
-                int ksh = n_shifts - 1;
-                for (int k = 0; k < n_shifts; ++k)
-                    if (double(offs[0]) * FS >= shift_ratio * f->gammas[k]) { ksh = k; break; }
-                auto cut = [&](int k) {
-                    if (k == 0) return;
-                    const double lim = 10.0 * f->gammas[k];
-                    size_t cnt = 0;
-                    while (cnt < offs.size() && double(offs[cnt]) * FS <= lim) cnt++;
-                    offs.resize(std::max<size_t>(1, cnt));
-                };
-                cut(ksh);
+                int32_t snap0 = 0;
+                std::vector<int64_t> offs = step_offsets(tout, t_a, spots[k_spot].t, &snap0);
+                int ksh = ladder_shift(f->gammas, offs[0], shift_ratio);
+                ladder_cut(offs, f->gammas, ksh);
                 KsHost h{};
                 while (true) {
                     std::vector<double> taus(offs.size());
@@ -794,7 +1259,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                     if (h.converged || ksh + 1 == n_shifts) break;
                     ksh++;
                     S.shift_downs++;
-                    cut(ksh);
+                    ladder_cut(offs, f->gammas, ksh);
                 }
                 if (!h.converged) {
                     // halve the step with the same basis until the checks pass
@@ -804,10 +1269,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                         S.halvings++;
                         if (hstep < h_min)
                             return fail(MATEX_E_NOCONV, "no convergence at t = " + std::to_string(t_a) + " fs");
-                        std::vector<int64_t> o2;
-                        for (int64_t v : offs)
-                            if (v < hstep) o2.push_back(v);
-                        o2.push_back(hstep);
+                        std::vector<int64_t> o2 = halved_offsets(offs, hstep);
                         std::vector<double> taus(o2.size());
                         for (size_t q = 0; q < o2.size(); ++q) taus[q] = double(o2[q]) * FS;
                         HIPCHK(hipStreamSynchronize(st));
