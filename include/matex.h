@@ -72,8 +72,10 @@ typedef struct {
 
 typedef struct {
     int32_t n_shifts;        /* shifts gamma_k = gamma * 10^-k, k < n_shifts
-                                (default 4 when 0): one factor of C + gamma_k G
-                                each, plus one of G, all factored once          */
+                                (default 5 when 0; with gamma = 10 ps the
+                                smallest is 1 fs, the time quantum): one
+                                factor of C + gamma_k G each, plus one of G,
+                                all factored once                               */
     int32_t leaf_max;        /* nested-dissection leaf size (default 16 when 0) */
 } matex_factor_opts;
 
@@ -113,6 +115,9 @@ matex_status matex_factor_get_info(matex_factor_t f, matex_factor_info* info);
  * -1 for G. Computes x = A^-1 (diag(scale) b) for nrhs right-hand sides.
  * d_b, d_x: device, n x nrhs column-major (leading dimension n), natural node
  * order; d_scale: device [n] or NULL (no scaling). d_b and d_x may not alias.
+ * nrhs = 1 runs the one-vector sweeps of the plain mode; nrhs > 1 the
+ * multi-right-hand-side sweeps of the batched mode, 64 columns at a time
+ * (this call then synchronises the stream: it frees its staging buffers).
  */
 matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const double* d_b,
                          const double* d_scale, double* d_x, void* stream);
@@ -158,7 +163,7 @@ typedef enum { MATEX_PLAIN = 0, MATEX_BATCHED = 1 } matex_mode;
 typedef struct {
     double tol;              /* per-basis error estimate bound (V), > 0          */
     int32_t m_max;           /* largest Krylov dimension, 1..32                  */
-    int32_t mode;            /* MATEX_PLAIN: subtasks one after another          */
+    int32_t mode;            /* MATEX_PLAIN or MATEX_BATCHED (see below)         */
     int64_t h_min;           /* smallest step after halving (fs), >= 1           */
     double shift_ratio;      /* ladder rule: a step uses the largest gamma_k with
                                 tau_1 >= shift_ratio * gamma_k (0 = default 1.0)  */
@@ -191,7 +196,15 @@ typedef struct {
  * the last check offset <= 10 gamma_k); without convergence at m_max the
  * step is retried one shift lower, and with the smallest shift it is halved
  * down to h_min. Stats may be NULL.
- * Errors: MATEX_E_INVALID, MATEX_E_NOCONV, MATEX_E_UNSUPPORTED (mode),
+ * Modes: MATEX_PLAIN runs the subtasks one after another. MATEX_BATCHED runs
+ * up to 64 subtasks together: in lockstep generations every unfinished
+ * subtask takes one step; subtasks that need the same shift share one
+ * multi-right-hand-side substitution pair per Krylov iteration, and each
+ * keeps its own Gram-Schmidt, checks and step decisions (those of the plain
+ * mode, so both modes take the same steps). In stats, solve_pairs_m and
+ * solve_pairs_g then count multi-right-hand-side pairs; bases, segments and
+ * krylov_dims count per subtask.
+ * Errors: MATEX_E_INVALID (also for an unknown mode), MATEX_E_NOCONV,
  * MATEX_E_OOM, MATEX_E_HIP.
  */
 matex_status matex_transient(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
@@ -211,12 +224,14 @@ matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex
  * matex_time_solves - `reps` substitution pairs (Alg. 1, U \ (L \ (C v)))
  * with factor `which` (as in matex_solve), back to back on `stream`, on
  * library-owned device vectors, timed with HIP events recorded on that
- * stream around the batch. Writes the mean seconds per pair to *seconds and
+ * stream around the batch. nrhs = 1 times the one-vector sweeps of the plain
+ * mode; nrhs in 2..64 the multi-right-hand-side sweeps of the batched mode
+ * (nrhs subtasks per pair). Writes the mean seconds per pair to *seconds and
  * the algorithmic bytes of one pair (panel values and indices read once per
- * sweep, plus the vectors) to *bytes. For measurement only.
+ * sweep, plus nrhs times the vectors) to *bytes. For measurement only.
  */
-matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t reps, double* seconds,
-                               double* bytes, void* stream);
+matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t nrhs, int32_t reps,
+                               double* seconds, double* bytes, void* stream);
 
 /* Copies the calling thread's last error text (NUL-terminated) into buf. */
 size_t matex_last_error(char* buf, size_t len);

@@ -136,7 +136,7 @@ class Stats:
 class RMatex:
     """Factors C + gamma G and G once (Alg. 2, LU_Decompose before the loop)."""
 
-    def __init__(self, netlist, gamma: float, n_shifts: int = 4):
+    def __init__(self, netlist, gamma: float, n_shifts: int = 5):
         self.nl = netlist
         self.n = netlist.n
         self.gammas = [gamma * 10.0 ** (-k) for k in range(n_shifts)]

@@ -37,127 +37,260 @@ constexpr int NVB = MAXM + 1;
 
 // ------------------------------------------------------------- sweeps
 
-__global__ __launch_bounds__(256) void kb_assemble(DevSym s, const int32_t* __restrict__ list,
-                                                   int R, const double* __restrict__ B,
-                                                   const double* __restrict__ scale, double* T,
-                                                   double* U)
+// Forward assembly of one level (pull form): btilde rows of the level's
+// supernodes and the seeds of their update slots from the children's slots.
+// Lane = subtask, one panel position per wavefront.
+__global__ __launch_bounds__(256) void kb_gather(int npos, int R, const int32_t* __restrict__ dst,
+                                                 const int32_t* __restrict__ cptr,
+                                                 const int32_t* __restrict__ cidx,
+                                                 const double* __restrict__ B,
+                                                 const double* __restrict__ scale, double* T,
+                                                 double* U)
 {
-    const int sn = list[blockIdx.x];
+    const int r = threadIdx.x & 63;
+    if (r >= R) return;
+    for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < npos; g += gridDim.x * 4) {
+        double acc = 0.0;
+        const int c1 = cptr[g + 1];
+        for (int c = cptr[g]; c < c1; ++c) acc += U[int64_t(cidx[c]) * R + r];
+        const int d = dst[g];
+        if (d >= 0) {
+            const int64_t o = int64_t(d) * R + r;
+            T[o] = (scale ? B[o] * scale[d] : B[o]) - acc;
+        } else {
+            U[int64_t(-d - 1) * R + r] = acc;
+        }
+    }
+}
+
+// Stage width of the sweep products and the padded LDS row (breaks bank
+// conflicts of the transposed panel store).
+constexpr int BK = 16;
+constexpr int LROW = RMAX + 2;
+
+// Rows first .. first + 63 of [y_s ; delta_s] for one supernode: the 64 x K
+// panel block times the K x R block of btilde over the task's panel
+// columns [kb, ke) (blocks of diagonal rows stop at their last row: the
+// panel is zero above its diagonal). 16 x 16 threads, each with a 4-row x
+// 4-subtask register tile; panel and right-hand-side stages of BK columns go
+// through LDS with coalesced loads (a panel column's rows are contiguous),
+// the next stage loaded into registers while the current one is used.
+__global__ __launch_bounds__(256) void kb_fwd(DevSym s, const BTask* __restrict__ tasks, int R,
+                                              const double* __restrict__ W, const double* T,
+                                              double* y, double* U, double* P)
+{
+    __shared__ double Ws[BK][LROW];
+    __shared__ double Ts[BK][LROW];
+    const BTask t = tasks[blockIdx.x];
+    const int sn = t.sn, r0 = t.first, kb = t.kb, ke = t.ke;
+    const int c0 = s.c0[sn], nr = s.nr[sn];
+    const int64_t ld = dpanel_ld(nr);
+    const double* Wp = W + s.w[sn];
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    double acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    double wr[4], tr[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + q * 256, kk = idx >> 6, e = idx & 63;
+            const int k = k0 + kk, row = r0 + e;
+            wr[q] = (k < ke && row < nr) ? Wp[int64_t(k) * ld + row] : 0.0;
+            tr[q] = (k < ke && e < R) ? T[int64_t(c0 + k) * R + e] : 0.0;
+        }
+    };
+    load(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + q * 256, kk = idx >> 6, e = idx & 63;
+            Ws[kk][e] = wr[q];
+            Ts[kk][e] = tr[q];
+        }
+        __syncthreads();
+        if (k0 + BK < ke) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = Ws[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Ts[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
+        }
+        __syncthreads();
+    }
+    if (t.slot >= 0) {
+        double* Pp = P + int64_t(t.slot) * PSLOT;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Pp[(ty * 4 + i) * 64 + tx * 4 + j] = acc[i][j];
+        return;
+    }
+    const int nc = s.nc[sn];
+    const int64_t u = s.u[sn];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int row = r0 + ty * 4 + i;
+        if (row >= nr) break;
+        double* dst = row < nc ? y + int64_t(c0 + row) * R : U + (u + row - nc) * R;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = tx * 4 + j;
+            if (r < R) {
+                if (row < nc) dst[r] = acc[i][j];
+                else dst[r] += acc[i][j];
+            }
+        }
+    }
+}
+
+// Sums the partial slots of split forward blocks, in slot order.
+__global__ __launch_bounds__(256) void kb_fwd_reduce(DevSym s, const BRed* __restrict__ items, int R,
+                                                     const double* __restrict__ P, double* y,
+                                                     double* U)
+{
+    const BRed it = items[blockIdx.x];
+    const int sn = it.sn;
     const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
     const int64_t u = s.u[sn];
-    for (int idx = threadIdx.x; idx < nc * R; idx += 256) {
-        const int k = idx / R, r = idx - (idx / R) * R;
-        const int64_t o = int64_t(c0 + k) * R + r;
-        T[o] = scale ? B[o] * scale[c0 + k] : B[o];
-    }
-    for (int idx = threadIdx.x; idx < (nr - nc) * R; idx += 256) U[u * R + idx] = 0.0;
-    __syncthreads();
-    const int cp1 = s.child_ptr[sn + 1];
-    for (int cp = s.child_ptr[sn]; cp < cp1; ++cp) {
-        const int c = s.child_idx[cp];
-        const int64_t uc = s.u[c];
-        const int noc = s.nr[c] - s.nc[c];
-        for (int idx = threadIdx.x; idx < noc * R; idx += 256) {
-            const int q = idx / R, r = idx - (idx / R) * R;
-            const int pos = s.relidx[uc + q];
-            const double val = U[(uc + q) * R + r];
-            if (pos < nc) T[int64_t(c0 + pos) * R + r] -= val;
-            else U[(u + pos - nc) * R + r] += val;
-        }
-        __syncthreads();
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+        const int e = idx >> 6, r = idx & 63, row = it.first + e;
+        if (r >= R || row >= nr) continue;
+        double sum = 0.0;
+        for (int c = 0; c < it.cnt; ++c) sum += P[int64_t(it.slot + c) * PSLOT + idx];
+        if (row < nc) y[int64_t(c0 + row) * R + r] = sum;
+        else U[(u + row - nc) * R + r] += sum;
     }
 }
 
-__global__ __launch_bounds__(256) void kb_fwd(DevSym s, const int32_t* __restrict__ tsn,
-                                              const int32_t* __restrict__ tfirst, int R,
-                                              const double* __restrict__ W, const double* T,
-                                              double* y, double* U)
-{
-    __shared__ double tile[BKT][RMAX];
-    const int sn = tsn[blockIdx.x], r0 = tfirst[blockIdx.x];
-    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
-    const int ld = dpanel_ld(nr);
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int rbase = __builtin_amdgcn_readfirstlane(r0 + wv * 16);
-    const double* Ws = W + s.w[sn];
-    double acc[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
-    const int kend = min(nc, r0 + BR);   // diagonal rows need k <= row
-    for (int kt = 0; kt < kend; kt += BKT) {
-        const int kn = min(BKT, kend - kt);
-        for (int idx = threadIdx.x; idx < kn * RMAX; idx += 256) {
-            const int kk = idx / RMAX, r = idx - (idx / RMAX) * RMAX;
-            tile[kk][r] = r < R ? T[int64_t(c0 + kt + kk) * R + r] : 0.0;
-        }
-        __syncthreads();
-        for (int kk = 0; kk < kn; ++kk) {
-            const int k = kt + kk;
-            const double tv = tile[kk][lane];
-            const double* wk = Ws + int64_t(k) * ld + rbase;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int row = rbase + i;
-                if (row < nr && (row >= nc || k <= row)) acc[i] += wk[i] * tv;
-            }
-        }
-        __syncthreads();
-    }
-    if (lane < R) {
-        const int64_t u = s.u[sn];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int row = rbase + i;
-            if (row >= nr) break;
-            if (row < nc) y[int64_t(c0 + row) * R + lane] = acc[i];
-            else U[(u + row - nc) * R + lane] += acc[i];
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void kb_bwd(DevSym s, const int32_t* __restrict__ tsn,
-                                              const int32_t* __restrict__ tfirst, int R,
+// Columns first .. first + 63 of x_s for one supernode: W_s^T [y_s ; -x_off]
+// over the task's panel rows [kb, ke) (the panel is zero above its
+// diagonal). Panel stages are read as 16-entry column pieces (one 128-byte
+// line each) and stored transposed in LDS; next stage prefetched as above.
+__global__ __launch_bounds__(256) void kb_bwd(DevSym s, const BTask* __restrict__ tasks, int R,
                                               const double* __restrict__ W, const double* y,
-                                              double* x)
+                                              double* x, double* P)
 {
-    __shared__ double tile[BKT][RMAX];
-    const int sn = tsn[blockIdx.x], col0 = tfirst[blockIdx.x];
+    __shared__ double Ws[BK][LROW];
+    __shared__ double Gs[BK][LROW];
+    const BTask t = tasks[blockIdx.x];
+    const int sn = t.sn, col0 = t.first, kb = t.kb, ke = t.ke;
     const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
-    const int ld = dpanel_ld(nr);
+    const int64_t ld = dpanel_ld(nr);
     const int32_t* roff = s.rows + s.roff[sn];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int cbase = __builtin_amdgcn_readfirstlane(col0 + wv * 16);
-    const double* Ws = W + s.w[sn];
-    double acc[16];
+    const double* Wp = W + s.w[sn];
+    const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+    double acc[4][4];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0;
-    for (int kt = col0; kt < nr; kt += BKT) {
-        const int kn = min(BKT, nr - kt);
-        for (int idx = threadIdx.x; idx < kn * RMAX; idx += 256) {
-            const int kk = idx / RMAX, r = idx - (idx / RMAX) * RMAX;
-            const int k = kt + kk;
-            double g = 0.0;
-            if (r < R) g = k < nc ? y[int64_t(c0 + k) * R + r] : -x[int64_t(roff[k - nc]) * R + r];
-            tile[kk][r] = g;
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
+    double wr[4], gr[4];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + q * 256;
+            {
+                const int cc = idx >> 4, kk = idx & (BK - 1);
+                const int c = col0 + cc, k = k0 + kk;
+                wr[q] = (c < nc && k < ke) ? Wp[int64_t(c) * ld + k] : 0.0;
+            }
+            {
+                const int kk = idx >> 6, r = idx & 63;
+                const int k = k0 + kk;
+                double g = 0.0;
+                if (k < ke && r < R)
+                    g = k < nc ? y[int64_t(c0 + k) * R + r] : -x[int64_t(roff[k - nc]) * R + r];
+                gr[q] = g;
+            }
+        }
+    };
+    load(kb);
+    for (int k0 = kb; k0 < ke; k0 += BK) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int idx = tid + q * 256;
+            Ws[idx & (BK - 1)][idx >> 4] = wr[q];
+            Gs[idx >> 6][idx & 63] = gr[q];
         }
         __syncthreads();
-        for (int kk = 0; kk < kn; ++kk) {
-            const int k = kt + kk;
-            const double gv = tile[kk][lane];
+        if (k0 + BK < ke) load(k0 + BK);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                const int c = cbase + i;
-                if (c < nc && k >= c) acc[i] += Ws[int64_t(c) * ld + k] * gv;
-            }
+        for (int kk = 0; kk < BK; ++kk) {
+            double a[4], b[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = Ws[kk][ty * 4 + i];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) b[j] = Gs[kk][tx * 4 + j];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) acc[i][j] += a[i] * b[j];
         }
         __syncthreads();
     }
-    if (lane < R) {
+    if (t.slot >= 0) {
+        double* Pp = P + int64_t(t.slot) * PSLOT;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int c = cbase + i;
-            if (c < nc) x[int64_t(c0 + c) * R + lane] = acc[i];
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) Pp[(ty * 4 + i) * 64 + tx * 4 + j] = acc[i][j];
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int c = col0 + ty * 4 + i;
+        if (c >= nc) break;
+        double* dst = x + int64_t(c0 + c) * R;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int r = tx * 4 + j;
+            if (r < R) dst[r] = acc[i][j];
         }
+    }
+}
+
+__global__ __launch_bounds__(256) void kb_bwd_reduce(DevSym s, const BRed* __restrict__ items, int R,
+                                                     const double* __restrict__ P, double* x)
+{
+    const BRed it = items[blockIdx.x];
+    const int sn = it.sn;
+    const int c0 = s.c0[sn], nc = s.nc[sn];
+    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
+        const int e = idx >> 6, r = idx & 63, c = it.first + e;
+        if (r >= R || c >= nc) continue;
+        double sum = 0.0;
+        for (int q = 0; q < it.cnt; ++q) sum += P[int64_t(it.slot + q) * PSLOT + idx];
+        x[int64_t(c0 + c) * R + r] = sum;
+    }
+}
+
+// Column-major natural-order right-hand sides (ld n) to row-interleaved
+// permuted order and back: dst[k * R + r] = src[perm[k] + r * n] and
+// dst[perm[k] + r * n] = src[k * R + r].
+__global__ void kb_interleave(int64_t n, int R, const int32_t* perm, const double* src, double* dst)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n * R; i += int64_t(gridDim.x) * 256) {
+        const int64_t k = i / R;
+        const int r = int(i - k * R);
+        dst[i] = src[perm[k] + int64_t(r) * n];
+    }
+}
+
+__global__ void kb_deinterleave(int64_t n, int R, const int32_t* perm, const double* src, double* dst)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n * R; i += int64_t(gridDim.x) * 256) {
+        const int64_t k = i / R;
+        const int r = int(i - k * R);
+        dst[perm[k] + int64_t(r) * n] = src[i];
     }
 }
 
@@ -482,16 +615,19 @@ inline int grid_rows(int64_t n, int per_block) { return int(std::min<int64_t>((n
 
 void launch_b_forward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
                       const double* B, const double* scale, double* T, double* y, double* U,
-                      hipStream_t st)
+                      double* P, hipStream_t st)
 {
-    kb_assemble<<<lv.n_sn, 256, 0, st>>>(s, lv.sn_list, R, B, scale, T, U);
-    kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, lv.fwd_sn, lv.fwd_first, R, W, T, y, U);
+    kb_gather<<<grid_rows(lv.n_pos, 4), 256, 0, st>>>(lv.n_pos, R, lv.g_dst, lv.g_cptr, lv.g_cidx, B, scale,
+                                                       T, U);
+    kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, lv.fwd, R, W, T, y, U, P);
+    if (lv.n_fred) kb_fwd_reduce<<<lv.n_fred, 256, 0, st>>>(s, lv.fred, R, P, y, U);
 }
 
 void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
-                       const double* y, double* x, hipStream_t st)
+                       const double* y, double* x, double* P, hipStream_t st)
 {
-    kb_bwd<<<lv.n_bwd, 256, 0, st>>>(s, lv.bwd_sn, lv.bwd_first, R, W, y, x);
+    kb_bwd<<<lv.n_bwd, 256, 0, st>>>(s, lv.bwd, R, W, y, x, P);
+    if (lv.n_bred) kb_bwd_reduce<<<lv.n_bred, 256, 0, st>>>(s, lv.bred, R, P, x);
 }
 
 void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial, KState* ks,
@@ -565,6 +701,18 @@ void launch_b_sum_final(int64_t n, int R, const int32_t* perm, const double* y, 
                         hipStream_t st)
 {
     kb_sum_final<<<grid_rows(n, 256), 256, 0, st>>>(n, R, perm, y, out);
+}
+
+void launch_b_interleave(int64_t n, int R, const int32_t* perm, const double* src, double* dst,
+                         hipStream_t st)
+{
+    kb_interleave<<<grid_rows(n * R, 256), 256, 0, st>>>(n, R, perm, src, dst);
+}
+
+void launch_b_deinterleave(int64_t n, int R, const int32_t* perm, const double* src, double* dst,
+                           hipStream_t st)
+{
+    kb_deinterleave<<<grid_rows(n * R, 256), 256, 0, st>>>(n, R, perm, src, dst);
 }
 
 void launch_b_fill(int64_t count, double v, double* x, hipStream_t st)

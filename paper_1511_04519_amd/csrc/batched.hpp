@@ -11,28 +11,51 @@ namespace matex {
 
 constexpr int RMAX = 64;           // subtasks per batch (one wavefront lane each)
 constexpr int BR = 64;             // panel rows / columns per batched sweep task
-constexpr int BKT = 32;            // LDS tile of the right-hand sides (rows)
 constexpr int B_RED_BLOCKS = 4096; // blocks of the batched reductions
+
+constexpr int KCHUNK = 256;        // panel columns (forward) / rows (backward) per task
+constexpr int PSLOT = 64 * RMAX;   // doubles of one partial-result slot (64 x RMAX)
+
+// One block of a batched sweep: panel rows (forward) or columns (backward)
+// first .. first + 63 of supernode sn, over the panel columns / rows
+// [kb, ke). slot < 0: the task owns the whole range and writes its result;
+// otherwise it writes a partial result to slot `slot` of the partial buffer.
+struct BTask {
+    int32_t sn, first, kb, ke, slot;
+};
+// Sum of the cnt partial slots slot .. slot + cnt - 1 of one 64-row/column block.
+struct BRed {
+    int32_t sn, first, slot, cnt;
+};
 
 // One level of the batched sweeps.
 struct BatchLevel {
-    const int32_t* sn_list;   // supernodes of the level (assembly)
-    int32_t n_sn;
-    const int32_t* fwd_sn;    // forward tasks: 64 panel rows each
-    const int32_t* fwd_first;
+    // forward assembly: one entry per panel position of the level's
+    // supernodes. dst >= 0: diagonal row dst (btilde = scale * b - sum);
+    // dst < 0: update slot -dst - 1 (= sum). The sum runs over the children's
+    // update slots cidx[cptr[g] .. cptr[g + 1]) in a fixed order.
+    const int32_t* g_dst;
+    const int32_t* g_cptr;
+    const int32_t* g_cidx;
+    int32_t n_pos;
+    const BTask* fwd;
     int32_t n_fwd;
-    const int32_t* bwd_sn;    // backward tasks: 64 panel columns each
-    const int32_t* bwd_first;
+    const BRed* fred;
+    int32_t n_fred;
+    const BTask* bwd;
     int32_t n_bwd;
+    const BRed* bred;
+    int32_t n_bred;
 };
 
 // Multi-right-hand-side pair, all n x R arrays row-interleaved (x[i * R + r]).
-// T (n x R) and U (n_upd x R) are scratch; y is the forward result.
+// T (n x R) and U (n_upd x R) are scratch; y is the forward result; P holds
+// the partial results of split tasks (PSLOT doubles per slot).
 void launch_b_forward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
                       const double* B, const double* scale, double* T, double* y, double* U,
-                      hipStream_t st);
+                      double* P, hipStream_t st);
 void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
-                       const double* y, double* x, hipStream_t st);
+                       const double* y, double* x, double* P, hipStream_t st);
 // Two classical Gram-Schmidt passes for every subtask not yet done; V holds
 // MAXM + 1 blocks of n x R. partial: B_RED_BLOCKS * R * (MAXM + 2) doubles.
 void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial, KState* ks,
@@ -62,5 +85,11 @@ void launch_b_sum_out(int64_t count, int R, const double* Yout, double* out, hip
 void launch_b_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double* out,
                         hipStream_t st);
 void launch_b_fill(int64_t count, double v, double* x, hipStream_t st);
+// Column-major natural order (leading dimension n) <-> row-interleaved
+// permuted order for R right-hand sides.
+void launch_b_interleave(int64_t n, int R, const int32_t* perm, const double* src, double* dst,
+                         hipStream_t st);
+void launch_b_deinterleave(int64_t n, int R, const int32_t* perm, const double* src, double* dst,
+                           hipStream_t st);
 
 }  // namespace matex

@@ -111,10 +111,21 @@ struct matex_factor_s {
     int sweep_blocks = 0;
     bool use_levels = false;
     // batched (multi-subtask) sweeps
-    DevMem d_b_list, d_b_fsn, d_b_ffirst, d_b_bsn, d_b_bfirst;
+    DevMem d_b_dst, d_b_cptr, d_b_cidx, d_b_ft, d_b_fr, d_b_bt, d_b_br;
     std::vector<BatchLevel> blevels;
+    int64_t b_slots = 0;   // partial-result slots one batched sweep needs
     DevSym dsym{};
     matex_factor_info info{};
+    int64_t held_bytes() const {
+        int64_t b = 0;
+        for (const DevMem* m : {&d_c0, &d_nc, &d_nr, &d_roff, &d_w, &d_u, &d_rows, &d_child_ptr, &d_child_idx,
+                                &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_fwd_sn, &d_fwd_first, &d_bwd_sn,
+                                &d_bwd_first, &d_task_sn, &d_task_first, &d_dep_ptr, &d_dep_idx, &d_b_dst,
+                                &d_b_cptr, &d_b_cidx, &d_b_ft, &d_b_fr, &d_b_bt, &d_b_br})
+            b += int64_t(m->bytes);
+        for (const DevMem& m : d_W) b += int64_t(m.bytes);
+        return b;
+    }
 };
 
 namespace {
@@ -157,33 +168,80 @@ void build_tasks(matex_factor_s& F)
         F.fwd.push_back(f);
         F.bwd.push_back(b);
     }
-    // batched sweeps: per level, the supernodes, 64-row forward tasks and
-    // 64-column backward tasks
+    // batched sweeps, per level: the assembly positions with their
+    // contributing child slots (inverse of relidx), forward blocks of 64 panel
+    // rows and backward blocks of 64 panel columns, each split into tasks of
+    // at most KCHUNK panel columns / rows whose partial results are summed
     {
-        std::vector<int32_t> lst, fsn2, ff2, bsn2, bf2;
-        std::vector<int64_t> lo(s.n_levels + 1), fo(s.n_levels + 1), bo(s.n_levels + 1);
-        for (int lv = 0; lv < s.n_levels; ++lv) {
-            lo[lv] = int64_t(lst.size()); fo[lv] = int64_t(fsn2.size()); bo[lv] = int64_t(bsn2.size());
+        const int L = s.n_levels;
+        std::vector<int32_t> dst, cptr{0}, cidx;
+        std::vector<BTask> ft, bt;
+        std::vector<BRed> fr, br;
+        std::vector<int64_t> po(L + 1), fo(L + 1), fro(L + 1), bo(L + 1), bro(L + 1);
+        std::vector<std::vector<int32_t>> contrib;
+        for (int lv = 0; lv < L; ++lv) {
+            po[lv] = int64_t(dst.size()); fo[lv] = int64_t(ft.size()); fro[lv] = int64_t(fr.size());
+            bo[lv] = int64_t(bt.size()); bro[lv] = int64_t(br.size());
+            int32_t fslots = 0, bslots = 0;
             for (int32_t k : s.level_sn[lv]) {
-                lst.push_back(k);
-                for (int32_t r = 0; r < s.sn[k].nr; r += BR) { fsn2.push_back(k); ff2.push_back(r); }
-                for (int32_t c = 0; c < s.sn[k].nc; c += BR) { bsn2.push_back(k); bf2.push_back(c); }
+                const Supernode& q = s.sn[k];
+                contrib.assign(q.nr, {});
+                for (int32_t cp = s.child_ptr[k]; cp < s.child_ptr[k + 1]; ++cp) {
+                    const Supernode& c = s.sn[s.child_idx[cp]];
+                    for (int32_t t = 0; t < c.nr - c.nc; ++t)
+                        contrib[s.relidx[c.u + t]].push_back(int32_t(c.u + t));
+                }
+                for (int32_t p = 0; p < q.nr; ++p) {
+                    dst.push_back(p < q.nc ? q.c0 + p : -int32_t(q.u + p - q.nc) - 1);
+                    cidx.insert(cidx.end(), contrib[p].begin(), contrib[p].end());
+                    cptr.push_back(int32_t(cidx.size()));
+                }
+                for (int32_t r0 = 0; r0 < q.nr; r0 += BR) {
+                    const int32_t K = std::min(q.nc, r0 + BR);
+                    const int32_t nch = (K + KCHUNK - 1) / KCHUNK;
+                    if (nch == 1) {
+                        ft.push_back({k, r0, 0, K, -1});
+                    } else {
+                        fr.push_back({k, r0, fslots, nch});
+                        for (int32_t c = 0; c < nch; ++c)
+                            ft.push_back({k, r0, c * KCHUNK, std::min(K, (c + 1) * KCHUNK), fslots++});
+                    }
+                }
+                for (int32_t c0 = 0; c0 < q.nc; c0 += BR) {
+                    const int32_t nch = (q.nr - c0 + KCHUNK - 1) / KCHUNK;
+                    if (nch == 1) {
+                        bt.push_back({k, c0, c0, q.nr, -1});
+                    } else {
+                        br.push_back({k, c0, bslots, nch});
+                        for (int32_t c = 0; c < nch; ++c)
+                            bt.push_back({k, c0, c0 + c * KCHUNK, std::min(q.nr, c0 + (c + 1) * KCHUNK),
+                                          bslots++});
+                    }
+                }
             }
+            F.b_slots = std::max<int64_t>(F.b_slots, std::max(fslots, bslots));
         }
-        lo[s.n_levels] = int64_t(lst.size()); fo[s.n_levels] = int64_t(fsn2.size());
-        bo[s.n_levels] = int64_t(bsn2.size());
-        F.d_b_list = upload(lst); F.d_b_fsn = upload(fsn2); F.d_b_ffirst = upload(ff2);
-        F.d_b_bsn = upload(bsn2); F.d_b_bfirst = upload(bf2);
-        for (int lv = 0; lv < s.n_levels; ++lv) {
+        po[L] = int64_t(dst.size()); fo[L] = int64_t(ft.size()); fro[L] = int64_t(fr.size());
+        bo[L] = int64_t(bt.size()); bro[L] = int64_t(br.size());
+        if (cidx.empty()) cidx.push_back(0);
+        if (fr.empty()) fr.push_back({0, 0, 0, 0});
+        if (br.empty()) br.push_back({0, 0, 0, 0});
+        F.d_b_dst = upload(dst); F.d_b_cptr = upload(cptr); F.d_b_cidx = upload(cidx);
+        F.d_b_ft = upload(ft); F.d_b_fr = upload(fr); F.d_b_bt = upload(bt); F.d_b_br = upload(br);
+        for (int lv = 0; lv < L; ++lv) {
             BatchLevel b;
-            b.sn_list = F.d_b_list.as<int32_t>() + lo[lv];
-            b.n_sn = int32_t(lo[lv + 1] - lo[lv]);
-            b.fwd_sn = F.d_b_fsn.as<int32_t>() + fo[lv];
-            b.fwd_first = F.d_b_ffirst.as<int32_t>() + fo[lv];
+            b.g_dst = F.d_b_dst.as<int32_t>() + po[lv];
+            b.g_cptr = F.d_b_cptr.as<int32_t>() + po[lv];
+            b.g_cidx = F.d_b_cidx.as<int32_t>();
+            b.n_pos = int32_t(po[lv + 1] - po[lv]);
+            b.fwd = F.d_b_ft.as<BTask>() + fo[lv];
             b.n_fwd = int32_t(fo[lv + 1] - fo[lv]);
-            b.bwd_sn = F.d_b_bsn.as<int32_t>() + bo[lv];
-            b.bwd_first = F.d_b_bfirst.as<int32_t>() + bo[lv];
+            b.fred = F.d_b_fr.as<BRed>() + fro[lv];
+            b.n_fred = int32_t(fro[lv + 1] - fro[lv]);
+            b.bwd = F.d_b_bt.as<BTask>() + bo[lv];
             b.n_bwd = int32_t(bo[lv + 1] - bo[lv]);
+            b.bred = F.d_b_br.as<BRed>() + bro[lv];
+            b.n_bred = int32_t(bro[lv + 1] - bro[lv]);
             F.blevels.push_back(b);
         }
     }
@@ -278,14 +336,34 @@ void dev_solve(const matex_factor_s& F, int which, const double* b, const double
 
 // Multi-subtask pair: x = A_which^-1 (scale .* B) for R row-interleaved
 // right-hand sides (n x R). T, yf: n x R scratch; U: n_upd x R scratch.
+// P: F.b_slots * PSLOT doubles of partial results.
 void dev_solve_batched(const matex_factor_s& F, int which, int R, const double* B,
-                       const double* scale, double* x, double* T, double* yf, double* U,
+                       const double* scale, double* x, double* T, double* yf, double* U, double* P,
                        hipStream_t st)
 {
     const double* W = F.d_W[which].as<double>();
     const int L = F.sym.n_levels;
-    for (int lv = 0; lv < L; ++lv) launch_b_forward(F.dsym, F.blevels[lv], R, W, B, scale, T, yf, U, st);
-    for (int lv = L - 1; lv >= 0; --lv) launch_b_backward(F.dsym, F.blevels[lv], R, W, yf, x, st);
+    for (int lv = 0; lv < L; ++lv) launch_b_forward(F.dsym, F.blevels[lv], R, W, B, scale, T, yf, U, P, st);
+    for (int lv = L - 1; lv >= 0; --lv) launch_b_backward(F.dsym, F.blevels[lv], R, W, yf, x, P, st);
+}
+
+// Scratch of one batched pair.
+struct BatchScratch {
+    DevMem T, yf, U, P;
+    BatchScratch(const matex_factor_s& F, int R) {
+        const size_t nr = sizeof(double) * size_t(F.sym.n) * R;
+        T = DevMem(nr);
+        yf = DevMem(nr);
+        U = DevMem(sizeof(double) * std::max<int64_t>(1, F.sym.n_upd) * R);
+        P = DevMem(sizeof(double) * std::max<int64_t>(1, F.b_slots) * PSLOT);
+    }
+};
+
+void dev_solve_batched(const matex_factor_s& F, int which, int R, const double* B,
+                       const double* scale, double* x, const BatchScratch& sc, hipStream_t st)
+{
+    dev_solve_batched(F, which, R, B, scale, x, sc.T.as<double>(), sc.yf.as<double>(), sc.U.as<double>(),
+                      sc.P.as<double>(), st);
 }
 
 // Raises if a one-launch sweep gave up waiting (reads the error word).
@@ -386,6 +464,15 @@ int64_t solve_pair_bytes(const Symbolic& s, bool scaled)
            int64_t(s.rows.size()) * 4;
 }
 
+// The same for a pair on R row-interleaved right-hand sides: the panels, the
+// scale and the index lists once, every vector term R times.
+int64_t solve_pair_bytes_batched(const Symbolic& s, bool scaled, int R)
+{
+    const int64_t vec = 8 * s.n;
+    return 2 * 8 * s.nnz_l + int64_t(R) * (4 * vec + s.n_upd * (8 + 8)) + (scaled ? vec : 0) +
+           s.n_upd * 4 + int64_t(s.rows.size()) * 4;
+}
+
 }  // namespace
 
 // --------------------------------------------------------------------- ABI
@@ -428,7 +515,7 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         if (nl->pad_node[k] < 0 || nl->pad_node[k] >= n) return fail(MATEX_E_INVALID, "pad node id");
         if (!(nl->pad_g[k] > 0.0)) return fail(MATEX_E_INVALID, "pad conductance must be > 0");
     }
-    int n_shifts = (opts && opts->n_shifts > 0) ? opts->n_shifts : 4;
+    int n_shifts = (opts && opts->n_shifts > 0) ? opts->n_shifts : 5;
     int leaf = (opts && opts->leaf_max > 0) ? opts->leaf_max : 16;
     if (n_shifts > 12) return fail(MATEX_E_INVALID, "n_shifts must be <= 12");
     try {
@@ -501,9 +588,7 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         I.gamma = gamma;
         I.seconds_analyse = t1 - t0;
         I.seconds_numeric = t2 - t1;
-        I.device_bytes = int64_t(sizeof(double)) * s.n_w * (n_shifts + 1) +
-                         int64_t(sizeof(int32_t)) * (s.relidx.size() + s.child_idx.size() +
-                                                     s.rows.size() + 3 * n);
+        I.device_bytes = F->held_bytes();
         *out = F.release();
         return MATEX_OK;
     } catch (const HipError& e) {
@@ -546,6 +631,22 @@ matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const do
             launch_gather_perm(n, f->d_perm.as<int32_t>(), d_scale, sc.as<double>(), n, n, 1, st);
             scale_p = sc.as<double>();
         }
+        if (nrhs > 1) {
+            // multi-right-hand-side sweeps, RMAX columns at a time
+            const int Rm = std::min<int>(RMAX, nrhs);
+            const size_t nr = sizeof(double) * size_t(n) * Rm;
+            DevMem Bi(nr), Xi(nr);
+            BatchScratch bs(*f, Rm);
+            for (int r0 = 0; r0 < nrhs; r0 += RMAX) {
+                const int R = std::min<int>(RMAX, nrhs - r0);
+                launch_b_interleave(n, R, f->d_perm.as<int32_t>(), d_b + int64_t(r0) * n, Bi.as<double>(), st);
+                dev_solve_batched(*f, idx, R, Bi.as<double>(), scale_p, Xi.as<double>(), bs, st);
+                launch_b_deinterleave(n, R, f->d_perm.as<int32_t>(), Xi.as<double>(), d_x + int64_t(r0) * n,
+                                      st);
+            }
+            HIPCHK(hipStreamSynchronize(st));
+            return MATEX_OK;
+        }
         for (int r = 0; r < nrhs; ++r) {
             launch_gather_perm(n, f->d_perm.as<int32_t>(), d_b + int64_t(r) * n, bp.as<double>(), n,
                                n, 1, st);
@@ -562,15 +663,43 @@ matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const do
     }
 }
 
-matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t reps, double* seconds,
-                               double* bytes, void* stream)
+matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t nrhs, int32_t reps,
+                               double* seconds, double* bytes, void* stream)
 {
     if (!f || !seconds || !bytes || reps <= 0) return fail(MATEX_E_INVALID, "bad argument");
+    if (nrhs < 1 || nrhs > RMAX) return fail(MATEX_E_INVALID, "nrhs must be in 1..64");
     const int n_shifts = int(f->gammas.size());
     if (which < -1 || which >= n_shifts) return fail(MATEX_E_INVALID, "factor index out of range");
     const int idx = which < 0 ? n_shifts : which;
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = f->sym.n;
+    if (nrhs > 1) {
+        try {
+            const size_t nr = sizeof(double) * size_t(n) * nrhs;
+            DevMem b(nr), x(nr);
+            BatchScratch bs(*f, nrhs);
+            HIPCHK(hipMemsetAsync(b.p, 0, b.bytes, st));
+            const double* sc = idx < n_shifts ? f->d_cperm.as<double>() : nullptr;
+            auto pair = [&]() { dev_solve_batched(*f, idx, nrhs, b.as<double>(), sc, x.as<double>(), bs, st); };
+            pair();   // warm
+            hipEvent_t e0, e1;
+            HIPCHK(hipEventCreate(&e0));
+            HIPCHK(hipEventCreate(&e1));
+            HIPCHK(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) pair();
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            *seconds = 1e-3 * double(ms) / reps;
+            *bytes = double(solve_pair_bytes_batched(f->sym, idx < n_shifts, nrhs));
+            return MATEX_OK;
+        } catch (const HipError& e) {
+            return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+        }
+    }
     try {
         DevMem b(sizeof(double) * n), x(sizeof(double) * n), tmp(sizeof(double) * n),
             upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd));
@@ -785,7 +914,8 @@ struct BCol {
 struct BatchWork {
     int64_t n;
     int Rmax, cap;
-    DevMem V, w, T, yf, U, partial, ks, y, y0, z1, z2, s, u, est, Yout, probe_perm;
+    DevMem V, w, partial, ks, y, y0, z1, z2, s, u, est, Yout, probe_perm;
+    BatchScratch sc;
     size_t tab_bytes, ev_bytes;
     PinnedMem h_pre, h_post, h_ks;
     DevMem d_pre, d_post;
@@ -796,14 +926,13 @@ struct BatchWork {
         return e * (2 * sizeof(double) + 3 * sizeof(int32_t)) + size_t(R) * 8 * sizeof(double) + 16 * 16;
     }
     BatchWork(const matex_factor_s& F, int Rmax_, int cap_, int64_t n_po)
-        : n(F.sym.n), Rmax(Rmax_), cap(cap_), tab_bytes(table_bytes(Rmax_, cap_)), ev_bytes(1 << 16),
-          h_pre(tab_bytes), h_post(tab_bytes), h_ks(sizeof(KState) * RMAX)
+        : n(F.sym.n), Rmax(Rmax_), cap(cap_), sc(F, Rmax_), tab_bytes(table_bytes(Rmax_, cap_)),
+          ev_bytes(1 << 16), h_pre(tab_bytes), h_post(tab_bytes), h_ks(sizeof(KState) * RMAX)
     {
         const size_t nr = sizeof(double) * size_t(n) * Rmax;
         V = DevMem(nr * (MAXM + 1));
         HIPCHK(hipMemset(V.p, 0, V.bytes));
-        w = DevMem(nr); T = DevMem(nr); yf = DevMem(nr);
-        U = DevMem(sizeof(double) * std::max<int64_t>(1, F.sym.n_upd) * Rmax);
+        w = DevMem(nr);
         partial = DevMem(sizeof(double) * size_t(B_RED_BLOCKS) * Rmax * (MAXM + 2));
         ks = DevMem(sizeof(KState) * Rmax);
         HIPCHK(hipMemset(ks.p, 0, ks.bytes));
@@ -893,7 +1022,7 @@ std::vector<KsHost> run_pass(const matex_factor_s& F, BatchWork& bw, int R, int 
         const int stop = std::min(m_max, j + chunk);
         for (; j < stop; ++j) {
             dev_solve_batched(F, k, R, V + int64_t(j) * n * R, F.d_cperm.as<double>(), bw.w.as<double>(),
-                              bw.T.as<double>(), bw.yf.as<double>(), bw.U.as<double>(), st);
+                              bw.sc, st);
             launch_b_gs(n, R, V, j + 1, bw.w.as<double>(), bw.partial.as<double>(), bw.kst(), st);
             launch_b_checks(bw.kst(), F.gammas[k], t.taus, t.off, t.cnt, bw.cap, t.col, t.idx, t.n_chk, tol,
                             bw.u.as<double>(), bw.est.as<double>(), m_max, 1, st);
@@ -1041,11 +1170,9 @@ void transient_batched(const matex_factor_s& F, const matex_problem* p, const ma
             if (cnt > 0) {
                 pk.upload(st);
                 launch_b_events(int(cnt), R, d_row, d_col, d_d, bw.s.as<double>(), st);
-                dev_solve_batched(F, n_shifts, R, bw.s.as<double>(), nullptr, bw.z1.as<double>(),
-                                  bw.T.as<double>(), bw.yf.as<double>(), bw.U.as<double>(), st);
+                dev_solve_batched(F, n_shifts, R, bw.s.as<double>(), nullptr, bw.z1.as<double>(), bw.sc, st);
                 dev_solve_batched(F, n_shifts, R, bw.z1.as<double>(), F.d_cperm.as<double>(),
-                                  bw.z2.as<double>(), bw.T.as<double>(), bw.yf.as<double>(),
-                                  bw.U.as<double>(), st);
+                                  bw.z2.as<double>(), bw.sc, st);
                 S.solve_pairs_g += 2;
             }
             // step plans
@@ -1256,6 +1383,10 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                     S.krylov_dims += h.m;
                     S.m_peak = std::max(S.m_peak, h.m);
                     if (h.m > 0) m_guess = h.m;
+                    if (trace && !h.converged)
+                        fprintf(stderr, "[matex] not converged t_a=%lld shift=%d m=%d est=%.3e checks=%zu first=%lld last=%lld\n",
+                                (long long)t_a, ksh, h.m, read_est(wk, hest, st), offs.size(),
+                                (long long)offs[0], (long long)offs.back());
                     if (h.converged || ksh + 1 == n_shifts) break;
                     ksh++;
                     S.shift_downs++;
@@ -1279,6 +1410,9 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                         launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), int(taus.size()),
                                       o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
                         KsHost hh = read_state(wk, hks, st);
+                        if (trace)
+                            fprintf(stderr, "[matex] halving t_a=%lld step=%lld est=%.3e\n", (long long)t_a,
+                                    (long long)hstep, read_est(wk, hest, st));
                         if (hh.converged) { offs = o2; break; }
                     }
                 }

@@ -93,7 +93,7 @@ def lib():
                                       _vp, ctypes.POINTER(Stats), _vp]
         L.matex_adjoint.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(RunOpts), _vp,
                                     _vp, _vp, _vp]
-        L.matex_time_solves.argtypes = [_vp, _i32, _i32, _pf64, _pf64, _vp]
+        L.matex_time_solves.argtypes = [_vp, _i32, _i32, _i32, _pf64, _pf64, _vp]
         L.matex_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.matex_last_error.restype = ctypes.c_size_t
         L.matex_version.restype = ctypes.c_char_p
@@ -154,7 +154,7 @@ class FactorHandle:
             self.handle = None
 
 
-def matex_factor(netlist, gamma: float, n_shifts: int = 4, leaf_max: int = 16,
+def matex_factor(netlist, gamma: float, n_shifts: int = 5, leaf_max: int = 16,
                  use_coords: bool = True) -> FactorHandle:
     """Factor C + gamma_k G for the shift ladder and G (see matex.h)."""
     a = np.ascontiguousarray(netlist.br_a, np.int32)
@@ -239,13 +239,13 @@ def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
     return out, fin, st.as_dict()
 
 
-def matex_time_solves(f: FactorHandle, which: int = 0, reps: int = 50):
-    """Mean seconds of one substitution pair (event-timed on the current
-    stream) and its algorithmic bytes."""
+def matex_time_solves(f: FactorHandle, which: int = 0, reps: int = 50, nrhs: int = 1):
+    """Mean seconds of one substitution pair on nrhs right-hand sides
+    (event-timed on the current stream) and its algorithmic bytes."""
     sec = ctypes.c_double()
     byt = ctypes.c_double()
-    _check(lib().matex_time_solves(f.handle, which, reps, ctypes.byref(sec), ctypes.byref(byt),
-                                   _stream()))
+    _check(lib().matex_time_solves(f.handle, which, nrhs, reps, ctypes.byref(sec),
+                                   ctypes.byref(byt), _stream()))
     return sec.value, byt.value
 
 

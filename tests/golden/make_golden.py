@@ -7,7 +7,7 @@ stored so a test can tell that it rebuilt the same instance.
   config1_head.npz  the 2x300x300 workload (180k nodes, 2000 sources) over
                     its first 500 ps: x at the 512 probe rows for t = 0..500 ps
                     every 10 ps, and x(500 ps) at every node. Oracle R-MATEX,
-                    tol 1e-13 (every basis) with the 4-shift ladder.
+                    tol 1e-13 (every basis) with the 5-shift ladder.
   config1_mid.npz   the same workload around 3 ns, where transition spots are
                     densest: x at the probes for t in [2.9, 3.0] ns. The oracle
                     starts at 2.6 ns from the quasi-static state G^-1 i(2.6 ns);

@@ -29,11 +29,7 @@ def _note(msg):
 
 # ------------------------------------------------------------------- solve
 
-@pytest.mark.parametrize("which", [-1, 0, 1, 3])
-@pytest.mark.parametrize("case", ["config0", "2x13x11", "3x9x20"])
-def test_solve_pair_matches_oracle(case, which):
-    """One forward/backward substitution pair (Alg. 1) on G or C + gamma_k G."""
-    _note(f"solve {case} which={which}")
+def _solve_case(case, which, nrhs, seed=11):
     if case == "config0":
         p = I.config0()
     else:
@@ -41,8 +37,8 @@ def test_solve_pair_matches_oracle(case, which):
         p = I.small(7, layers=L, nx=nx, ny=ny, n_src=3)
     nl = p.netlist
     F = M.matex_factor(nl, GAMMA, n_shifts=4)
-    rng = np.random.default_rng(11)
-    b = rng.standard_normal((3, nl.n))
+    rng = np.random.default_rng(seed)
+    b = rng.standard_normal((nrhs, nl.n))
     rp, ci, gv = C.assemble_G(nl)
     if which < 0:
         vals, scale = gv, None
@@ -50,9 +46,42 @@ def test_solve_pair_matches_oracle(case, which):
         vals = C.csr_add_diag(rp, ci, gv, nl.c_node, alpha=GAMMA * 10.0 ** (-which))
         scale = nl.c_node
     ref = C.Cholesky(rp, ci, vals).solve((b * (scale if scale is not None else 1.0)).T).T
-    x = M.matex_solve(F, which, _dev(b), _dev(scale) if scale is not None else None)
-    x = x.cpu().numpy()
+    return F, b, scale, ref
+
+
+@pytest.mark.parametrize("which", [-1, 0, 1, 3])
+@pytest.mark.parametrize("case", ["config0", "2x13x11", "3x9x20"])
+def test_solve_pair_matches_oracle(case, which):
+    """One forward/backward substitution pair (Alg. 1) on G or C + gamma_k G:
+    the one-vector sweeps (each right-hand side alone) and the
+    multi-right-hand-side sweeps (all three together)."""
+    _note(f"solve {case} which={which}")
+    F, b, scale, ref = _solve_case(case, which, 3)
+    sc = _dev(scale) if scale is not None else None
+    for r in range(3):
+        x = M.matex_solve(F, which, _dev(b[r]), sc).cpu().numpy()
+        assert np.abs(x - ref[r]).max() <= 1e-12 * np.abs(ref[r]).max()
+    x = M.matex_solve(F, which, _dev(b), sc).cpu().numpy()
     assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("case,which,nrhs", [
+    ("2x70x55", 0, 64),     # separators wider than one 64-row / 64-column task
+    ("2x70x55", -1, 70),    # two column groups: 64 + 6
+    ("3x41x90", 2, 17),
+    ("1x150x9", 0, 5),      # long thin strip: deep tree
+])
+def test_multi_rhs_solve_large_supernodes(case, which, nrhs):
+    _note(f"multi-rhs solve {case} which={which} nrhs={nrhs}")
+    F, b, scale, ref = _solve_case(case, which, nrhs, seed=12)
+    assert F.info["max_nr"] > 64 or case == "1x150x9"
+    x = M.matex_solve(F, which, _dev(b), _dev(scale) if scale is not None else None).cpu().numpy()
+    err = np.abs(x - ref).max(axis=1) / np.abs(ref).max(axis=1)
+    assert err.max() <= 1e-12, err.max()
+    # the one-vector sweeps on one of the columns agree as well
+    x1 = M.matex_solve(F, which, _dev(b[nrhs - 1]),
+                       _dev(scale) if scale is not None else None).cpu().numpy()
+    assert np.abs(x1 - ref[nrhs - 1]).max() <= 1e-12 * np.abs(ref[nrhs - 1]).max()
 
 
 # ------------------------------------------------------------ krylov step
