@@ -5,15 +5,14 @@
 // a wavefront owns subtask r.
 //
 //  * Multi-right-hand-side substitution pair (Alg. 1's step, for all
-//    subtasks at once). Forward, per level: kb_assemble forms
-//    btilde_s = b_s - (children's updates) for every subtask and seeds the
-//    supernode's update slots with the children's off-row contributions;
-//    kb_fwd then computes [y_s ; delta_s] += W_s * btilde_s, 64 panel rows per
-//    block (16 per wavefront), the panel entry W[row, k] being the same for
-//    all lanes (one scalar load feeds 64 subtasks) and btilde staged in LDS
-//    tiles. Backward, per level: kb_bwd computes x_s = W_s^T [y_s ; -x_off],
-//    64 panel columns per block. Each panel entry is read once per sweep for
-//    all R subtasks.
+//    subtasks at once), one or two launches per level and sweep. Forward:
+//    kb_fwd computes [y_s ; delta_s] = W_s * btilde_s for 64 panel rows per
+//    block as a dense 64 x K by K x R product staged through LDS, assembling
+//    btilde_s = b_s - (children's updates) while staging it; supernodes with
+//    many columns are split over blocks whose partial products kb_fwd_reduce
+//    sums in a fixed order. Backward: kb_bwd computes x_s = W_s^T [y_s ;
+//    -x_off] for 64 panel columns per block, split the same way. Each panel
+//    entry is read once per sweep for all R subtasks.
 //  * Gram-Schmidt per subtask (two classical passes): 256-thread blocks
 //    (lane = subtask, four wavefronts on interleaved rows) write per-block
 //    partial sums per subtask; kb_col_reduce (one block per subtask) sums
@@ -37,53 +36,43 @@ constexpr int NVB = MAXM + 1;
 
 // ------------------------------------------------------------- sweeps
 
-// Forward assembly of one level (pull form): btilde rows of the level's
-// supernodes and the seeds of their update slots from the children's slots.
-// Lane = subtask, one panel position per wavefront.
-__global__ __launch_bounds__(256) void kb_gather(int npos, int R, const int32_t* __restrict__ dst,
-                                                 const int32_t* __restrict__ cptr,
-                                                 const int32_t* __restrict__ cidx,
-                                                 const double* __restrict__ B,
-                                                 const double* __restrict__ scale, double* T,
-                                                 double* U)
-{
-    const int r = threadIdx.x & 63;
-    if (r >= R) return;
-    for (int g = blockIdx.x * 4 + (threadIdx.x >> 6); g < npos; g += gridDim.x * 4) {
-        double acc = 0.0;
-        const int c1 = cptr[g + 1];
-        for (int c = cptr[g]; c < c1; ++c) acc += U[int64_t(cidx[c]) * R + r];
-        const int d = dst[g];
-        if (d >= 0) {
-            const int64_t o = int64_t(d) * R + r;
-            T[o] = (scale ? B[o] * scale[d] : B[o]) - acc;
-        } else {
-            U[int64_t(-d - 1) * R + r] = acc;
-        }
-    }
-}
-
 // Stage width of the sweep products and the padded LDS row (breaks bank
 // conflicts of the transposed panel store).
 constexpr int BK = 16;
 constexpr int LROW = RMAX + 2;
 
+// Sum of the children's update slots that land on panel position g.
+__device__ inline double pull(const BatchAssembly& as, int g, int R, int r, const double* U)
+{
+    double acc = 0.0;
+    const int c1 = as.cptr[g + 1];
+    for (int c = as.cptr[g]; c < c1; ++c) acc += U[int64_t(as.cidx[c]) * R + r];
+    return acc;
+}
+
 // Rows first .. first + 63 of [y_s ; delta_s] for one supernode: the 64 x K
 // panel block times the K x R block of btilde over the task's panel
 // columns [kb, ke) (blocks of diagonal rows stop at their last row: the
-// panel is zero above its diagonal). 16 x 16 threads, each with a 4-row x
-// 4-subtask register tile; panel and right-hand-side stages of BK columns go
-// through LDS with coalesced loads (a panel column's rows are contiguous),
-// the next stage loaded into registers while the current one is used.
-__global__ __launch_bounds__(256) void kb_fwd(DevSym s, const BTask* __restrict__ tasks, int R,
-                                              const double* __restrict__ W, const double* T,
-                                              double* y, double* U, double* P)
+// panel is zero above its diagonal). btilde is assembled while it is staged
+// (scale * b minus the children's updates), and an off-diagonal row's
+// update slot gets the children's updates plus the product. 16 x 16
+// threads, each with a 4-row x 4-subtask register tile; panel and
+// right-hand-side stages of BK columns go through LDS with coalesced loads
+// (a panel column's rows are contiguous), the next stage loaded into
+// registers while the current one is used.
+__global__ __launch_bounds__(256) void kb_fwd(DevSym s, BatchAssembly as,
+                                              const BTask* __restrict__ tasks, int R,
+                                              const double* __restrict__ W,
+                                              const double* __restrict__ B,
+                                              const double* __restrict__ scale, double* y,
+                                              double* U, double* P)
 {
     __shared__ double Ws[BK][LROW];
     __shared__ double Ts[BK][LROW];
     const BTask t = tasks[blockIdx.x];
     const int sn = t.sn, r0 = t.first, kb = t.kb, ke = t.ke;
     const int c0 = s.c0[sn], nr = s.nr[sn];
+    const int pb = as.pos_base[sn];
     const int64_t ld = dpanel_ld(nr);
     const double* Wp = W + s.w[sn];
     const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
@@ -99,7 +88,12 @@ __global__ __launch_bounds__(256) void kb_fwd(DevSym s, const BTask* __restrict_
             const int idx = tid + q * 256, kk = idx >> 6, e = idx & 63;
             const int k = k0 + kk, row = r0 + e;
             wr[q] = (k < ke && row < nr) ? Wp[int64_t(k) * ld + row] : 0.0;
-            tr[q] = (k < ke && e < R) ? T[int64_t(c0 + k) * R + e] : 0.0;
+            double b = 0.0;
+            if (k < ke && e < R) {
+                const int64_t o = int64_t(c0 + k) * R + e;
+                b = (scale ? B[o] * scale[c0 + k] : B[o]) - pull(as, pb + k, R, e, U);
+            }
+            tr[q] = b;
         }
     };
     load(kb);
@@ -140,34 +134,36 @@ __global__ __launch_bounds__(256) void kb_fwd(DevSym s, const BTask* __restrict_
     for (int i = 0; i < 4; ++i) {
         const int row = r0 + ty * 4 + i;
         if (row >= nr) break;
-        double* dst = row < nc ? y + int64_t(c0 + row) * R : U + (u + row - nc) * R;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int r = tx * 4 + j;
             if (r < R) {
-                if (row < nc) dst[r] = acc[i][j];
-                else dst[r] += acc[i][j];
+                if (row < nc) y[int64_t(c0 + row) * R + r] = acc[i][j];
+                else U[(u + row - nc) * R + r] = pull(as, pb + row, R, r, U) + acc[i][j];
             }
         }
     }
 }
 
-// Sums the partial slots of split forward blocks, in slot order.
-__global__ __launch_bounds__(256) void kb_fwd_reduce(DevSym s, const BRed* __restrict__ items, int R,
+// Sums the partial slots of split forward blocks, in slot order (an
+// off-diagonal row adds the children's updates first).
+__global__ __launch_bounds__(256) void kb_fwd_reduce(DevSym s, BatchAssembly as,
+                                                     const BRed* __restrict__ items, int R,
                                                      const double* __restrict__ P, double* y,
                                                      double* U)
 {
     const BRed it = items[blockIdx.x];
     const int sn = it.sn;
     const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    const int pb = as.pos_base[sn];
     const int64_t u = s.u[sn];
     for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
         const int e = idx >> 6, r = idx & 63, row = it.first + e;
         if (r >= R || row >= nr) continue;
-        double sum = 0.0;
+        double sum = row < nc ? 0.0 : pull(as, pb + row, R, r, U);
         for (int c = 0; c < it.cnt; ++c) sum += P[int64_t(it.slot + c) * PSLOT + idx];
         if (row < nc) y[int64_t(c0 + row) * R + r] = sum;
-        else U[(u + row - nc) * R + r] += sum;
+        else U[(u + row - nc) * R + r] = sum;
     }
 }
 
@@ -327,71 +323,69 @@ __device__ inline void combine_waves(double (&acc)[N], int cnt, double* buf)
     }
 }
 
-// Pass 1: per-block partial dots V_i^T w per subtask, i < nv, into
-// partial[(block * R + r) * (NVB + 1) + i]. Lane = subtask, the block's four
-// wavefronts take interleaved rows.
+// Dots of a chunk of up to GS_CHUNK basis vectors with w, per subtask:
+// partial[(block * R + r) * (NVB + 1) + i] for i in the chunk (blockIdx.y),
+// and with `norm`, ||w||^2 into slot nv (chunk 0). Lane = subtask, the
+// block's four wavefronts take interleaved rows.
+constexpr int GS_CHUNK = 16;
+
 __global__ __launch_bounds__(256) void kb_gs_dots(int64_t n, int R, const double* __restrict__ V,
                                                   int nv, const double* __restrict__ w,
-                                                  double* partial, const KState* ks)
+                                                  double* partial, const KState* ks, int norm)
 {
-    __shared__ double buf[2 * NVB * 64];
+    __shared__ double buf[2 * (GS_CHUNK + 1) * 64];
     const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i0 = blockIdx.y * GS_CHUNK;
+    const int cnt = min(GS_CHUNK, nv - i0);
+    const bool with_norm = norm && blockIdx.y == 0;
     const bool on = r < R && !ks[r < R ? r : 0].done;
-    double acc[NVB];
+    double acc[GS_CHUNK + 1];
 #pragma unroll
-    for (int i = 0; i < NVB; ++i) acc[i] = 0.0;
+    for (int i = 0; i <= GS_CHUNK; ++i) acc[i] = 0.0;
     if (on) {
+        const double* Vc = V + int64_t(i0) * n * R;
         for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
             const double wr = w[row * R + r];
 #pragma unroll
-            for (int i = 0; i < NVB; ++i)
-                if (i < nv) acc[i] += wr * V[int64_t(i) * n * R + row * R + r];
+            for (int i = 0; i < GS_CHUNK; ++i)
+                if (i < cnt) acc[i] += wr * Vc[int64_t(i) * n * R + row * R + r];
+            if (with_norm) acc[GS_CHUNK] += wr * wr;
         }
     }
-    combine_waves(acc, nv, buf);
+    combine_waves(acc, GS_CHUNK + 1, buf);
     if (wv == 0 && r < R) {
         double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
 #pragma unroll
-        for (int i = 0; i < NVB; ++i)
-            if (i < nv) out[i] = acc[i];
+        for (int i = 0; i < GS_CHUNK; ++i)
+            if (i < cnt) out[i0 + i] = acc[i];
+        if (with_norm) out[nv] = acc[GS_CHUNK];
     }
 }
 
-// Pass 2: w' = w - V h1 (h1 per subtask from its state), partial dots
-// V^T w' and ||w'||^2 (slot nv; nv <= MAXM so it fits NVB slots).
-__global__ __launch_bounds__(256) void kb_gs_update(int64_t n, int R, const double* __restrict__ V,
-                                                    int nv, double* w, double* partial,
-                                                    const KState* ks)
+// out = (w - sum_i h[i] V_i) * sc per subtask, h = h1 (mode 0, sc = 1, out
+// = w in place) or h2 (mode 1, sc = vscale, out = V_nv). The coefficients
+// sit in LDS, so a row needs only its nv basis values in flight.
+__global__ __launch_bounds__(256) void kb_gs_axpy(int64_t n, int R, double* V, int nv, double* w,
+                                                  const KState* ks, int mode)
 {
-    __shared__ double buf[2 * NVB * 64];
+    __shared__ double hs[NVB][64];
     const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const bool on = r < R && !ks[r < R ? r : 0].done;
-    double h[NVB];
-#pragma unroll
-    for (int i = 0; i < NVB; ++i) h[i] = (on && i < nv) ? ks[r].h1[i] : 0.0;
-    double acc[NVB];
-#pragma unroll
-    for (int i = 0; i < NVB; ++i) acc[i] = 0.0;
-    if (on) {
-        for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
-            double wr = w[row * R + r];
-#pragma unroll
-            for (int i = 0; i < NVB; ++i)
-                if (i < nv) wr -= h[i] * V[int64_t(i) * n * R + row * R + r];
-            w[row * R + r] = wr;
-#pragma unroll
-            for (int i = 0; i < NVB; ++i) {
-                if (i < nv) acc[i] += wr * V[int64_t(i) * n * R + row * R + r];
-                else if (i == nv) acc[i] += wr * wr;
-            }
-        }
+    for (int idx = threadIdx.x; idx < NVB * 64; idx += 256) {
+        const int i = idx >> 6, q = idx & 63;
+        double h = 0.0;
+        if (q < R && i < nv) h = mode == 0 ? ks[q].h1[i] : ks[q].h2[i];
+        hs[i][q] = h;
     }
-    combine_waves(acc, nv + 1, buf);
-    if (wv == 0 && r < R) {
-        double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
+    __syncthreads();
+    if (r >= R || ks[r].done) return;
+    const double sc = mode == 0 ? 1.0 : ks[r].vscale;
+    double* out = mode == 0 ? w : V + int64_t(nv) * n * R;
+    for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
+        double wr = w[row * R + r];
 #pragma unroll
         for (int i = 0; i < NVB; ++i)
-            if (i <= nv) out[i] = acc[i];
+            if (i < nv) wr -= hs[i][r] * V[int64_t(i) * n * R + row * R + r];
+        out[row * R + r] = wr * sc;
     }
 }
 
@@ -455,45 +449,36 @@ __global__ __launch_bounds__(256) void kb_col_reduce(int R, int nblk, const doub
     }
 }
 
-// v_{j+1} = (w' - V h2) * vscale per subtask.
-__global__ __launch_bounds__(256) void kb_gs_finish(int64_t n, int R, double* V, int nv,
-                                                    const double* __restrict__ w,
-                                                    const KState* ks)
-{
-    const int r = threadIdx.x & 63;
-    if (r >= R || ks[r].done) return;
-    double h[NVB];
-#pragma unroll
-    for (int i = 0; i < NVB; ++i) h[i] = i < nv ? ks[r].h2[i] : 0.0;
-    const double sc = ks[r].vscale;
-    double* vout = V + int64_t(nv) * n * R;
-    for (int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); row < n; row += int64_t(gridDim.x) * 4) {
-        double wr = w[row * R + r];
-#pragma unroll
-        for (int i = 0; i < NVB; ++i)
-            if (i < nv) wr -= h[i] * V[int64_t(i) * n * R + row * R + r];
-        vout[row * R + r] = wr * sc;
-    }
-}
-
 // -------------------------------------------------------------- checks
 
-// blocks: (subtask chk_col[b], check chk_idx[b]); the subtask's offsets are
-// taus[tau_off[r] .. + tau_cnt[r]], its u vectors and estimates sit in its
-// fixed region of `cap` checks (u_buf + r * cap * MAXM, est_buf + r * cap).
+// blocks: (subtask chk_col[b], check chk_idx[b]); subtask r's blocks are
+// chk_idx[col_off[r] .. + col_cnt[r]], its offsets taus[tau_off[r] ..], its u
+// vectors and estimates sit in its fixed region of `cap` checks
+// (u_buf + r * cap * MAXM, est_buf + r * cap).
 __global__ __launch_bounds__(256) void kb_checks(KState* ks, double gamma, const double* taus,
-                                                 const int32_t* tau_off, const int32_t* tau_cnt,
-                                                 int cap, const int32_t* chk_col,
-                                                 const int32_t* chk_idx, double tol, double* u_buf,
-                                                 double* est_buf, int m_max, int update_state)
+                                                 const int32_t* tau_off, int cap,
+                                                 const int32_t* chk_col, const int32_t* chk_idx,
+                                                 const int32_t* col_off, const int32_t* col_cnt,
+                                                 double tol, double* u_buf, double* est_buf,
+                                                 int m_max, int update_state)
 {
     const int r = chk_col[blockIdx.x], c = chk_idx[blockIdx.x];
     KState* k = ks + r;
     if (update_state && k->done) return;
     extern __shared__ double sm[];
     const int64_t reg = int64_t(r) * cap;
-    check_block(k, gamma, taus + tau_off[r], c, tau_cnt[r], tol, u_buf + reg * MAXM, est_buf + reg,
-                m_max, update_state, sm);
+    check_block(k, gamma, taus + tau_off[r], c, chk_idx + col_off[r], col_cnt[r], tol, u_buf + reg * MAXM,
+                est_buf + reg, m_max, update_state, sm);
+}
+
+// Lets the listed subtasks continue iterating.
+__global__ void kb_resume(KState* ks, const int32_t* cols, int cnt)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < cnt) {
+        ks[cols[k]].done = 0;
+        ks[cols[k]].converged = 0;
+    }
 }
 
 // ---------------------------------------------------- set-up and outputs
@@ -613,14 +598,12 @@ inline int grid_rows(int64_t n, int per_block) { return int(std::min<int64_t>((n
 
 }  // namespace
 
-void launch_b_forward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
-                      const double* B, const double* scale, double* T, double* y, double* U,
-                      double* P, hipStream_t st)
+void launch_b_forward(const DevSym& s, const BatchAssembly& as, const BatchLevel& lv, int R,
+                      const double* W, const double* B, const double* scale, double* y,
+                      double* U, double* P, hipStream_t st)
 {
-    kb_gather<<<grid_rows(lv.n_pos, 4), 256, 0, st>>>(lv.n_pos, R, lv.g_dst, lv.g_cptr, lv.g_cidx, B, scale,
-                                                       T, U);
-    kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, lv.fwd, R, W, T, y, U, P);
-    if (lv.n_fred) kb_fwd_reduce<<<lv.n_fred, 256, 0, st>>>(s, lv.fred, R, P, y, U);
+    kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, as, lv.fwd, R, W, B, scale, y, U, P);
+    if (lv.n_fred) kb_fwd_reduce<<<lv.n_fred, 256, 0, st>>>(s, as, lv.fred, R, P, y, U);
 }
 
 void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
@@ -635,22 +618,30 @@ void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial
 {
     const int nb = B_RED_BLOCKS;
     const int stride = NVB + 1;
-    kb_gs_dots<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
+    const dim3 gd(nb, (nv + GS_CHUNK - 1) / GS_CHUNK);
+    kb_gs_dots<<<gd, 256, 0, st>>>(n, R, V, nv, w, partial, ks, 0);
     kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 0, ks, nullptr);
-    kb_gs_update<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
+    kb_gs_axpy<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks, 0);
+    kb_gs_dots<<<gd, 256, 0, st>>>(n, R, V, nv, w, partial, ks, 1);
     kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 1, ks, nullptr);
-    kb_gs_finish<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks);
+    kb_gs_axpy<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks, 1);
 }
 
-void launch_b_checks(KState* ks, double gamma, const double* taus, const int32_t* tau_off,
-                     const int32_t* tau_cnt, int cap, const int32_t* chk_col,
-                     const int32_t* chk_idx, int n_chk, double tol, double* u_buf, double* est_buf,
+void launch_b_checks(KState* ks, double gamma, const double* taus, const int32_t* tau_off, int cap,
+                     const int32_t* chk_col, const int32_t* chk_idx, const int32_t* col_off,
+                     const int32_t* col_cnt, int n_chk, double tol, double* u_buf, double* est_buf,
                      int m_max, int update_state, hipStream_t st)
 {
     if (n_chk <= 0) return;
-    kb_checks<<<n_chk, 256, checks_lds_bytes(), st>>>(ks, gamma, taus, tau_off, tau_cnt, cap, chk_col,
-                                                      chk_idx, tol, u_buf, est_buf, m_max,
+    kb_checks<<<n_chk, 256, checks_lds_bytes(), st>>>(ks, gamma, taus, tau_off, cap, chk_col, chk_idx,
+                                                      col_off, col_cnt, tol, u_buf, est_buf, m_max,
                                                       update_state);
+}
+
+void launch_b_resume(KState* ks, const int32_t* cols, int cnt, hipStream_t st)
+{
+    if (cnt <= 0) return;
+    kb_resume<<<(cnt + 63) / 64, 64, 0, st>>>(ks, cols, cnt);
 }
 
 void launch_b_setup(int64_t n, int R, const double* y, const double* y0, const double* z2,

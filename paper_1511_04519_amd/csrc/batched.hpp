@@ -28,16 +28,19 @@ struct BRed {
     int32_t sn, first, slot, cnt;
 };
 
+// Forward assembly (pull form), shared by all levels: panel position p of
+// supernode s has global index pos_base[s] + p; its sum runs over the
+// children's update slots cidx[cptr[g] .. cptr[g + 1]) in a fixed order. A
+// diagonal position's btilde is scale * b minus that sum; an off-diagonal
+// position's update slot is that sum plus the supernode's own product.
+struct BatchAssembly {
+    const int32_t* pos_base;
+    const int32_t* cptr;
+    const int32_t* cidx;
+};
+
 // One level of the batched sweeps.
 struct BatchLevel {
-    // forward assembly: one entry per panel position of the level's
-    // supernodes. dst >= 0: diagonal row dst (btilde = scale * b - sum);
-    // dst < 0: update slot -dst - 1 (= sum). The sum runs over the children's
-    // update slots cidx[cptr[g] .. cptr[g + 1]) in a fixed order.
-    const int32_t* g_dst;
-    const int32_t* g_cptr;
-    const int32_t* g_cidx;
-    int32_t n_pos;
     const BTask* fwd;
     int32_t n_fwd;
     const BRed* fred;
@@ -49,24 +52,28 @@ struct BatchLevel {
 };
 
 // Multi-right-hand-side pair, all n x R arrays row-interleaved (x[i * R + r]).
-// T (n x R) and U (n_upd x R) are scratch; y is the forward result; P holds
-// the partial results of split tasks (PSLOT doubles per slot).
-void launch_b_forward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
-                      const double* B, const double* scale, double* T, double* y, double* U,
-                      double* P, hipStream_t st);
+// U (n_upd x R) is scratch; y is the forward result; P holds the partial
+// results of split tasks (PSLOT doubles per slot).
+void launch_b_forward(const DevSym& s, const BatchAssembly& as, const BatchLevel& lv, int R,
+                      const double* W, const double* B, const double* scale, double* y,
+                      double* U, double* P, hipStream_t st);
 void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
                        const double* y, double* x, double* P, hipStream_t st);
 // Two classical Gram-Schmidt passes for every subtask not yet done; V holds
 // MAXM + 1 blocks of n x R. partial: B_RED_BLOCKS * R * (MAXM + 2) doubles.
 void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial, KState* ks,
                  hipStream_t st);
-// Estimates for the blocks (chk_col[b], chk_idx[b]); subtask r's offsets are
-// taus[tau_off[r] ..][tau_cnt[r]], its u vectors and estimates live in its
-// region of `cap` checks. update_state as for the single-subtask checks.
-void launch_b_checks(KState* ks, double gamma, const double* taus, const int32_t* tau_off,
-                     const int32_t* tau_cnt, int cap, const int32_t* chk_col,
-                     const int32_t* chk_idx, int n_chk, double tol, double* u_buf, double* est_buf,
+// Estimates for the blocks (chk_col[b], chk_idx[b]); subtask r's blocks are
+// chk_idx[col_off[r] .. + col_cnt[r]] (the checks its decision takes the
+// maximum over), its offsets taus[tau_off[r] ..], its u vectors and
+// estimates live in its region of `cap` checks. update_state as for the
+// single-subtask checks.
+void launch_b_checks(KState* ks, double gamma, const double* taus, const int32_t* tau_off, int cap,
+                     const int32_t* chk_col, const int32_t* chk_idx, const int32_t* col_off,
+                     const int32_t* col_cnt, int n_chk, double tol, double* u_buf, double* est_buf,
                      int m_max, int update_state, hipStream_t st);
+// Lets the subtasks cols[0 .. cnt) continue iterating.
+void launch_b_resume(KState* ks, const int32_t* cols, int cnt, hipStream_t st);
 void launch_b_setup(int64_t n, int R, const double* y, const double* y0, const double* z2,
                     double* V, double* partial, KState* ks, const int32_t* active, hipStream_t st);
 void launch_b_recon_probes(int64_t n, int R, int n_probe, const int32_t* probe_perm, int n_ent,

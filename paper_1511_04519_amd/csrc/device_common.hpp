@@ -258,13 +258,15 @@ __device__ inline void expm_e1(double* H, int m, double tau, double* buf, double
 
 // One check offset of one Krylov process (block-wide): H_m from Ht, u =
 // e^{tau H_m} e1 into u_buf[c], the estimate into est_buf[c]; the last of
-// the process's n_tau blocks takes the maximum and decides. update_state:
-// iterating (u_buf[c] holds the previous dimension's vector and the decision
-// may end the process) or only evaluating a new check set on a fixed basis.
+// the n_sel blocks of the process takes the maximum over the checked
+// offsets (sel[0 .. n_sel), or 0 .. n_sel - 1 when sel is null) and decides.
+// update_state: iterating (u_buf[c] holds the previous dimension's vector
+// and the decision may end the process) or only evaluating a check set on a
+// fixed basis.
 // sm: 7 * MAXM * LD + 2 * MAXM doubles.
-__device__ inline void check_block(KState* ks, double gamma, const double* taus, int c, int n_tau,
-                                   double tol, double* u_buf, double* est_buf, int m_max,
-                                   int update_state, double* sm)
+__device__ inline void check_block(KState* ks, double gamma, const double* taus, int c,
+                                   const int32_t* sel, int n_sel, double tol, double* u_buf,
+                                   double* est_buf, int m_max, int update_state, double* sm)
 {
     double* H = sm;                          // MAXM x LD
     double* buf = H + MAXM * LD;             // 6 matrices
@@ -302,9 +304,9 @@ __device__ inline void check_block(KState* ks, double gamma, const double* taus,
         est_buf[c] = est;
     }
     for (int i = threadIdx.x; i < m; i += blockDim.x) u_buf[c * MAXM + i] = u[i];
-    if (last_of(&ks->counter, n_tau)) {
+    if (last_of(&ks->counter, n_sel)) {
         double e = 0.0;
-        for (int k = threadIdx.x; k < n_tau; k += blockDim.x) e = fmax(e, est_buf[k]);
+        for (int k = threadIdx.x; k < n_sel; k += blockDim.x) e = fmax(e, est_buf[sel ? sel[k] : k]);
         // block maximum through the sum helper's layout
         e = -e;
 #pragma unroll

@@ -404,13 +404,15 @@ __global__ __launch_bounds__(256) void k_gs_finish(int64_t n, double* V, int64_t
 
 // One block per check offset.
 __global__ __launch_bounds__(256) void k_checks(KState* ks, double gamma,
-                                                const double* __restrict__ taus, int n_tau,
+                                                const double* __restrict__ taus,
+                                                const int32_t* __restrict__ sel, int n_sel,
                                                 double tol, double* u_buf, double* est_buf,
                                                 int m_max, int update_state)
 {
     if (update_state && ks->done) return;
     extern __shared__ double sm[];
-    check_block(ks, gamma, taus, blockIdx.x, n_tau, tol, u_buf, est_buf, m_max, update_state, sm);
+    const int c = sel ? sel[blockIdx.x] : int(blockIdx.x);
+    check_block(ks, gamma, taus, c, sel, n_sel, tol, u_buf, est_buf, m_max, update_state, sm);
 }
 
 // ------------------------------------------------------ segment set-up
@@ -612,11 +614,38 @@ void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w
 
 size_t checks_lds_bytes() { return sizeof(double) * (7 * MAXM * LD + 2 * MAXM); }
 
-void launch_checks(KState* ks, double gamma, const double* tau, int n_tau, double tol,
-                   double* u_buf, double* est_buf, int m_max, int update_state, hipStream_t st)
+void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* sel, int n_sel,
+                   double tol, double* u_buf, double* est_buf, int m_max, int update_state,
+                   hipStream_t st)
 {
-    k_checks<<<n_tau, 256, checks_lds_bytes(), st>>>(ks, gamma, tau, n_tau, tol, u_buf, est_buf,
+    k_checks<<<n_sel, 256, checks_lds_bytes(), st>>>(ks, gamma, tau, sel, n_sel, tol, u_buf, est_buf,
                                                      m_max, update_state);
+}
+
+__global__ void k_resume(KState* ks)
+{
+    if (threadIdx.x == 0) {
+        ks->done = 0;
+        ks->converged = 0;
+    }
+}
+
+void launch_resume(KState* ks, hipStream_t st)
+{
+    k_resume<<<1, 64, 0, st>>>(ks);
+}
+
+__global__ void k_set_ends(int32_t* sel, int last)
+{
+    if (threadIdx.x == 0) {
+        sel[0] = 0;
+        sel[1] = last;
+    }
+}
+
+void launch_set_ends(int32_t* sel, int last, hipStream_t st)
+{
+    k_set_ends<<<1, 64, 0, st>>>(sel, last);
 }
 
 void launch_setup_v(int64_t n, const double* y, const double* y0, const double* z2, double* v,

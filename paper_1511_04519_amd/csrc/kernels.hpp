@@ -95,10 +95,17 @@ void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w
                       const double* partial, KState* ks, const int32_t* done, hipStream_t st);
 
 // ---- small dense part: H_m, exp(tau H_m) e1, estimates, decision ----------
-// One workgroup per check offset. u_buf[c*MAXM + i] = (e^{tau_c H_m} e1)_i;
-// when iterating (update_state) it also holds the previous dimension's vector.
-void launch_checks(KState* ks, double gamma, const double* tau, int n_tau, double tol,
-                   double* u_buf, double* est_buf, int m_max, int update_state, hipStream_t st);
+// One workgroup per checked offset: sel[0 .. n_sel) (sel null: offsets
+// 0 .. n_sel - 1). u_buf[c*MAXM + i] = (e^{tau_c H_m} e1)_i; when iterating
+// (update_state) it also holds the previous dimension's vector.
+void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* sel, int n_sel,
+                   double tol, double* u_buf, double* est_buf, int m_max, int update_state,
+                   hipStream_t st);
+// Lets a process whose check subset passed but whose full check set did not
+// continue iterating.
+void launch_resume(KState* ks, hipStream_t st);
+// sel = {0, last}: the first and the last check offset.
+void launch_set_ends(int32_t* sel, int last, hipStream_t st);
 size_t checks_lds_bytes();
 
 // ---- segment set-up and reconstruction ------------------------------------

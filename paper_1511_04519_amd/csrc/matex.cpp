@@ -111,7 +111,8 @@ struct matex_factor_s {
     int sweep_blocks = 0;
     bool use_levels = false;
     // batched (multi-subtask) sweeps
-    DevMem d_b_dst, d_b_cptr, d_b_cidx, d_b_ft, d_b_fr, d_b_bt, d_b_br;
+    DevMem d_b_pos, d_b_cptr, d_b_cidx, d_b_ft, d_b_fr, d_b_bt, d_b_br;
+    BatchAssembly bas{};
     std::vector<BatchLevel> blevels;
     int64_t b_slots = 0;   // partial-result slots one batched sweep needs
     DevSym dsym{};
@@ -120,7 +121,7 @@ struct matex_factor_s {
         int64_t b = 0;
         for (const DevMem* m : {&d_c0, &d_nc, &d_nr, &d_roff, &d_w, &d_u, &d_rows, &d_child_ptr, &d_child_idx,
                                 &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_fwd_sn, &d_fwd_first, &d_bwd_sn,
-                                &d_bwd_first, &d_task_sn, &d_task_first, &d_dep_ptr, &d_dep_idx, &d_b_dst,
+                                &d_bwd_first, &d_task_sn, &d_task_first, &d_dep_ptr, &d_dep_idx, &d_b_pos,
                                 &d_b_cptr, &d_b_cidx, &d_b_ft, &d_b_fr, &d_b_bt, &d_b_br})
             b += int64_t(m->bytes);
         for (const DevMem& m : d_W) b += int64_t(m.bytes);
@@ -168,19 +169,19 @@ void build_tasks(matex_factor_s& F)
         F.fwd.push_back(f);
         F.bwd.push_back(b);
     }
-    // batched sweeps, per level: the assembly positions with their
-    // contributing child slots (inverse of relidx), forward blocks of 64 panel
-    // rows and backward blocks of 64 panel columns, each split into tasks of
-    // at most KCHUNK panel columns / rows whose partial results are summed
+    // batched sweeps: every panel position's contributing child slots (the
+    // inverse of relidx); per level, forward blocks of 64 panel rows and
+    // backward blocks of 64 panel columns, each split into tasks of at most
+    // KCHUNK panel columns / rows whose partial results are summed
     {
         const int L = s.n_levels;
-        std::vector<int32_t> dst, cptr{0}, cidx;
+        std::vector<int32_t> pos_base(s.sn.size()), cptr{0}, cidx;
         std::vector<BTask> ft, bt;
         std::vector<BRed> fr, br;
-        std::vector<int64_t> po(L + 1), fo(L + 1), fro(L + 1), bo(L + 1), bro(L + 1);
+        std::vector<int64_t> fo(L + 1), fro(L + 1), bo(L + 1), bro(L + 1);
         std::vector<std::vector<int32_t>> contrib;
         for (int lv = 0; lv < L; ++lv) {
-            po[lv] = int64_t(dst.size()); fo[lv] = int64_t(ft.size()); fro[lv] = int64_t(fr.size());
+            fo[lv] = int64_t(ft.size()); fro[lv] = int64_t(fr.size());
             bo[lv] = int64_t(bt.size()); bro[lv] = int64_t(br.size());
             int32_t fslots = 0, bslots = 0;
             for (int32_t k : s.level_sn[lv]) {
@@ -191,8 +192,8 @@ void build_tasks(matex_factor_s& F)
                     for (int32_t t = 0; t < c.nr - c.nc; ++t)
                         contrib[s.relidx[c.u + t]].push_back(int32_t(c.u + t));
                 }
+                pos_base[k] = int32_t(cptr.size()) - 1;
                 for (int32_t p = 0; p < q.nr; ++p) {
-                    dst.push_back(p < q.nc ? q.c0 + p : -int32_t(q.u + p - q.nc) - 1);
                     cidx.insert(cidx.end(), contrib[p].begin(), contrib[p].end());
                     cptr.push_back(int32_t(cidx.size()));
                 }
@@ -221,19 +222,16 @@ void build_tasks(matex_factor_s& F)
             }
             F.b_slots = std::max<int64_t>(F.b_slots, std::max(fslots, bslots));
         }
-        po[L] = int64_t(dst.size()); fo[L] = int64_t(ft.size()); fro[L] = int64_t(fr.size());
+        fo[L] = int64_t(ft.size()); fro[L] = int64_t(fr.size());
         bo[L] = int64_t(bt.size()); bro[L] = int64_t(br.size());
         if (cidx.empty()) cidx.push_back(0);
         if (fr.empty()) fr.push_back({0, 0, 0, 0});
         if (br.empty()) br.push_back({0, 0, 0, 0});
-        F.d_b_dst = upload(dst); F.d_b_cptr = upload(cptr); F.d_b_cidx = upload(cidx);
+        F.d_b_pos = upload(pos_base); F.d_b_cptr = upload(cptr); F.d_b_cidx = upload(cidx);
+        F.bas = BatchAssembly{F.d_b_pos.as<int32_t>(), F.d_b_cptr.as<int32_t>(), F.d_b_cidx.as<int32_t>()};
         F.d_b_ft = upload(ft); F.d_b_fr = upload(fr); F.d_b_bt = upload(bt); F.d_b_br = upload(br);
         for (int lv = 0; lv < L; ++lv) {
             BatchLevel b;
-            b.g_dst = F.d_b_dst.as<int32_t>() + po[lv];
-            b.g_cptr = F.d_b_cptr.as<int32_t>() + po[lv];
-            b.g_cidx = F.d_b_cidx.as<int32_t>();
-            b.n_pos = int32_t(po[lv + 1] - po[lv]);
             b.fwd = F.d_b_ft.as<BTask>() + fo[lv];
             b.n_fwd = int32_t(fo[lv + 1] - fo[lv]);
             b.fred = F.d_b_fr.as<BRed>() + fro[lv];
@@ -338,21 +336,20 @@ void dev_solve(const matex_factor_s& F, int which, const double* b, const double
 // right-hand sides (n x R). T, yf: n x R scratch; U: n_upd x R scratch.
 // P: F.b_slots * PSLOT doubles of partial results.
 void dev_solve_batched(const matex_factor_s& F, int which, int R, const double* B,
-                       const double* scale, double* x, double* T, double* yf, double* U, double* P,
+                       const double* scale, double* x, double* yf, double* U, double* P,
                        hipStream_t st)
 {
     const double* W = F.d_W[which].as<double>();
     const int L = F.sym.n_levels;
-    for (int lv = 0; lv < L; ++lv) launch_b_forward(F.dsym, F.blevels[lv], R, W, B, scale, T, yf, U, P, st);
+    for (int lv = 0; lv < L; ++lv) launch_b_forward(F.dsym, F.bas, F.blevels[lv], R, W, B, scale, yf, U, P, st);
     for (int lv = L - 1; lv >= 0; --lv) launch_b_backward(F.dsym, F.blevels[lv], R, W, yf, x, P, st);
 }
 
 // Scratch of one batched pair.
 struct BatchScratch {
-    DevMem T, yf, U, P;
+    DevMem yf, U, P;
     BatchScratch(const matex_factor_s& F, int R) {
         const size_t nr = sizeof(double) * size_t(F.sym.n) * R;
-        T = DevMem(nr);
         yf = DevMem(nr);
         U = DevMem(sizeof(double) * std::max<int64_t>(1, F.sym.n_upd) * R);
         P = DevMem(sizeof(double) * std::max<int64_t>(1, F.b_slots) * PSLOT);
@@ -362,8 +359,7 @@ struct BatchScratch {
 void dev_solve_batched(const matex_factor_s& F, int which, int R, const double* B,
                        const double* scale, double* x, const BatchScratch& sc, hipStream_t st)
 {
-    dev_solve_batched(F, which, R, B, scale, x, sc.T.as<double>(), sc.yf.as<double>(), sc.U.as<double>(),
-                      sc.P.as<double>(), st);
+    dev_solve_batched(F, which, R, B, scale, x, sc.yf.as<double>(), sc.U.as<double>(), sc.P.as<double>(), st);
 }
 
 // Raises if a one-launch sweep gave up waiting (reads the error word).
@@ -378,7 +374,7 @@ void check_sweep(SweepSync& sy, hipStream_t st)
 // Scratch of one Krylov process.
 struct Work {
     int64_t n = 0;
-    DevMem V, w, tmp, upd, partial, ks, u, est, taus;
+    DevMem V, w, tmp, upd, partial, ks, u, est, taus, sel;
     int64_t max_checks = 0;
     SweepSync sync;
     Work(const matex_factor_s& F, int64_t max_chk) : sync(F) {
@@ -394,6 +390,7 @@ struct Work {
         u = DevMem(sizeof(double) * max_checks * MAXM);
         est = DevMem(sizeof(double) * max_checks);
         taus = DevMem(sizeof(double) * max_checks);
+        sel = DevMem(sizeof(int32_t) * 2);
     }
     KState* kst() const { return ks.as<KState>(); }
     const int32_t* done() const { return &ks.as<KState>()->done; }
@@ -418,9 +415,10 @@ double read_est(const Work& wk, double* pinned, hipStream_t st)
 }
 
 // One Krylov iteration j (0-based): w = M^-1 C v_j, two Gram-Schmidt passes,
-// v_{j+1}, column j of Ht, and the estimate over the check set.
-void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, int n_tau, double tol,
-                      int m_max, hipStream_t st)
+// v_{j+1}, column j of Ht, and the estimate over the checked offsets (sel,
+// n_sel as for launch_checks).
+void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, const int32_t* sel,
+                      int n_sel, double tol, int m_max, hipStream_t st)
 {
     const int64_t n = wk.n;
     double* V = wk.V.as<double>();
@@ -429,23 +427,44 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, int n
     launch_gs_dots(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_update(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
-    launch_checks(wk.kst(), F.gammas[shift], wk.taus.as<double>(), n_tau, tol, wk.u.as<double>(),
+    launch_checks(wk.kst(), F.gammas[shift], wk.taus.as<double>(), sel, n_sel, tol, wk.u.as<double>(),
                   wk.est.as<double>(), m_max, 1, st);
 }
 
 // Runs Alg. 1 from the (already normalised) V_0 until the device says done.
-// Returns the final host view of the state.
+// With more than two check offsets the iterations test only the first and
+// the last; once those pass, one evaluation of every offset confirms the
+// decision, and if it fails the process continues with every offset
+// tested. This stops at the same dimension as testing every offset each
+// time: a failing subset implies a failing full set, and the evaluation
+// leaves every offset's vector of the current dimension for the next
+// iteration's difference term. Returns the final host view of the state.
 KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, double tol, int m_max,
                    int m_guess, KsHost* pinned, hipStream_t st)
 {
+    bool full = n_tau <= 2;
+    if (!full) launch_set_ends(wk.sel.as<int32_t>(), n_tau - 1, st);
     KsHost h = read_state(wk, pinned, st);
     int j = 0;
     int chunk = std::max(1, std::min(m_guess, m_max));
-    while (!h.done && j < m_max) {
-        int stop = std::min(m_max, j + chunk);
-        for (; j < stop; ++j) krylov_iteration(F, shift, wk, j, n_tau, tol, m_max, st);
+    while (true) {
+        while (!h.done && j < m_max) {
+            int stop = std::min(m_max, j + chunk);
+            for (; j < stop; ++j)
+                krylov_iteration(F, shift, wk, j, full ? nullptr : wk.sel.as<int32_t>(), full ? n_tau : 2, tol,
+                                 m_max, st);
+            h = read_state(wk, pinned, st);
+            chunk = 1;
+        }
+        if (full || !h.converged || h.m == 0) break;
+        launch_checks(wk.kst(), F.gammas[shift], wk.taus.as<double>(), nullptr, n_tau, tol, wk.u.as<double>(),
+                      wk.est.as<double>(), m_max, 0, st);
         h = read_state(wk, pinned, st);
-        chunk = 1;
+        if (h.converged) break;
+        full = true;
+        if (h.m >= m_max) break;
+        launch_resume(wk.kst(), st);
+        h.done = 0;
     }
     return h;
 }
@@ -958,56 +977,85 @@ std::vector<KsHost> read_states(const BatchWork& bw, int R, hipStream_t st)
     return std::vector<KsHost>(h, h + R);
 }
 
-// Checks table of the columns in `cols_in` with offsets off_of(r).
+// Checks table of the columns in cols_in: every offset off_of(r) is
+// uploaded; the checked ones are all of them when all_of(r), else the first
+// and the last. `extra` is packed after the table (ext = its device copy).
 struct CheckTab {
     double* taus = nullptr;
-    int32_t *off = nullptr, *cnt = nullptr, *active = nullptr, *col = nullptr, *idx = nullptr;
+    int32_t *off = nullptr, *active = nullptr, *col = nullptr, *idx = nullptr, *coff = nullptr,
+            *ccnt = nullptr, *ext = nullptr;
     int n_chk = 0;
 };
 
-template <class OffsOf>
-CheckTab build_checks(BatchWork& bw, int R, const std::vector<int>& cols_in, OffsOf off_of,
-                      hipStream_t st)
+template <class OffsOf, class AllOf>
+CheckTab build_checks(BatchWork& bw, int R, const std::vector<int>& cols_in, OffsOf off_of, AllOf all_of,
+                      const std::vector<int32_t>& extra, hipStream_t st)
 {
-    size_t tot = 0;
-    for (int r : cols_in) tot += off_of(r).size();
+    size_t tot = 0, nsel = 0;
+    for (int r : cols_in) {
+        const size_t c = off_of(r).size();
+        tot += c;
+        nsel += (all_of(r) || c <= 2) ? c : 2;
+    }
     Packer pk(bw.h_pre, bw.d_pre, bw.tab_bytes);
     CheckTab t;
     double* ht = pk.take<double>(std::max<size_t>(1, tot), &t.taus);
     int32_t* hoff = pk.take<int32_t>(R, &t.off);
-    int32_t* hcnt = pk.take<int32_t>(R, &t.cnt);
     int32_t* hact = pk.take<int32_t>(R, &t.active);
-    int32_t* hcol = pk.take<int32_t>(std::max<size_t>(1, tot), &t.col);
-    int32_t* hidx = pk.take<int32_t>(std::max<size_t>(1, tot), &t.idx);
+    int32_t* hcoff = pk.take<int32_t>(R, &t.coff);
+    int32_t* hccnt = pk.take<int32_t>(R, &t.ccnt);
+    int32_t* hcol = pk.take<int32_t>(std::max<size_t>(1, nsel), &t.col);
+    int32_t* hidx = pk.take<int32_t>(std::max<size_t>(1, nsel), &t.idx);
+    int32_t* hext = pk.take<int32_t>(std::max<size_t>(1, extra.size()), &t.ext);
     std::fill(hoff, hoff + R, 0);
-    std::fill(hcnt, hcnt + R, 0);
     std::fill(hact, hact + R, 0);
-    size_t q = 0;
+    std::fill(hcoff, hcoff + R, 0);
+    std::fill(hccnt, hccnt + R, 0);
+    std::copy(extra.begin(), extra.end(), hext);
+    size_t q = 0, e = 0;
     for (int r : cols_in) {
         const std::vector<int64_t>& of = off_of(r);
+        const int32_t c = int32_t(of.size());
         hoff[r] = int32_t(q);
-        hcnt[r] = int32_t(of.size());
         hact[r] = 1;
-        for (size_t c = 0; c < of.size(); ++c, ++q) {
-            ht[q] = double(of[c]) * FS;
-            hcol[q] = r;
-            hidx[q] = int32_t(c);
+        for (int32_t k = 0; k < c; ++k) ht[q + k] = double(of[k]) * FS;
+        q += c;
+        hcoff[r] = int32_t(e);
+        if (all_of(r) || c <= 2) {
+            for (int32_t k = 0; k < c; ++k, ++e) { hcol[e] = r; hidx[e] = k; }
+        } else {
+            hcol[e] = r; hidx[e] = 0; ++e;
+            hcol[e] = r; hidx[e] = c - 1; ++e;
         }
+        hccnt[r] = int32_t(e) - hcoff[r];
     }
-    t.n_chk = int(q);
+    t.n_chk = int(e);
     pk.upload(st);
     return t;
+}
+
+void launch_tab_checks(const matex_factor_s& F, BatchWork& bw, const CheckTab& t, int k, double tol, int m_max,
+                       int update, hipStream_t st)
+{
+    launch_b_checks(bw.kst(), F.gammas[k], t.taus, t.off, bw.cap, t.col, t.idx, t.coff, t.ccnt, t.n_chk, tol,
+                    bw.u.as<double>(), bw.est.as<double>(), m_max, update, st);
 }
 
 // One lockstep pass of Alg. 1 with shift k for the subtasks in grp (the
 // others inactive): one multi-right-hand-side substitution pair per Krylov
 // iteration for the whole batch, then per-subtask Gram-Schmidt and checks.
+// Check offsets as in the one-subtask path: the first and the last while
+// iterating, every offset to confirm, every offset from then on for a
+// subtask whose confirmation failed.
 std::vector<KsHost> run_pass(const matex_factor_s& F, BatchWork& bw, int R, int k,
                              const std::vector<int>& grp, std::vector<BCol>& cols, double tol,
                              int m_max, int& m_guess, matex_stats& S, hipStream_t st)
 {
     const int64_t n = bw.n;
-    CheckTab t = build_checks(bw, R, grp, [&](int r) -> const std::vector<int64_t>& { return cols[r].offs; }, st);
+    std::vector<char> full(R, 0);
+    auto offs_of = [&](int r) -> const std::vector<int64_t>& { return cols[r].offs; };
+    auto mode_of = [&](int r) { return full[r] != 0; };
+    CheckTab t = build_checks(bw, R, grp, offs_of, mode_of, {}, st);
     double* V = bw.Vd();
     launch_b_setup(n, R, bw.y.as<double>(), bw.y0.as<double>(), bw.z2.as<double>(), V,
                    bw.partial.as<double>(), bw.kst(), t.active, st);
@@ -1018,18 +1066,35 @@ std::vector<KsHost> run_pass(const matex_factor_s& F, BatchWork& bw, int R, int 
         return true;
     };
     int j = 0, chunk = std::max(1, std::min(m_guess, m_max));
-    while (!all_done() && j < m_max) {
-        const int stop = std::min(m_max, j + chunk);
-        for (; j < stop; ++j) {
-            dev_solve_batched(F, k, R, V + int64_t(j) * n * R, F.d_cperm.as<double>(), bw.w.as<double>(),
-                              bw.sc, st);
-            launch_b_gs(n, R, V, j + 1, bw.w.as<double>(), bw.partial.as<double>(), bw.kst(), st);
-            launch_b_checks(bw.kst(), F.gammas[k], t.taus, t.off, t.cnt, bw.cap, t.col, t.idx, t.n_chk, tol,
-                            bw.u.as<double>(), bw.est.as<double>(), m_max, 1, st);
-            S.solve_pairs_m++;
+    while (true) {
+        while (!all_done() && j < m_max) {
+            const int stop = std::min(m_max, j + chunk);
+            for (; j < stop; ++j) {
+                dev_solve_batched(F, k, R, V + int64_t(j) * n * R, F.d_cperm.as<double>(), bw.w.as<double>(),
+                                  bw.sc, st);
+                launch_b_gs(n, R, V, j + 1, bw.w.as<double>(), bw.partial.as<double>(), bw.kst(), st);
+                launch_tab_checks(F, bw, t, k, tol, m_max, 1, st);
+                S.solve_pairs_m++;
+            }
+            hs = read_states(bw, R, st);
+            chunk = 1;
         }
+        std::vector<int> ver;
+        for (int r : grp)
+            if (!full[r] && hs[r].converged && hs[r].m > 0 && cols[r].offs.size() > 2) ver.push_back(r);
+        if (ver.empty()) break;
+        CheckTab tv = build_checks(bw, R, ver, offs_of, [](int) { return true; }, {}, st);
+        launch_tab_checks(F, bw, tv, k, tol, m_max, 0, st);
         hs = read_states(bw, R, st);
-        chunk = 1;
+        std::vector<int32_t> res;
+        for (int r : ver) {
+            full[r] = 1;
+            if (!hs[r].converged && hs[r].m < m_max) res.push_back(r);
+        }
+        if (res.empty()) break;
+        t = build_checks(bw, R, grp, offs_of, mode_of, res, st);
+        launch_b_resume(bw.kst(), t.ext, int(res.size()), st);
+        for (int r : res) hs[r].done = 0;
     }
     int mx = 0;
     for (int r : grp) {
@@ -1214,10 +1279,10 @@ void transient_batched(const matex_factor_s& F, const matex_problem* p, const ma
                                          std::to_string(b0 + r) + ")"};
                         c.cand = halved_offsets(c.offs, c.hstep);
                     }
-                    CheckTab t = build_checks(bw, R, halve,
-                                              [&](int r) -> const std::vector<int64_t>& { return cols[r].cand; }, st);
-                    launch_b_checks(bw.kst(), F.gammas[k], t.taus, t.off, t.cnt, bw.cap, t.col, t.idx, t.n_chk,
-                                    o->tol, bw.u.as<double>(), bw.est.as<double>(), o->m_max, 0, st);
+                    CheckTab t = build_checks(
+                        bw, R, halve, [&](int r) -> const std::vector<int64_t>& { return cols[r].cand; },
+                        [](int) { return true; }, {}, st);
+                    launch_tab_checks(F, bw, t, k, o->tol, o->m_max, 0, st);
                     std::vector<KsHost> hh = read_states(bw, R, st);
                     std::vector<int> still;
                     for (int r : halve) {
@@ -1407,7 +1472,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
                         std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
                         HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
                                               hipMemcpyHostToDevice, st));
-                        launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), int(taus.size()),
+                        launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), nullptr, int(taus.size()),
                                       o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
                         KsHost hh = read_state(wk, hks, st);
                         if (trace)
