@@ -14,6 +14,10 @@ roofline: the substitution-pair sweeps (the dominant kernels), algorithmic
 bytes per pair over the event-timed mean pair duration, against 8 TB/s.
 cpu_baseline: the CPU oracle, single-threaded, on the first part of the same
 window (a bounded sample), scaled to node-steps/s.
+batched: the 3 x 580 x 580 grid (1,009,200 nodes, 2000 sources in 64
+subtasks of shared pulse timing, 20 ns window) run batched and plain
+(subtasks one after another) at the per-subtask tolerance 1e-10 / 64, with
+the 64-right-hand-side pair's roofline (--no-batched skips it).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -34,7 +38,7 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_pair_config1.md")
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "factor.cpp", "factor.hpp"):
+    for f in ("kernels.hip", "kernels.hpp", "device_common.hpp", "factor.cpp", "factor.hpp"):
         h.update(open(os.path.join(ROOT, "paper_1511_04519_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -82,6 +86,58 @@ print(json.dumps(dict(factor_s=tf, transient_s=tt, n=p.netlist.n, n_out=int(q.t_
     return d
 
 
+def batched_vs_plain(window_ps=0):
+    """The 64-subtask workload batched and plain, and the 64-RHS pair."""
+    import numpy as np
+    import torch
+    from paper_1511_04519_amd import instances as I
+    from paper_1511_04519_amd import matex as M
+    p = I.config2()
+    if window_ps:
+        T = window_ps * I.PS
+        p = I.Problem(p.name + f" (first {window_ps} ps)", p.netlist, p.sources, T,
+                      p.t_out[p.t_out <= T], p.probe)
+    groups = len(np.unique(p.sources.group))
+    tol = 1e-10 / groups
+    n, n_out = p.netlist.n, p.t_out.size
+    t0 = time.time()
+    F = M.matex_factor(p.netlist, p.gamma)
+    factor_s = time.time() - t0
+    print(f"[bench] batched workload: n {n}, {groups} subtasks, factor {factor_s:.1f} s, "
+          f"nnz(L) {F.info['nnz_l']}", flush=True)
+    res = {}
+    for mode, md in (("batched", M.MATEX_BATCHED), ("plain", M.MATEX_PLAIN)):
+        torch.cuda.synchronize()
+        t0 = time.time()
+        x, _, st = M.matex_transient(F, p, tol=tol, m_max=p.m_max, mode=md)
+        torch.cuda.synchronize()
+        dt = time.time() - t0
+        res[mode] = (x.cpu().numpy(), dt, st)
+        print(f"[bench] {mode}: {dt:.2f} s, pairs {st['solve_pairs_m']}+{st['solve_pairs_g']}, "
+              f"bases {st['bases']}", flush=True)
+    diff = float(np.abs(res["batched"][0] - res["plain"][0]).max())
+    pair_s, pair_b = M.matex_time_solves(F, which=0, reps=20, nrhs=64)
+    one_s, one_b = M.matex_time_solves(F, which=0, reps=20, nrhs=1)
+    sb, sp = res["batched"][2], res["plain"][2]
+    return {
+        "workload": p.name, "n": n, "n_out": int(n_out), "subtasks": groups, "tol": tol,
+        "factor_s": round(factor_s, 2),
+        "batched_node_steps_per_s": n * n_out / res["batched"][1],
+        "plain_node_steps_per_s": n * n_out / res["plain"][1],
+        "batched_s": round(res["batched"][1], 3), "plain_s": round(res["plain"][1], 3),
+        "speedup": round(res["plain"][1] / res["batched"][1], 3),
+        "max_abs_diff_batched_vs_plain": diff,
+        "same_steps": sb["segments"] == sp["segments"] and sb["krylov_dims"] == sp["krylov_dims"],
+        "stats_batched": sb, "stats_plain": sp,
+        "pair64": {"bound": "hbm", "achieved": round(pair_b / pair_s / 1e9, 2), "peak": HBM_PEAK_GBS,
+                   "unit": "GB/s", "frac": round(pair_b / pair_s / 1e9 / HBM_PEAK_GBS, 5),
+                   "pair_ms": round(pair_s * 1e3, 3), "pair_bytes": int(pair_b),
+                   "ms_per_subtask": round(pair_s * 1e3 / 64, 4)},
+        "pair1": {"achieved": round(one_b / one_s / 1e9, 2), "unit": "GB/s",
+                  "frac": round(one_b / one_s / 1e9 / HBM_PEAK_GBS, 5), "pair_ms": round(one_s * 1e3, 3)},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +147,8 @@ def main():
     ap.add_argument("--window-ps", type=int, default=0, help="shorten the window (0 = full)")
     ap.add_argument("--cpu-window-ps", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-window-ps", type=int, default=0, help="shorten the batched window")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -155,6 +213,8 @@ def main():
     torch.empty_like(a).copy_(a)
     torch.cuda.synchronize()
 
+    batched = None if args.no_batched else batched_vs_plain(args.batched_window_ps)
+
     cpu = None
     if not args.no_cpu_baseline:
         d = cpu_baseline(p, args.tol, args.cpu_window_ps * I.PS)
@@ -174,7 +234,7 @@ def main():
                    "bases": st["bases"], "solve_pairs": st["solve_pairs_m"] + st["solve_pairs_g"],
                    "max_abs_err_vs_oracle_0_500ps": err_head,
                    "max_abs_err_vs_oracle_2900_3000ps": err_mid},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "batched": batched,
     }
     print(json.dumps(line), flush=True)
 
