@@ -212,6 +212,26 @@ matex_status matex_transient(matex_factor_t f, const matex_problem* p, const mat
                              void* stream);
 
 /*
+ * matex_transient_many - matex_transient for n_inst independent problems,
+ * each with its own factor (an uneven batch: grids of different sizes),
+ * advanced concurrently: the instances, largest first (nodes times sources),
+ * go to `n_streams` workers (0 = 4, at most 16), each a host thread driving
+ * its own library-owned HIP stream of default priority, so the GPU overlaps
+ * the instances' kernels. Instance k uses f[k], p[k], o[k] and writes
+ * d_probe_out[k] (and d_final[k] when d_final is not NULL) as
+ * matex_transient does; stats: [n_inst] or NULL. The call first synchronises
+ * `stream` (the inputs may come from it) and returns when every instance is
+ * done. Each instance takes the same steps and gives the same results as a
+ * matex_transient call on its own. Errors: those of matex_transient, for the
+ * first instance that failed (the text names it); the remaining instances
+ * are then not started.
+ */
+matex_status matex_transient_many(int32_t n_inst, const matex_factor_t* f, const matex_problem* p,
+                                  const matex_run_opts* o, double* const* d_probe_out,
+                                  double* const* d_final, matex_stats* stats, int32_t n_streams,
+                                  void* stream);
+
+/*
  * matex_adjoint - gradients of a droop objective with respect to source
  * amplitudes and node capacitances. Not provided by this build: returns
  * MATEX_E_UNSUPPORTED.

@@ -14,8 +14,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -1515,6 +1517,68 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     }
     S.seconds = now_s() - t_start;
     if (stats) *stats = S;
+    return MATEX_OK;
+}
+
+extern "C" matex_status matex_transient_many(int32_t n_inst, const matex_factor_t* f,
+                                             const matex_problem* p, const matex_run_opts* o,
+                                             double* const* d_probe_out, double* const* d_final,
+                                             matex_stats* stats, int32_t n_streams, void* stream)
+{
+    if (n_inst < 0 || (n_inst > 0 && (!f || !p || !o || !d_probe_out)))
+        return fail(MATEX_E_INVALID, "null argument");
+    if (n_streams < 0 || n_streams > 16) return fail(MATEX_E_INVALID, "n_streams must be in 0..16");
+    if (n_inst == 0) return MATEX_OK;
+    const int workers = std::min<int>(n_inst, n_streams > 0 ? n_streams : 4);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(MATEX_E_HIP, "hipGetDevice failed");
+    // the caller's stream may hold work that produced the inputs
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess)
+        return fail(MATEX_E_HIP, "stream synchronisation failed");
+    // largest work first: nodes times transition spots
+    std::vector<int32_t> order(n_inst);
+    std::vector<double> work(n_inst);
+    for (int32_t k = 0; k < n_inst; ++k) {
+        order[k] = k;
+        work[k] = f[k] ? double(f[k]->sym.n) * (4.0 * std::max(1, p[k].n_src) + 2.0) : 0.0;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[a] > work[b]; });
+    std::atomic<int32_t> next{0};
+    std::mutex mu;
+    matex_status first = MATEX_OK;
+    std::string first_msg;
+    auto run = [&]() {
+        if (hipSetDevice(dev) != hipSuccess) return;
+        hipStream_t st = nullptr;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+            std::lock_guard<std::mutex> g(mu);
+            if (first == MATEX_OK) { first = MATEX_E_HIP; first_msg = "stream creation failed"; }
+            return;
+        }
+        while (true) {
+            const int32_t q = next.fetch_add(1);
+            if (q >= n_inst) break;
+            const int32_t k = order[q];
+            matex_stats sk{};
+            const matex_status r = matex_transient(f[k], &p[k], &o[k], d_probe_out[k],
+                                                   d_final ? d_final[k] : nullptr, &sk, st);
+            if (stats) stats[k] = sk;
+            if (r != MATEX_OK) {
+                std::lock_guard<std::mutex> g(mu);
+                if (first == MATEX_OK) {
+                    first = r;
+                    first_msg = "instance " + std::to_string(k) + ": " + g_err;
+                }
+                next.store(n_inst);
+            }
+        }
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    };
+    std::vector<std::thread> th;
+    for (int w = 0; w < workers; ++w) th.emplace_back(run);
+    for (auto& t : th) t.join();
+    if (first != MATEX_OK) return fail(first, first_msg);
     return MATEX_OK;
 }
 

@@ -69,8 +69,8 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
-           "matex_krylov_step", "matex_transient", "matex_adjoint", "matex_time_solves",
-           "matex_last_error", "matex_version"]
+           "matex_krylov_step", "matex_transient", "matex_transient_many", "matex_adjoint",
+           "matex_time_solves", "matex_last_error", "matex_version"]
 
 _lib = None
 
@@ -81,6 +81,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_1511_04519_amd/build.py")
+        # torch's HIP runtime must be the process's first: the library then
+        # shares its device context and streams
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         L.matex_factor.argtypes = [ctypes.POINTER(Netlist), _f64, ctypes.POINTER(FactorOpts), _vp,
                                    ctypes.POINTER(_vp)]
@@ -91,6 +94,9 @@ def lib():
                                         _pf64, _vp]
         L.matex_transient.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(RunOpts), _vp,
                                       _vp, ctypes.POINTER(Stats), _vp]
+        L.matex_transient_many.argtypes = [_i32, ctypes.POINTER(_vp), ctypes.POINTER(Problem),
+                                           ctypes.POINTER(RunOpts), ctypes.POINTER(_vp),
+                                           ctypes.POINTER(_vp), ctypes.POINTER(Stats), _i32, _vp]
         L.matex_adjoint.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(RunOpts), _vp,
                                     _vp, _vp, _vp]
         L.matex_time_solves.argtypes = [_vp, _i32, _i32, _i32, _pf64, _pf64, _vp]
@@ -98,8 +104,8 @@ def lib():
         L.matex_last_error.restype = ctypes.c_size_t
         L.matex_version.restype = ctypes.c_char_p
         for name in ("matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
-                     "matex_krylov_step", "matex_transient", "matex_adjoint",
-                     "matex_time_solves"):
+                     "matex_krylov_step", "matex_transient", "matex_transient_many",
+                     "matex_adjoint", "matex_time_solves"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -146,11 +152,13 @@ class FactorHandle:
     def __init__(self, handle, info):
         self.handle = handle
         self.info = info
+        self._free = lib().matex_factor_free   # still reachable at interpreter exit
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
-            lib().matex_factor_free(h)
+        free = getattr(self, "_free", None)
+        if h and free is not None:
+            free(h)
             self.handle = None
 
 
@@ -237,6 +245,28 @@ def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
     _check(lib().matex_transient(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(out), _ptr(fin),
                                  ctypes.byref(st), _stream()))
     return out, fin, st.as_dict()
+
+
+def matex_transient_many(factors, probs, tol: float = 1e-11, m_max: int = 20,
+                         mode: int = MATEX_PLAIN, h_min: int = 1, n_streams: int = 4,
+                         device="cuda", final: bool = True, shift_ratio: float = 1.0):
+    """Independent instances (own factor each) advanced concurrently on
+    n_streams library streams. Returns a list of (x, x_final or None, stats)."""
+    import torch
+    k = len(factors)
+    assert len(probs) == k
+    keep = []
+    prs = (Problem * max(1, k))(*[_problem_struct(q, keep) for q in probs])
+    outs = [torch.empty((q.probe.size, q.t_out.size), dtype=torch.float64, device=device) for q in probs]
+    fins = [torch.empty(F.info["n"], dtype=torch.float64, device=device) for F in factors] if final else None
+    fh = (_vp * max(1, k))(*[F.handle.value for F in factors])
+    po = (_vp * max(1, k))(*[_ptr(t) for t in outs])
+    pf = (_vp * max(1, k))(*[_ptr(t) for t in fins]) if final else None
+    opts = (RunOpts * max(1, k))(*[RunOpts(float(tol), int(m_max), int(mode), int(h_min),
+                                           float(shift_ratio)) for _ in range(k)])
+    sts = (Stats * max(1, k))()
+    _check(lib().matex_transient_many(k, fh, prs, opts, po, pf, sts, int(n_streams), _stream()))
+    return [(outs[i], fins[i] if final else None, sts[i].as_dict()) for i in range(k)]
 
 
 def matex_time_solves(f: FactorHandle, which: int = 0, reps: int = 50, nrhs: int = 1):

@@ -102,3 +102,28 @@ def test_batched_edge_cases():
     with pytest.raises(M.MatexError) as e:
         M.matex_transient(F, q, mode=7)
     assert e.value.status == M.MATEX_E_INVALID
+
+
+def test_uneven_instances_concurrent():
+    """Independent grids of different sizes (own factor each) on concurrent
+    streams: each instance gives exactly what a call on its own gives, and
+    matches the oracle and the exact modal solution."""
+    _note("uneven instances")
+    shapes = [(1, 9, 7, 5), (2, 14, 11, 9), (1, 23, 6, 4), (3, 8, 8, 6), (2, 5, 17, 3), (1, 12, 12, 7)]
+    probs = [I.small(500 + k, layers=L, nx=nx, ny=ny, n_src=ns, t_end=2 * I.NS)
+             for k, (L, nx, ny, ns) in enumerate(shapes)]
+    facs = [M.matex_factor(q.netlist, GAMMA) for q in probs]
+    many = M.matex_transient_many(facs, probs, tol=1e-12, n_streams=3)
+    for q, F, (x, xf, st) in zip(probs, facs, many):
+        x1, xf1, st1 = M.matex_transient(F, q, tol=1e-12)
+        assert np.array_equal(x.cpu().numpy(), x1.cpu().numpy())
+        assert np.array_equal(xf.cpu().numpy(), xf1.cpu().numpy())
+        assert st["segments"] == st1["segments"] and st["krylov_dims"] == st1["krylov_dims"]
+        ym, _ = R.modal(q)
+        assert np.abs(x.cpu().numpy() - (q.netlist.vdd - ym)).max() <= 1e-10
+    # one failing instance: the call reports it by index
+    bad = I.Problem("bad", probs[1].netlist, probs[1].sources, probs[1].t_end,
+                    np.array([10, 5]), probs[1].probe)
+    with pytest.raises(M.MatexError) as e:
+        M.matex_transient_many(facs[:2], [probs[0], bad], n_streams=2)
+    assert e.value.status == M.MATEX_E_INVALID and "instance 1" in str(e.value)
