@@ -72,10 +72,11 @@ typedef struct {
 
 typedef struct {
     int32_t n_shifts;        /* shifts gamma_k = gamma * 10^-k, k < n_shifts
-                                (default 5 when 0; with gamma = 10 ps the
-                                smallest is 1 fs, the time quantum): one
-                                factor of C + gamma_k G each, plus one of G,
-                                all factored once                               */
+                                (default 6 when 0; with gamma = 10 ps, gamma_4
+                                is 1 fs, the time quantum, and gamma_5 the
+                                step-down rung for 1 fs steps of the adjoint):
+                                one factor of C + gamma_k G each, plus one of
+                                G, all factored once                            */
     int32_t leaf_max;        /* nested-dissection leaf size (default 16 when 0) */
 } matex_factor_opts;
 
@@ -232,9 +233,26 @@ matex_status matex_transient_many(int32_t n_inst, const matex_factor_t* f, const
                                   void* stream);
 
 /*
- * matex_adjoint - gradients of a droop objective with respect to source
- * amplitudes and node capacitances. Not provided by this build: returns
- * MATEX_E_UNSUPPORTED.
+ * matex_adjoint - gradients of an objective J of the probe voltages (for
+ * example a droop penalty) with respect to the source amplitudes, by the
+ * continuous adjoint of Eq. 5 propagated with the same rational Krylov steps
+ * (Sec. 3.3.2) backwards in time. The method itself is not in the paper;
+ * only its propagator is.
+ *   d_dJdx: device [n_probe][n_out] (row-major, as d_probe_out of
+ *           matex_transient) = dJ/dx at the probes and output times; the
+ *           output times > 0 whose column is not all zero are the samples.
+ *   d_grad_amp: device [n_src] = dJ/da_k (a_k = amp[k]; the pulses' timing
+ *           from p), or NULL.
+ *   d_grad_c: must be NULL (capacitance gradients: MATEX_E_UNSUPPORTED).
+ * The adjoint lambda is zero after the last sample, jumps by C^-1 dJ/dy at
+ * each sample and satisfies C lambda' = G lambda between samples; dJ/da_k
+ * is the time integral of the source's unit pulse times lambda at its node.
+ * Steps end at the samples and at every source's transition spots, and
+ * after each jump grow geometrically from 1 fs; o->tol bounds each step's
+ * estimate relative to the largest jump norm ||C^-1 dJ/dy(t_s)||_2 (about
+ * 1e-10 is the practical floor), o->m_max must be <= 30, o->mode is ignored.
+ * Synchronises `stream`. Errors: MATEX_E_INVALID, MATEX_E_UNSUPPORTED,
+ * MATEX_E_NOCONV, MATEX_E_OOM, MATEX_E_HIP.
  */
 matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
                            const double* d_dJdx, double* d_grad_amp, double* d_grad_c,

@@ -181,9 +181,11 @@ __device__ inline void form_h(const KState* ks, int m, double gamma, double* H, 
     __syncthreads();
 }
 
-// u = e^{tau H} e1 (m entries). Uses 6 matrices of MAXM x LD in `buf`; H is
-// overwritten (its storage holds V of the approximant once A = tau H / 2^s).
-__device__ inline void expm_e1(double* H, int m, double tau, double* buf, double* u)
+// e^{tau H} (m x m, row-major, stride LD; m <= MAXM). Uses 6 matrices of
+// MAXM x LD in `buf`; H is overwritten (its storage holds V of the
+// approximant once A = tau H / 2^s). Returns the matrix holding the result
+// (inside buf), valid until buf is reused.
+__device__ inline double* expm_mat(double* H, int m, double tau, double* buf)
 {
     double* A = buf;
     double* A2 = A + MAXM * LD;
@@ -251,6 +253,13 @@ __device__ inline void expm_e1(double* H, int m, double tau, double* buf, double
         mm(R, R, S, m);
         double* t = R; R = S; S = t;
     }
+    return R;
+}
+
+// u = e^{tau H} e1 (m entries); buffers as for expm_mat.
+__device__ inline void expm_e1(double* H, int m, double tau, double* buf, double* u)
+{
+    const double* R = expm_mat(H, m, tau, buf);
     for (int i = threadIdx.x; i < m; i += blockDim.x) u[i] = R[i * LD];
     __syncthreads();
 }

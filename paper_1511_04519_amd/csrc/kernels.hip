@@ -622,6 +622,94 @@ void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* s
                                                      m_max, update_state);
 }
 
+// ------------------------------------------------------------- adjoint
+
+// Step integrals of the adjoint (Van Loan 1978): with the (m+2) x (m+2)
+// matrix M = [[H, e1, 0], [0, 0, 1], [0, 0, 0]], e^{tau M} holds
+// phi1 = int_0^tau e^{sH} e1 ds and phi2 = int_0^tau (tau - s) e^{sH} e1 ds in
+// its last two columns. I[0 .. m) = phi1 and I[MAXM .. MAXM + m) =
+// tau phi1 - phi2 = int_0^tau s e^{sH} e1 ds. Needs m <= MAXM - 2.
+__global__ __launch_bounds__(256) void k_adj_integrals(const KState* ks, double gamma, double tau,
+                                                       double* I)
+{
+    extern __shared__ double sm[];
+    double* H = sm;
+    double* buf = H + MAXM * LD;
+    const int m = ks->m;
+    if (m == 0) {
+        for (int i = threadIdx.x; i < 2 * MAXM; i += blockDim.x) I[i] = 0.0;
+        return;
+    }
+    form_h(ks, m, gamma, H, buf);
+    const int N = m + 2;
+    for (int idx = threadIdx.x; idx < N * LD; idx += blockDim.x) {
+        const int i = idx / LD, j = idx % LD;
+        if (i < m && j < m) continue;
+        double v = 0.0;
+        if (i == 0 && j == m) v = 1.0;
+        if (i == m && j == m + 1) v = 1.0;
+        H[idx] = v;
+    }
+    __syncthreads();
+    const double* R = expm_mat(H, N, tau, buf);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) {
+        const double p1 = R[i * LD + m], p2 = R[i * LD + m + 1];
+        I[i] = p1;
+        I[MAXM + i] = tau * p1 - p2;
+    }
+}
+
+// Amplitude gradients over one adjoint step [t_hi - dt, t_hi] (fs), inside
+// which every pulse is linear: with sigma = t_hi - t, u_k = alpha + beta sigma
+// and lambda(t_hi - sigma) = b V e^{sigma H} e1, so
+// int u_k lambda_{n_k} dt = b V[row_k, :] (alpha I0 + beta I1).
+__global__ void k_adj_amp(int n_src, const int32_t* __restrict__ row, const int64_t* __restrict__ delay,
+                          const int64_t* __restrict__ rise, const int64_t* __restrict__ width,
+                          const int64_t* __restrict__ fall, int64_t t_hi, int64_t dt,
+                          const double* __restrict__ V, int64_t ldv, const KState* ks,
+                          const double* __restrict__ I, double lscale, double* grad)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_src) return;
+    const int m = ks->m;
+    if (m == 0) return;
+    const int64_t d = delay[k], r = rise[k], w = width[k], f = fall[k];
+    // value at t_hi and slope (per fs) on the step, from its midpoint's piece
+    auto val = [&](int64_t t) -> double {
+        if (t <= d) return 0.0;
+        if (t < d + r) return double(t - d) / double(r);
+        if (t <= d + r + w) return 1.0;
+        if (t < d + r + w + f) return 1.0 - double(t - d - r - w) / double(f);
+        return 0.0;
+    };
+    const double tm = double(t_hi) - 0.5 * double(dt);
+    double slope = 0.0;
+    if (tm > double(d) && tm < double(d + r)) slope = 1.0 / double(r);
+    else if (tm > double(d + r + w) && tm < double(d + r + w + f)) slope = -1.0 / double(f);
+    const double alpha = val(t_hi);
+    const double beta = -slope * 1e15;   // d u / d sigma, per second
+    if (alpha == 0.0 && beta == 0.0) return;
+    const int64_t o = row[k];
+    double acc = 0.0;
+    for (int j = 0; j < m; ++j) acc += V[int64_t(j) * ldv + o] * (alpha * I[j] + beta * I[MAXM + j]);
+    grad[k] += lscale * ks->beta * acc;
+}
+
+// lambda += C^-1 g at a sample time: g = -dJ/dx at the probes. The probes
+// are grouped by row (rows[q], their probe indices pidx[ptr[q] .. ptr[q+1])),
+// summed in a fixed order.
+__global__ void k_adj_jump(int n_rows, const int32_t* __restrict__ rows, const int32_t* __restrict__ ptr,
+                           const int32_t* __restrict__ pidx, const double* __restrict__ dJdx,
+                           int64_t n_out, int s, const double* __restrict__ cperm, double inv_scale,
+                           double* lam)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_rows) return;
+    double g = 0.0;
+    for (int e = ptr[q]; e < ptr[q + 1]; ++e) g -= dJdx[int64_t(pidx[e]) * n_out + s];
+    lam[rows[q]] += g / cperm[rows[q]] * inv_scale;
+}
+
 __global__ void k_resume(KState* ks)
 {
     if (threadIdx.x == 0) {
@@ -646,6 +734,30 @@ __global__ void k_set_ends(int32_t* sel, int last)
 void launch_set_ends(int32_t* sel, int last, hipStream_t st)
 {
     k_set_ends<<<1, 64, 0, st>>>(sel, last);
+}
+
+void launch_adj_integrals(const KState* ks, double gamma, double tau, double* I, hipStream_t st)
+{
+    k_adj_integrals<<<1, 256, sizeof(double) * 7 * MAXM * LD, st>>>(ks, gamma, tau, I);
+}
+
+void launch_adj_amp(int n_src, const int32_t* row, const int64_t* delay, const int64_t* rise,
+                    const int64_t* width, const int64_t* fall, int64_t t_hi, int64_t dt,
+                    const double* V, int64_t ldv, const KState* ks, const double* I, double lscale,
+                    double* grad, hipStream_t st)
+{
+    if (n_src <= 0) return;
+    k_adj_amp<<<(n_src + 255) / 256, 256, 0, st>>>(n_src, row, delay, rise, width, fall, t_hi, dt, V, ldv,
+                                                   ks, I, lscale, grad);
+}
+
+void launch_adj_jump(int n_rows, const int32_t* rows, const int32_t* ptr, const int32_t* pidx,
+                     const double* dJdx, int64_t n_out, int s, const double* cperm, double inv_scale,
+                     double* lam, hipStream_t st)
+{
+    if (n_rows <= 0) return;
+    k_adj_jump<<<(n_rows + 255) / 256, 256, 0, st>>>(n_rows, rows, ptr, pidx, dJdx, n_out, s, cperm, inv_scale,
+                                                     lam);
 }
 
 void launch_setup_v(int64_t n, const double* y, const double* y0, const double* z2, double* v,

@@ -106,6 +106,22 @@ void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* s
 void launch_resume(KState* ks, hipStream_t st);
 // sel = {0, last}: the first and the last check offset.
 void launch_set_ends(int32_t* sel, int last, hipStream_t st);
+
+// ---- adjoint ----------------------------------------------------------------
+// I[0 .. m) = int_0^tau e^{sH_m} e1 ds, I[MAXM .. MAXM + m) = int_0^tau s e^{sH_m} e1 ds
+// for the process's current basis (m <= MAXM - 2); zeros when m = 0.
+void launch_adj_integrals(const KState* ks, double gamma, double tau, double* I, hipStream_t st);
+// grad[k] += lscale * int over [t_hi - dt, t_hi] of u_k(t) lambda_{row_k}(t) dt
+// (pulses linear on the step; lambda = beta V e^{(t_hi - t) H} e1 carried
+// divided by lscale).
+void launch_adj_amp(int n_src, const int32_t* row, const int64_t* delay, const int64_t* rise,
+                    const int64_t* width, const int64_t* fall, int64_t t_hi, int64_t dt,
+                    const double* V, int64_t ldv, const KState* ks, const double* I, double lscale,
+                    double* grad, hipStream_t st);
+// lambda[rows[q]] += -(sum of dJdx[pidx[e], s]) / cperm[rows[q]] * inv_scale.
+void launch_adj_jump(int n_rows, const int32_t* rows, const int32_t* ptr, const int32_t* pidx,
+                     const double* dJdx, int64_t n_out, int s, const double* cperm, double inv_scale,
+                     double* lam, hipStream_t st);
 size_t checks_lds_bytes();
 
 // ---- segment set-up and reconstruction ------------------------------------

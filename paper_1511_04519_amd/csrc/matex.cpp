@@ -100,6 +100,7 @@ struct matex_factor_s {
     double gamma = 0.0;
     std::vector<double> gammas;       // shift ladder
     double vdd = 1.0;
+    std::vector<double> c_host;       // node capacitances, natural order
     int device = 0;
     // device structure
     DevMem d_c0, d_nc, d_nr, d_roff, d_w, d_u, d_rows, d_child_ptr, d_child_idx, d_relidx;
@@ -536,7 +537,7 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         if (nl->pad_node[k] < 0 || nl->pad_node[k] >= n) return fail(MATEX_E_INVALID, "pad node id");
         if (!(nl->pad_g[k] > 0.0)) return fail(MATEX_E_INVALID, "pad conductance must be > 0");
     }
-    int n_shifts = (opts && opts->n_shifts > 0) ? opts->n_shifts : 5;
+    int n_shifts = (opts && opts->n_shifts > 0) ? opts->n_shifts : 6;
     int leaf = (opts && opts->leaf_max > 0) ? opts->leaf_max : 16;
     if (n_shifts > 12) return fail(MATEX_E_INVALID, "n_shifts must be <= 12");
     try {
@@ -589,6 +590,7 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         std::vector<double> cperm(n);
         for (int64_t k = 0; k < n; ++k) cperm[k] = nl->c_node[s.perm[k]];
         F->d_cperm = upload(cperm);
+        F->c_host.assign(nl->c_node, nl->c_node + n);
         for (int k = 0; k <= n_shifts; ++k) {
             F->d_W.push_back(upload(Wh[k]));
             std::vector<double>().swap(Wh[k]);
@@ -1312,12 +1314,10 @@ void transient_batched(const matex_factor_s& F, const matex_problem* p, const ma
 
 }  // namespace
 
-extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p,
-                                        const matex_run_opts* o, double* d_probe_out,
-                                        double* d_final, matex_stats* stats, void* stream)
+// Argument checks shared by matex_transient and matex_adjoint.
+static matex_status check_problem(matex_factor_t f, const matex_problem* p, const matex_run_opts* o)
 {
-    const double t_start = now_s();
-    if (!f || !p || !o || !d_probe_out) return fail(MATEX_E_INVALID, "null argument");
+    if (!f || !p || !o) return fail(MATEX_E_INVALID, "null argument");
     const int64_t n = f->sym.n;
     if (p->n_src < 0 || p->n_out <= 0 || p->n_probe < 0 || p->t_end <= 0)
         return fail(MATEX_E_INVALID, "bad sizes");
@@ -1327,8 +1327,6 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     if (o->mode != MATEX_PLAIN && o->mode != MATEX_BATCHED) return fail(MATEX_E_INVALID, "unknown mode");
     if (o->m_max < 1 || o->m_max > MAXM) return fail(MATEX_E_INVALID, "m_max must be in 1..32");
     if (!(o->tol > 0.0)) return fail(MATEX_E_INVALID, "tol must be > 0");
-    const int64_t h_min = std::max<int64_t>(1, o->h_min);
-    const double shift_ratio = o->shift_ratio > 0.0 ? o->shift_ratio : 1.0;
     for (int32_t k = 0; k < p->n_src; ++k) {
         if (p->node[k] < 0 || p->node[k] >= n) return fail(MATEX_E_INVALID, "source node out of range");
         if (p->delay[k] < 0 || p->rise[k] <= 0 || p->fall[k] <= 0 || p->width[k] < 0)
@@ -1341,6 +1339,19 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     }
     for (int32_t k = 0; k < p->n_probe; ++k)
         if (p->probe[k] < 0 || p->probe[k] >= n) return fail(MATEX_E_INVALID, "probe out of range");
+    return MATEX_OK;
+}
+
+extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p,
+                                        const matex_run_opts* o, double* d_probe_out,
+                                        double* d_final, matex_stats* stats, void* stream)
+{
+    const double t_start = now_s();
+    if (!d_probe_out) return fail(MATEX_E_INVALID, "null argument");
+    if (matex_status cs = check_problem(f, p, o)) return cs;
+    const int64_t n = f->sym.n;
+    const int64_t h_min = std::max<int64_t>(1, o->h_min);
+    const double shift_ratio = o->shift_ratio > 0.0 ? o->shift_ratio : 1.0;
 
     // subtasks (Sec. 3.1)
     std::map<int32_t, std::vector<int32_t>> groups;
@@ -1582,10 +1593,165 @@ extern "C" matex_status matex_transient_many(int32_t n_inst, const matex_factor_
     return MATEX_OK;
 }
 
+// Adjoint sweep (continuous adjoint of C y' = -G y + i(t)): lambda is zero
+// after the last sample time, jumps by C^-1 g_s at every sample time t_s
+// (g_s = dJ/dy(t_s) = -dJ/dx(t_s) at the probes) and between them satisfies
+// C lambda' = G lambda, i.e. lambda(t_hi - sigma) = e^{sigma A} lambda(t_hi)
+// with the forward operator A = -C^-1 G: the same rational Krylov steps as
+// the forward run, backwards in time, with no input terms. Steps break at
+// the sample times and at every source's transition spots, so each pulse
+// is linear on a step and its amplitude gradient
+// dJ/da_k = int u_k(t) lambda_{n_k}(t) dt accumulates step by step from the
+// step's exact integrals of e^{sigma H} e1 and sigma e^{sigma H} e1.
 extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
                                       const double* d_dJdx, double* d_grad_amp, double* d_grad_c,
                                       void* stream)
 {
-    (void)f; (void)p; (void)o; (void)d_dJdx; (void)d_grad_amp; (void)d_grad_c; (void)stream;
-    return fail(MATEX_E_UNSUPPORTED, "matex_adjoint is not provided by this build");
+    if (!d_dJdx) return fail(MATEX_E_INVALID, "null argument");
+    if (matex_status cs = check_problem(f, p, o)) return cs;
+    if (o->m_max > MAXM - 2) return fail(MATEX_E_INVALID, "m_max must be <= 30 for the adjoint");
+    if (d_grad_c) return fail(MATEX_E_UNSUPPORTED, "capacitance gradients are not provided by this build");
+    const int64_t n = f->sym.n;
+    const int n_shifts = int(f->gammas.size());
+    const int32_t n_out = p->n_out, n_probe = p->n_probe, n_src = p->n_src;
+    const int64_t h_min = std::max<int64_t>(1, o->h_min);
+    const double ratio = o->shift_ratio > 0.0 ? o->shift_ratio : 1.0;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    try {
+        // sample times: output times > 0 whose column of dJ/dx is not zero
+        std::vector<double> g(size_t(n_probe) * n_out);
+        if (!g.empty())
+            HIPCHK(hipMemcpyAsync(g.data(), d_dJdx, sizeof(double) * g.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::map<int64_t, int32_t> sample;   // time -> output column
+        for (int32_t c = 0; c < n_out; ++c) {
+            if (p->t_out[c] <= 0) continue;
+            bool nz = false;
+            for (int32_t q = 0; q < n_probe && !nz; ++q) nz = g[size_t(q) * n_out + c] != 0.0;
+            if (nz) sample[p->t_out[c]] = c;
+        }
+        if (d_grad_amp && n_src > 0) HIPCHK(hipMemsetAsync(d_grad_amp, 0, sizeof(double) * n_src, st));
+        if (sample.empty() || n_src == 0) {
+            HIPCHK(hipStreamSynchronize(st));
+            return MATEX_OK;
+        }
+        const int64_t t_last = sample.rbegin()->first;
+        // lambda is carried divided by the largest jump norm max_s ||C^-1 g_s||,
+        // so the tolerance is relative to the strongest sensitivity
+        double lscale = 0.0;
+        for (auto& kv : sample) {
+            std::map<int32_t, double> jv;
+            for (int32_t q = 0; q < n_probe; ++q) jv[p->probe[q]] -= g[size_t(q) * n_out + kv.second];
+            double s2 = 0.0;
+            for (auto& e : jv) s2 += (e.second / f->c_host[e.first]) * (e.second / f->c_host[e.first]);
+            lscale = std::max(lscale, std::sqrt(s2));
+        }
+        // step boundaries below t_last: sample times and transition spots
+        std::vector<int64_t> bnd{0};
+        for (auto& kv : sample) bnd.push_back(kv.first);
+        for (int32_t k = 0; k < n_src; ++k) {
+            const int64_t d = p->delay[k], r = p->rise[k], w = p->width[k], fl = p->fall[k];
+            for (int64_t t : {d, d + r, d + r + w, d + r + w + fl})
+                if (t > 0 && t < t_last) bnd.push_back(t);
+        }
+        std::sort(bnd.begin(), bnd.end());
+        bnd.erase(std::unique(bnd.begin(), bnd.end()), bnd.end());
+        // probes grouped by permuted row (fixed summation order for repeats)
+        std::map<int32_t, std::vector<int32_t>> by_row;
+        for (int32_t q = 0; q < n_probe; ++q) by_row[f->sym.iperm[p->probe[q]]].push_back(q);
+        std::vector<int32_t> rows, ptr{0}, pidx;
+        for (auto& kv : by_row) {
+            rows.push_back(kv.first);
+            pidx.insert(pidx.end(), kv.second.begin(), kv.second.end());
+            ptr.push_back(int32_t(pidx.size()));
+        }
+        DevMem d_rows = upload(rows), d_ptr = upload(ptr), d_pidx = upload(pidx);
+        std::vector<int32_t> srow(n_src);
+        for (int32_t k = 0; k < n_src; ++k) srow[k] = f->sym.iperm[p->node[k]];
+        DevMem d_srow = upload(srow);
+        DevMem d_del = upload(std::vector<int64_t>(p->delay, p->delay + n_src));
+        DevMem d_ris = upload(std::vector<int64_t>(p->rise, p->rise + n_src));
+        DevMem d_wid = upload(std::vector<int64_t>(p->width, p->width + n_src));
+        DevMem d_fal = upload(std::vector<int64_t>(p->fall, p->fall + n_src));
+        Work wk(*f, 2);
+        PinnedMem pin(4096);
+        KsHost* hks = pin.as<KsHost>();
+        DevMem lam(sizeof(double) * n), zero(sizeof(double) * n), I(sizeof(double) * 2 * MAXM);
+        HIPCHK(hipMemsetAsync(lam.p, 0, lam.bytes, st));
+        HIPCHK(hipMemsetAsync(zero.p, 0, zero.bytes, st));
+        double* V = wk.V.as<double>();
+        const double* cperm = f->d_cperm.as<double>();
+        auto jump = [&](int64_t t) {
+            auto it = sample.find(t);
+            if (it != sample.end())
+                launch_adj_jump(int(rows.size()), d_rows.as<int32_t>(), d_ptr.as<int32_t>(), d_pidx.as<int32_t>(),
+                                d_dJdx, n_out, it->second, cperm, 1.0 / lscale, lam.as<double>(), st);
+        };
+        auto set_tau = [&](int64_t dt) {
+            HIPCHK(hipStreamSynchronize(st));
+            double* h = pin.as<double>() + 64;
+            *h = double(dt) * FS;
+            HIPCHK(hipMemcpyAsync(wk.taus.p, h, sizeof(double), hipMemcpyHostToDevice, st));
+        };
+        const char* trace_env = std::getenv("MATEX_TRACE");
+        const bool trace = trace_env && trace_env[0] == '1';
+        int m_guess = 6;
+        int64_t t_hi = t_last;
+        jump(t_hi);
+        // a jump puts weight on modes much faster than the steps; the step
+        // integrals need them resolved, so after a jump the steps grow
+        // geometrically from 1 fs (a step never exceeds the time since the
+        // jump), each with the shift of the ladder that fits it
+        int64_t since = 0;
+        size_t b = bnd.size() - 1;   // bnd[b] == t_last
+        while (t_hi > 0) {
+            while (bnd[b] >= t_hi) --b;
+            int64_t dt = std::min(t_hi - bnd[b], std::max<int64_t>(1, since));
+            int ksh = ladder_shift(f->gammas, dt, ratio);
+            set_tau(dt);
+            KsHost h{};
+            while (true) {
+                launch_setup_v(n, lam.as<double>(), zero.as<double>(), zero.as<double>(), V,
+                               wk.partial.as<double>(), wk.kst(), st);
+                launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
+                h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, m_guess, hks, st);
+                if (h.m > 0) m_guess = h.m;
+                if (h.converged || ksh + 1 == n_shifts) break;
+                ksh++;
+            }
+            if (trace)
+                fprintf(stderr, "[matex-adj] t_hi=%lld dt=%lld shift=%d m=%d conv=%d est=%.3e\n", (long long)t_hi,
+                        (long long)dt, ksh, h.m, h.converged, read_est(wk, pin.as<double>() + 128, st));
+            while (!h.converged) {
+                dt /= 2;
+                if (dt < h_min)
+                    return fail(MATEX_E_NOCONV, "adjoint: no convergence at t = " + std::to_string(t_hi) + " fs");
+                set_tau(dt);
+                launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), nullptr, 1, o->tol,
+                              wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
+                h = read_state(wk, hks, st);
+            }
+            if (d_grad_amp) {
+                launch_adj_integrals(wk.kst(), f->gammas[ksh], double(dt) * FS, I.as<double>(), st);
+                launch_adj_amp(n_src, d_srow.as<int32_t>(), d_del.as<int64_t>(), d_ris.as<int64_t>(),
+                               d_wid.as<int64_t>(), d_fal.as<int64_t>(), t_hi, dt, V, n, wk.kst(),
+                               I.as<double>(), lscale, d_grad_amp, st);
+            }
+            // lambda at the step's lower end
+            launch_recon_full(n, double(dt) * FS, wk.u.as<double>(), wk.kst(), V, n, lam.as<double>(),
+                              zero.as<double>(), zero.as<double>(), zero.as<double>(), st);
+            t_hi -= dt;
+            since += dt;
+            if (sample.count(t_hi)) since = 0;
+            jump(t_hi);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+        check_sweep(wk.sync, st);
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return fail(MATEX_E_OOM, "host allocation failed");
+    }
+    return MATEX_OK;
 }

@@ -162,7 +162,7 @@ class FactorHandle:
             self.handle = None
 
 
-def matex_factor(netlist, gamma: float, n_shifts: int = 5, leaf_max: int = 16,
+def matex_factor(netlist, gamma: float, n_shifts: int = 6, leaf_max: int = 16,
                  use_coords: bool = True) -> FactorHandle:
     """Factor C + gamma_k G for the shift ladder and G (see matex.h)."""
     a = np.ascontiguousarray(netlist.br_a, np.int32)
@@ -279,14 +279,18 @@ def matex_time_solves(f: FactorHandle, which: int = 0, reps: int = 50, nrhs: int
     return sec.value, byt.value
 
 
-def matex_adjoint(f: FactorHandle, prob, dJdx, tol: float = 1e-11, m_max: int = 20):
-    """Gradients of a droop objective (not provided by this build: raises)."""
+def matex_adjoint(f: FactorHandle, prob, dJdx, tol: float = 1e-10, m_max: int = 30,
+                  h_min: int = 1, grad_c: bool = False, shift_ratio: float = 1.0):
+    """Gradients of an objective J of the probe voltages. dJdx: device tensor
+    (n_probe, n_out) = dJ/dx at the probes and output times. Returns
+    (dJ/d amplitude (n_src,), dJ/d c (n,) or None)."""
     import torch
     keep = []
     pr = _problem_struct(prob, keep)
-    ga = torch.empty(prob.sources.n_src, dtype=torch.float64, device=dJdx.device)
-    gc = torch.empty(f.info["n"], dtype=torch.float64, device=dJdx.device)
-    opts = RunOpts(float(tol), int(m_max), MATEX_PLAIN, 1, 1.0)
-    _check(lib().matex_adjoint(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(dJdx), _ptr(ga),
+    d = dJdx.contiguous()
+    ga = torch.empty(prob.sources.n_src, dtype=torch.float64, device=d.device)
+    gc = torch.empty(f.info["n"], dtype=torch.float64, device=d.device) if grad_c else None
+    opts = RunOpts(float(tol), int(m_max), MATEX_PLAIN, int(h_min), float(shift_ratio))
+    _check(lib().matex_adjoint(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(d), _ptr(ga),
                                _ptr(gc), _stream()))
     return ga, gc

@@ -349,3 +349,68 @@ def test_trapezoidal_second_order():
         yt, _, _ = R.trapezoidal(p, h)
         e.append(np.abs(yt - ym).max())
     assert 3.5 < e[0] / e[1] < 4.5
+
+
+# ------------------------------------------------------------- P14 adjoint
+
+def _rc_pulse_case():
+    c, g = 2e-14, 0.5
+    nl = single_rc(c, g)
+    src = sources([0], [1e-3], [50], [30], [100], [40])
+    p = problem(nl, src, 400, step=10)          # times in fs
+    w = np.random.default_rng(14).standard_normal((1, p.t_out.size))
+    return c, g, p, w
+
+
+def _rc_ramps(c, g, t, a, d, r, w, f):
+    """Closed-form droop of one RC node under a trapezoid (four ramps) and its
+    derivative in c: rho(u) = (u - tau (1 - e^-u/tau)) / g, tau = c / g,
+    d rho / d c = (-1 + e^-u/tau (1 + u/tau)) / g^2."""
+    tau = c / g
+    y = np.zeros_like(t, dtype=float)
+    dy = np.zeros_like(t, dtype=float)
+    for t0, s in ((d, 1 / r), (d + r, -1 / r), (d + r + w, -1 / f), (d + r + w + f, 1 / f)):
+        u = np.maximum(t - t0, 0.0) * 1e-15
+        s = s * 1e15 * a
+        e = np.exp(-u / tau)
+        y += s * (u - tau * (1 - e)) / g
+        dy += s * np.where(u > 0, -1 + e * (1 + u / tau), 0.0) / g ** 2
+    return y, dy
+
+
+def test_P14_amplitude_gradient_single_rc_closed_form():
+    from oracle import adjoint as A
+    c, g, p, w = _rc_pulse_case()
+    y, _ = _rc_ramps(c, g, p.t_out.astype(float), 1.0, 50, 30, 100, 40)
+    # J = sum w x, x = Vdd - a y_unit: dJ/da = -sum w y_unit
+    assert np.isclose(A.amp_gradient(p, w)[0], -np.sum(w[0] * y), rtol=1e-12, atol=0)
+
+
+def test_P14_capacitance_gradient_single_rc_closed_form():
+    from oracle import adjoint as A
+    c, g, p, w = _rc_pulse_case()
+    _, dy = _rc_ramps(c, g, p.t_out.astype(float), 1e-3, 50, 30, 100, 40)
+    fd = A.c_gradient_fd(p, lambda x: float(np.sum(w * x)))[0]
+    exact = -np.sum(w[0] * dy)
+    assert abs(fd - exact) <= 1e-7 * abs(exact)
+
+
+def test_P14_amplitude_gradient_is_the_derivative_on_a_mesh():
+    """J linear in x, so J is linear in each amplitude: a central difference
+    in a_k is exact up to rounding and pins the bookkeeping (signs, probe and
+    time layout) of the linearity route."""
+    import dataclasses
+    from oracle import adjoint as A
+    p = I.small(14, layers=2, nx=5, ny=4, n_src=4, t_end=1 * I.NS)
+    w = np.random.default_rng(5).standard_normal((p.probe.size, p.t_out.size))
+    J = lambda x: float(np.sum(w * x))  # noqa: E731
+    grad = A.amp_gradient(p, w)
+    for k in range(p.sources.n_src):
+        fd = []
+        for sgn in (1, -1):
+            amp = p.sources.amp.copy()
+            amp[k] += sgn * 1e-4
+            q = dataclasses.replace(p, sources=dataclasses.replace(p.sources, amp=amp))
+            fd.append(J(A.x_probes(q)))
+        d = (fd[0] - fd[1]) / 2e-4
+        assert abs(d - grad[k]) <= 1e-6 * abs(grad).max()
