@@ -168,6 +168,9 @@ typedef struct {
     int64_t h_min;           /* smallest step after halving (fs), >= 1           */
     double shift_ratio;      /* ladder rule: a step uses the largest gamma_k with
                                 tau_1 >= shift_ratio * gamma_k (0 = default 1.0)  */
+    int32_t output_droop;    /* 0: outputs are x = Vdd - y; 1: the droop y itself
+                                (no supply offset, full relative precision)     */
+    int32_t reserved_;       /* 0                                                */
 } matex_run_opts;
 
 typedef struct {
@@ -186,7 +189,8 @@ typedef struct {
 
 /*
  * matex_transient - Alg. 2 for every subtask of the problem, summed by
- * superposition (Sec. 3.1-3.2). Writes x = Vdd - sum_k y_k at the probes:
+ * superposition (Sec. 3.1-3.2). Writes x = Vdd - sum_k y_k (or the droop
+ * sum_k y_k with o->output_droop) at the probes:
  * d_probe_out device [n_probe][n_out] (row-major), and, if d_final is not
  * NULL, x(t_end) at every node: device [n], natural order. Each subtask
  * starts from y_k(0) = G^-1 i_k(0) = 0 (no source draws current at t = 0).

@@ -36,8 +36,8 @@ def pade_coefficients(m: int) -> np.ndarray:
 def pade(A: np.ndarray, m: int) -> np.ndarray:
     c = pade_coefficients(m)
     n = A.shape[0]
-    P = np.zeros((n, n))
-    Q = np.zeros((n, n))
+    P = np.zeros((n, n), dtype=A.dtype)
+    Q = np.zeros((n, n), dtype=A.dtype)
     Ak = np.eye(n)
     for j in range(m + 1):
         if j > 0:
@@ -48,7 +48,9 @@ def pade(A: np.ndarray, m: int) -> np.ndarray:
 
 
 def expm(A: np.ndarray) -> np.ndarray:
-    A = np.asarray(A, dtype=np.float64)
+    """e^A in float64, or complex128 for a complex A (the method is the same;
+    complex input serves complex-step differentiation)."""
+    A = np.asarray(A, dtype=np.complex128 if np.iscomplexobj(A) else np.float64)
     if A.size == 0:
         return A.copy()
     nrm = np.abs(A).sum(axis=0).max()

@@ -568,23 +568,24 @@ __global__ void kb_events(int cnt, int R, const int32_t* row, const int32_t* col
     if (k < cnt) s[int64_t(row[k]) * R + col[k]] += d[k];
 }
 
-// Superposition of one batch (Sec. 3.1): out[p, t] -= sum_r Yout[r, p, t];
-// final[perm[i]] -= sum_r y[i, r] (the outputs start at Vdd).
-__global__ void kb_sum_out(int64_t count, int R, const double* Yout, double* out)
+// Superposition of one batch (Sec. 3.1): out[p, t] += sgn * sum_r Yout[r, p, t];
+// final[perm[i]] += sgn * sum_r y[i, r].
+__global__ void kb_sum_out(int64_t count, int R, const double* Yout, double sgn, double* out)
 {
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < count; i += int64_t(gridDim.x) * 256) {
         double acc = 0.0;
         for (int r = 0; r < R; ++r) acc += Yout[int64_t(r) * count + i];
-        out[i] -= acc;
+        out[i] += sgn * acc;
     }
 }
 
-__global__ void kb_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double* out)
+__global__ void kb_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double sgn,
+                             double* out)
 {
     for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
         double acc = 0.0;
         for (int r = 0; r < R; ++r) acc += y[i * R + r];
-        out[perm[i]] -= acc;
+        out[perm[i]] += sgn * acc;
     }
 }
 
@@ -682,16 +683,17 @@ void launch_b_events(int cnt, int R, const int32_t* row, const int32_t* col, con
     kb_events<<<(cnt + 255) / 256, 256, 0, st>>>(cnt, R, row, col, d, s);
 }
 
-void launch_b_sum_out(int64_t count, int R, const double* Yout, double* out, hipStream_t st)
+void launch_b_sum_out(int64_t count, int R, const double* Yout, double sgn, double* out,
+                      hipStream_t st)
 {
     if (count <= 0) return;
-    kb_sum_out<<<grid_rows(count, 256), 256, 0, st>>>(count, R, Yout, out);
+    kb_sum_out<<<grid_rows(count, 256), 256, 0, st>>>(count, R, Yout, sgn, out);
 }
 
-void launch_b_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double* out,
-                        hipStream_t st)
+void launch_b_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double sgn,
+                        double* out, hipStream_t st)
 {
-    kb_sum_final<<<grid_rows(n, 256), 256, 0, st>>>(n, R, perm, y, out);
+    kb_sum_final<<<grid_rows(n, 256), 256, 0, st>>>(n, R, perm, y, sgn, out);
 }
 
 void launch_b_interleave(int64_t n, int R, const int32_t* perm, const double* src, double* dst,

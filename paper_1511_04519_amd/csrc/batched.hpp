@@ -87,10 +87,11 @@ void launch_b_recon_full(int64_t n, int R, const double* col_tau, const int32_t*
                          hipStream_t st);
 void launch_b_events(int cnt, int R, const int32_t* row, const int32_t* col, const double* d,
                      double* s, hipStream_t st);
-// out -= sum over the batch's subtasks (outputs are filled with Vdd first).
-void launch_b_sum_out(int64_t count, int R, const double* Yout, double* out, hipStream_t st);
-void launch_b_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double* out,
-                        hipStream_t st);
+// out += sgn * (sum over the batch's subtasks).
+void launch_b_sum_out(int64_t count, int R, const double* Yout, double sgn, double* out,
+                      hipStream_t st);
+void launch_b_sum_final(int64_t n, int R, const int32_t* perm, const double* y, double sgn,
+                        double* out, hipStream_t st);
 void launch_b_fill(int64_t count, double v, double* x, hipStream_t st);
 // Column-major natural order (leading dimension n) <-> row-interleaved
 // permuted order for R right-hand sides.

@@ -104,95 +104,103 @@ static __constant__ double PADE13[14] = {
     182.0,               1.0};
 constexpr double THETA13 = 5.371920351148152;
 
-// C = A * B (m x m, row-major, stride LD) by the whole block.
+// The small dense routines take their row stride L as a template argument:
+// L = LD for matrices in LDS (at most MAXM rows), a larger L for matrices in
+// a global-memory workspace. A matrix buffer holds (L - 1) x L doubles.
+
+// C = A * B (m x m, row-major, stride L) by the whole block.
+template <int L = LD>
 __device__ inline void mm(const double* A, const double* B, double* C, int m)
 {
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
         const int i = idx / m, j = idx - (idx / m) * m;
         double s = 0.0;
-        for (int k = 0; k < m; ++k) s += A[i * LD + k] * B[k * LD + j];
-        C[i * LD + j] = s;
+        for (int k = 0; k < m; ++k) s += A[i * L + k] * B[k * L + j];
+        C[i * L + j] = s;
     }
     __syncthreads();
 }
 
 // Solve Q X = P in place (X overwrites P) by Gaussian elimination with partial
 // pivoting; Q is destroyed. Whole block.
+template <int L = LD>
 __device__ inline void solve_inplace(double* Q, double* P, int m, int ncol)
 {
     __shared__ int piv;
     for (int k = 0; k < m; ++k) {
         if (threadIdx.x == 0) {
             int p = k;
-            double best = fabs(Q[k * LD + k]);
+            double best = fabs(Q[k * L + k]);
             for (int i = k + 1; i < m; ++i)
-                if (fabs(Q[i * LD + k]) > best) { best = fabs(Q[i * LD + k]); p = i; }
+                if (fabs(Q[i * L + k]) > best) { best = fabs(Q[i * L + k]); p = i; }
             piv = p;
         }
         __syncthreads();
         const int p = piv;
         if (p != k) {
             for (int j = threadIdx.x; j < m; j += blockDim.x) {
-                const double t = Q[k * LD + j]; Q[k * LD + j] = Q[p * LD + j]; Q[p * LD + j] = t;
+                const double t = Q[k * L + j]; Q[k * L + j] = Q[p * L + j]; Q[p * L + j] = t;
             }
             for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
-                const double t = P[k * LD + j]; P[k * LD + j] = P[p * LD + j]; P[p * LD + j] = t;
+                const double t = P[k * L + j]; P[k * L + j] = P[p * L + j]; P[p * L + j] = t;
             }
         }
         __syncthreads();
-        const double dk = Q[k * LD + k];
+        const double dk = Q[k * L + k];
         const int rows = m - k - 1;
         for (int idx = threadIdx.x; idx < rows * (m - k + ncol); idx += blockDim.x) {
             const int i = k + 1 + idx / (m - k + ncol);
             const int c = idx % (m - k + ncol);
-            const double f = Q[i * LD + k] / dk;
-            if (c < m - k) { if (c > 0) Q[i * LD + k + c] -= f * Q[k * LD + k + c]; }
-            else P[i * LD + (c - (m - k))] -= f * P[k * LD + (c - (m - k))];
+            const double f = Q[i * L + k] / dk;
+            if (c < m - k) { if (c > 0) Q[i * L + k + c] -= f * Q[k * L + k + c]; }
+            else P[i * L + (c - (m - k))] -= f * P[k * L + (c - (m - k))];
         }
         __syncthreads();
-        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) Q[i * LD + k] = 0.0;
+        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) Q[i * L + k] = 0.0;
         __syncthreads();
     }
     // back substitution, one column per thread
     for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
         for (int i = m - 1; i >= 0; --i) {
-            double s = P[i * LD + j];
-            for (int k = i + 1; k < m; ++k) s -= Q[i * LD + k] * P[k * LD + j];
-            P[i * LD + j] = s / Q[i * LD + i];
+            double s = P[i * L + j];
+            for (int k = i + 1; k < m; ++k) s -= Q[i * L + k] * P[k * L + j];
+            P[i * L + j] = s / Q[i * L + i];
         }
     }
     __syncthreads();
 }
 
-// H = (I - Ht_m^-1) / gamma into H (row-major, stride LD); uses T1, T2.
+// H = (I - Ht_m^-1) / gamma into H (row-major, stride L); uses T1.
+template <int L = LD>
 __device__ inline void form_h(const KState* ks, int m, double gamma, double* H, double* T1)
 {
-    for (int idx = threadIdx.x; idx < m * LD; idx += blockDim.x) {
-        const int i = idx / LD, j = idx % LD;
+    for (int idx = threadIdx.x; idx < m * L; idx += blockDim.x) {
+        const int i = idx / L, j = idx % L;
         T1[idx] = (j < m) ? ks->Ht[i + j * (MAXM + 1)] : 0.0;
         H[idx] = (j < m && i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    solve_inplace(T1, H, m, m);           // H = Ht^-1
+    solve_inplace<L>(T1, H, m, m);        // H = Ht^-1
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
         const int i = idx / m, j = idx % m;
-        H[i * LD + j] = ((i == j ? 1.0 : 0.0) - H[i * LD + j]) / gamma;
+        H[i * L + j] = ((i == j ? 1.0 : 0.0) - H[i * L + j]) / gamma;
     }
     __syncthreads();
 }
 
-// e^{tau H} (m x m, row-major, stride LD; m <= MAXM). Uses 6 matrices of
-// MAXM x LD in `buf`; H is overwritten (its storage holds V of the
+// e^{tau H} (m x m, row-major, stride L; m <= L - 1). Uses 6 matrices of
+// (L - 1) x L in `buf`; H is overwritten (its storage holds V of the
 // approximant once A = tau H / 2^s). Returns the matrix holding the result
 // (inside buf), valid until buf is reused.
+template <int L = LD>
 __device__ inline double* expm_mat(double* H, int m, double tau, double* buf)
 {
     double* A = buf;
-    double* A2 = A + MAXM * LD;
-    double* A4 = A2 + MAXM * LD;
-    double* A6 = A4 + MAXM * LD;
-    double* T = A6 + MAXM * LD;
-    double* Um = T + MAXM * LD;
+    double* A2 = A + (L - 1) * L;
+    double* A4 = A2 + (L - 1) * L;
+    double* A6 = A4 + (L - 1) * L;
+    double* T = A6 + (L - 1) * L;
+    double* Um = T + (L - 1) * L;
     double* Vm = H;
     __shared__ double nrm;
     __shared__ int sq;
@@ -201,56 +209,58 @@ __device__ inline double* expm_mat(double* H, int m, double tau, double* buf)
         double best = 0.0;
         for (int j = 0; j < m; ++j) {
             double c = 0.0;
-            for (int i = 0; i < m; ++i) c += fabs(H[i * LD + j]);
+            for (int i = 0; i < m; ++i) c += fabs(H[i * L + j]);
             best = fmax(best, c);
         }
         nrm = best * tau;
+        // a non-finite norm gives no squarings (the result is then NaN, as
+        // it must be) instead of an unbounded count
         int s = 0;
-        if (nrm > THETA13) s = int(ceil(log2(nrm / THETA13)));
-        sq = s;
+        if (nrm > THETA13 && nrm < 1e300) s = int(ceil(log2(nrm / THETA13)));
+        sq = min(s, 1100);
     }
     __syncthreads();
     const double scl = tau * ldexp(1.0, -sq);
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
         const int i = idx / m, j = idx % m;
-        A[i * LD + j] = H[i * LD + j] * scl;
+        A[i * L + j] = H[i * L + j] * scl;
     }
     __syncthreads();
-    mm(A, A, A2, m);
-    mm(A2, A2, A4, m);
-    mm(A4, A2, A6, m);
+    mm<L>(A, A, A2, m);
+    mm<L>(A2, A2, A4, m);
+    mm<L>(A4, A2, A6, m);
     const double* b = PADE13;
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-        const int i = idx / m, j = idx % m, o = i * LD + j;
+        const int i = idx / m, j = idx % m, o = i * L + j;
         T[o] = b[13] * A6[o] + b[11] * A4[o] + b[9] * A2[o];
     }
     __syncthreads();
-    mm(A6, T, Um, m);
+    mm<L>(A6, T, Um, m);
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-        const int i = idx / m, j = idx % m, o = i * LD + j;
+        const int i = idx / m, j = idx % m, o = i * L + j;
         T[o] = Um[o] + b[7] * A6[o] + b[5] * A4[o] + b[3] * A2[o] + (i == j ? b[1] : 0.0);
     }
     __syncthreads();
-    mm(A, T, Um, m);                        // U
+    mm<L>(A, T, Um, m);                        // U
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-        const int i = idx / m, j = idx % m, o = i * LD + j;
+        const int i = idx / m, j = idx % m, o = i * L + j;
         T[o] = b[12] * A6[o] + b[10] * A4[o] + b[8] * A2[o];
     }
     __syncthreads();
-    mm(A6, T, Vm, m);
+    mm<L>(A6, T, Vm, m);
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
-        const int i = idx / m, j = idx % m, o = i * LD + j;
+        const int i = idx / m, j = idx % m, o = i * L + j;
         const double v = Vm[o] + b[6] * A6[o] + b[4] * A4[o] + b[2] * A2[o] + (i == j ? b[0] : 0.0);
         const double uu = Um[o];
         A2[o] = v - uu;   // Q
         A4[o] = v + uu;   // P
     }
     __syncthreads();
-    solve_inplace(A2, A4, m, m);            // R = Q^-1 P in A4
+    solve_inplace<L>(A2, A4, m, m);            // R = Q^-1 P in A4
     double* R = A4;
     double* S = A6;
     for (int k = 0; k < sq; ++k) {
-        mm(R, R, S, m);
+        mm<L>(R, R, S, m);
         double* t = R; R = S; S = t;
     }
     return R;

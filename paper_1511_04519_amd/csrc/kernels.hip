@@ -710,12 +710,241 @@ __global__ void k_adj_jump(int n_rows, const int32_t* __restrict__ rows, const i
     lam[rows[q]] += g / cperm[rows[q]] * inv_scale;
 }
 
+// Capacitance gradient, integrated by parts:
+//   dJ/dc_i = (1/c_i) (-sum_s g_{s,i} y_i(t_s) + int (G lambda)_i y_i dt),
+// so only values of the forward droop y are needed (no derivative of its
+// Krylov approximation). One overlap [t1, t2] of an adjoint step
+// (lambda(t) = beta_l V_l e^{(t_hi - t) H_l} e1) and a forward segment
+// (y(t) = beta_f V_f e^{(t - t_a) H_f} e1 + y0 + (t - t_a) z1 - z2) needs, with
+// h = t2 - t1, a = e^{(t_hi - t2) H_l} e1, b = e^{(t1 - t_a) H_f} e1, s = t - t1:
+//   W  = int (e^{(t_hi-t) H_l} e1)(e^{(t-t_a) H_f} e1)^T dt
+//   q0 = int e^{(t_hi-t) H_l} e1 dt,  q1 = int (t - t_a) e^{(t_hi-t) H_l} e1 dt.
+// All three are the top-right block of exp(h T), T = [[A, B], [0, D]] with
+// A = H_l, B = [a b^T, a, 0], D = [[H_f^T, 0, 0], [0, 0, 1], [0, 0, 0]]
+// (Van Loan 1978): W is its first mf columns, q0 the next, and the last is
+// int_0^h s e^{(h-s) H_l} a ds, so q1 = (t1 - t_a) q0 + that. The exponential
+// is taken block by block, each block at most MAXM wide in LDS: Taylor's
+// series in Horner form on T / 2^s with ||T / 2^s||_1 <= 1/2 (18 terms), then
+// s squarings [[Xa, Xb], [0, Xd]]^2 = [[Xa^2, Xa Xb + Xb Xd], [0, Xd^2]].
+// Wq: W row-major (stride MAXM), then q0, then q1 (MAXM each).
+constexpr int CG_TERMS = 18;
+
+// C (r x c) = A (r x k) B (k x c), or += with acc; row-major stride LD.
+__device__ inline void mm_rect(const double* A, const double* B, double* C, int r, int k, int c, bool acc)
+{
+    for (int idx = threadIdx.x; idx < r * c; idx += blockDim.x) {
+        const int i = idx / c, j = idx - (idx / c) * c;
+        double s = acc ? C[i * LD + j] : 0.0;
+        for (int q = 0; q < k; ++q) s += A[i * LD + q] * B[q * LD + j];
+        C[i * LD + j] = s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_cg_block(const KState* kl, double gam_l, const KState* kf,
+                                                  double gam_f, double sig_b, double tau_a, double h,
+                                                  double* Wq)
+{
+    extern __shared__ double sm[];
+    constexpr int BS = MAXM * LD;
+    double* blk[7];
+    for (int q = 0; q < 7; ++q) blk[q] = sm + q * BS;
+    double* va = sm + 7 * BS;
+    double* vb = va + MAXM;
+    __shared__ double nrm;
+    __shared__ int sq;
+    const int ml = kl->m, mf = kf->m;   // mf = 0: a forward segment with no Krylov part
+    if (ml == 0) {
+        for (int i = threadIdx.x; i < MAXM * MAXM + 2 * MAXM; i += blockDim.x) Wq[i] = 0.0;
+        return;
+    }
+    const int na = ml, nd = mf + 2;
+    // a and b
+    form_h(kl, ml, gam_l, blk[0], blk[1]);
+    expm_e1(blk[0], ml, sig_b, blk[1], va);
+    if (mf > 0) {
+        form_h(kf, mf, gam_f, blk[0], blk[1]);
+        expm_e1(blk[0], mf, tau_a, blk[1], vb);
+    }
+    // A = H_l in blk0, D in blk2 (H_f^T from blk1), B in blk3
+    form_h(kl, ml, gam_l, blk[0], blk[1]);
+    if (mf > 0) form_h(kf, mf, gam_f, blk[1], blk[4]);
+    for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) {
+        const int i = idx / nd, j = idx % nd;
+        double v = 0.0;
+        if (i < mf && j < mf) v = blk[1][j * LD + i];
+        else if (i == mf && j == mf + 1) v = 1.0;
+        blk[2][i * LD + j] = v;
+    }
+    for (int idx = threadIdx.x; idx < na * nd; idx += blockDim.x) {
+        const int i = idx / nd, j = idx % nd;
+        blk[3][i * LD + j] = j < mf ? va[i] * vb[j] : (j == mf ? va[i] : 0.0);
+    }
+    __syncthreads();
+    double* A = blk[0];
+    double* D = blk[2];
+    double* B = blk[3];
+    // scale: ||h T||_1 / 2^s <= 1/2
+    if (threadIdx.x == 0) {
+        double best = 0.0;
+        for (int j = 0; j < na; ++j) {
+            double c = 0.0;
+            for (int i = 0; i < na; ++i) c += fabs(A[i * LD + j]);
+            best = fmax(best, c);
+        }
+        for (int j = 0; j < nd; ++j) {
+            double c = 0.0;
+            for (int i = 0; i < na; ++i) c += fabs(B[i * LD + j]);
+            for (int i = 0; i < nd; ++i) c += fabs(D[i * LD + j]);
+            best = fmax(best, c);
+        }
+        nrm = best * h;
+        sq = (nrm > 0.5 && nrm < 1e300) ? min(int(ceil(log2(nrm / 0.5))), 1100) : 0;
+    }
+    __syncthreads();
+    const double scl = h * ldexp(1.0, -sq);
+    for (int idx = threadIdx.x; idx < MAXM * LD; idx += blockDim.x) {
+        A[idx] *= scl;
+        B[idx] *= scl;
+        D[idx] *= scl;
+    }
+    __syncthreads();
+    // Horner: X = I; X = I + (T / k) X for k = CG_TERMS .. 1
+    double* Xa = blk[4];
+    double* Xb = blk[5];
+    double* Xd = blk[6];
+    double* T1 = blk[1];
+    for (int idx = threadIdx.x; idx < MAXM * LD; idx += blockDim.x) {
+        const int i = idx / LD, j = idx % LD;
+        Xa[idx] = (i == j) ? 1.0 : 0.0;
+        Xd[idx] = (i == j) ? 1.0 : 0.0;
+        Xb[idx] = 0.0;
+    }
+    __syncthreads();
+    for (int k = CG_TERMS; k >= 1; --k) {
+        const double ik = 1.0 / double(k);
+        mm_rect(A, Xb, T1, na, na, nd, false);
+        mm_rect(B, Xd, T1, na, nd, nd, true);
+        for (int idx = threadIdx.x; idx < na * nd; idx += blockDim.x) {
+            const int i = idx / nd, j = idx % nd;
+            Xb[i * LD + j] = T1[i * LD + j] * ik;
+        }
+        __syncthreads();
+        mm_rect(A, Xa, T1, na, na, na, false);
+        for (int idx = threadIdx.x; idx < na * na; idx += blockDim.x) {
+            const int i = idx / na, j = idx % na;
+            Xa[i * LD + j] = (i == j ? 1.0 : 0.0) + T1[i * LD + j] * ik;
+        }
+        __syncthreads();
+        mm_rect(D, Xd, T1, nd, nd, nd, false);
+        for (int idx = threadIdx.x; idx < nd * nd; idx += blockDim.x) {
+            const int i = idx / nd, j = idx % nd;
+            Xd[i * LD + j] = (i == j ? 1.0 : 0.0) + T1[i * LD + j] * ik;
+        }
+        __syncthreads();
+    }
+    // squarings (A, B, D buffers are free now)
+    double* SA = A;
+    double* SD = D;
+    for (int q = 0; q < sq; ++q) {
+        mm_rect(Xa, Xb, T1, na, na, nd, false);
+        mm_rect(Xb, Xd, T1, na, nd, nd, true);
+        mm_rect(Xa, Xa, SA, na, na, na, false);
+        mm_rect(Xd, Xd, SD, nd, nd, nd, false);
+        double* t;
+        t = Xb; Xb = T1; T1 = t;
+        t = Xa; Xa = SA; SA = t;
+        t = Xd; Xd = SD; SD = t;
+    }
+    for (int idx = threadIdx.x; idx < MAXM * MAXM; idx += blockDim.x) {
+        const int i = idx / MAXM, j = idx % MAXM;
+        Wq[idx] = (i < ml && j < mf) ? Xb[i * LD + j] : 0.0;
+    }
+    for (int i = threadIdx.x; i < MAXM; i += blockDim.x) {
+        const double q0 = i < ml ? Xb[i * LD + mf] : 0.0;
+        const double m1 = i < ml ? Xb[i * LD + mf + 1] : 0.0;
+        Wq[MAXM * MAXM + i] = q0;
+        Wq[MAXM * MAXM + MAXM + i] = tau_a * q0 + m1;
+    }
+}
+
+// GV[:, j] = G V[:, j] for j < m (G in CSR, rows in the factor's order).
+__global__ void k_spmv_cols(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                            const double* __restrict__ gv, const double* __restrict__ V, int64_t ldv,
+                            const KState* ks, double* GV)
+{
+    const int m = ks->m;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        const int a = rp[i], b = rp[i + 1];
+        for (int j = 0; j < m; ++j) {
+            double acc = 0.0;
+            for (int q = a; q < b; ++q) acc += gv[q] * V[int64_t(j) * ldv + ci[q]];
+            GV[int64_t(j) * ldv + i] = acc;
+        }
+    }
+}
+
+// gc[i] += lscale beta_l / c_i * sum_j GV_l[i, j] (beta_f (W V_f[i, :]^T)_j
+//          + q0_j (y0_i - z2_i) + q1_j z1_i) for every row i (permuted order).
+__global__ __launch_bounds__(256) void k_cg_nodes(int64_t n, const double* __restrict__ GVl,
+                                                  const double* __restrict__ Vf, int64_t ldv,
+                                                  const KState* kl, const KState* kf,
+                                                  const double* __restrict__ y0,
+                                                  const double* __restrict__ z1,
+                                                  const double* __restrict__ z2,
+                                                  const double* __restrict__ cperm,
+                                                  const double* __restrict__ Wq, double lscale,
+                                                  double* gc)
+{
+    __shared__ double Ws[MAXM * MAXM + 2 * MAXM];
+    const int ml = kl->m, mf = kf->m;
+    for (int i = threadIdx.x; i < MAXM * MAXM + 2 * MAXM; i += blockDim.x) Ws[i] = Wq[i];
+    __syncthreads();
+    if (ml == 0) return;
+    const double bl = kl->beta, bf = kf->beta;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+        double vf[MAXM];
+#pragma unroll
+        for (int k = 0; k < MAXM; ++k) vf[k] = k < mf ? Vf[int64_t(k) * ldv + i] : 0.0;
+        const double d0 = y0[i] - z2[i], d1 = z1[i];
+        double acc = 0.0;
+        for (int j = 0; j < ml; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int k = 0; k < MAXM; ++k) t += Ws[j * MAXM + k] * vf[k];
+            acc += GVl[int64_t(j) * ldv + i] *
+                   (bf * t + Ws[MAXM * MAXM + j] * d0 + Ws[MAXM * MAXM + MAXM + j] * d1);
+        }
+        gc[i] += lscale * bl * acc / cperm[i];
+    }
+}
+
+// Restarts a Krylov process from a recorded normalised start vector (already
+// in V_0) and its norm: the state k_normalize_v leaves.
+__global__ void k_restore_start(KState* ks, const double* beta)
+{
+    if (threadIdx.x == 0) {
+        const double b = *beta;
+        ks->beta = b;
+        ks->m = 0;
+        ks->breakdown = 0;
+        ks->converged = b == 0.0 ? 1 : 0;
+        ks->done = b == 0.0 ? 1 : 0;
+        ks->est = 0.0;
+    }
+}
+
 __global__ void k_resume(KState* ks)
 {
     if (threadIdx.x == 0) {
         ks->done = 0;
         ks->converged = 0;
     }
+}
+
+void launch_restore_start(KState* ks, const double* beta, hipStream_t st)
+{
+    k_restore_start<<<1, 64, 0, st>>>(ks, beta);
 }
 
 void launch_resume(KState* ks, hipStream_t st)
@@ -749,6 +978,26 @@ void launch_adj_amp(int n_src, const int32_t* row, const int64_t* delay, const i
     if (n_src <= 0) return;
     k_adj_amp<<<(n_src + 255) / 256, 256, 0, st>>>(n_src, row, delay, rise, width, fall, t_hi, dt, V, ldv,
                                                    ks, I, lscale, grad);
+}
+
+void launch_cg_block(const KState* kl, double gam_l, const KState* kf, double gam_f, double sig_b,
+                     double tau_a, double h, double* Wq, hipStream_t st)
+{
+    k_cg_block<<<1, 256, sizeof(double) * (7 * MAXM * LD + 2 * MAXM), st>>>(kl, gam_l, kf, gam_f, sig_b, tau_a,
+                                                                         h, Wq);
+}
+
+void launch_spmv_cols(int64_t n, const int32_t* rp, const int32_t* ci, const double* gv,
+                      const double* V, int64_t ldv, const KState* ks, double* GV, hipStream_t st)
+{
+    k_spmv_cols<<<grid_for(n), 256, 0, st>>>(n, rp, ci, gv, V, ldv, ks, GV);
+}
+
+void launch_cg_nodes(int64_t n, const double* GVl, const double* Vf, int64_t ldv, const KState* kl,
+                     const KState* kf, const double* y0, const double* z1, const double* z2,
+                     const double* cperm, const double* Wq, double lscale, double* gc, hipStream_t st)
+{
+    k_cg_nodes<<<grid_for(n), 256, 0, st>>>(n, GVl, Vf, ldv, kl, kf, y0, z1, z2, cperm, Wq, lscale, gc);
 }
 
 void launch_adj_jump(int n_rows, const int32_t* rows, const int32_t* ptr, const int32_t* pidx,

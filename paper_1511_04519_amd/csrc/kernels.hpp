@@ -104,6 +104,8 @@ void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* s
 // Lets a process whose check subset passed but whose full check set did not
 // continue iterating.
 void launch_resume(KState* ks, hipStream_t st);
+// State of a process restarted from a recorded start vector (in V_0) of norm *beta.
+void launch_restore_start(KState* ks, const double* beta, hipStream_t st);
 // sel = {0, last}: the first and the last check offset.
 void launch_set_ends(int32_t* sel, int last, hipStream_t st);
 
@@ -118,6 +120,20 @@ void launch_adj_amp(int n_src, const int32_t* row, const int64_t* delay, const i
                     const int64_t* width, const int64_t* fall, int64_t t_hi, int64_t dt,
                     const double* V, int64_t ldv, const KState* ks, const double* I, double lscale,
                     double* grad, hipStream_t st);
+// Capacitance gradient (by parts: dJ/dc_i = (1/c_i)(-sum_s g_{s,i} y_i(t_s) +
+// int (G lambda)_i y_i dt)). One overlap [t1, t2] of an adjoint step and a
+// forward segment: W (ml x mf, row-major stride MAXM), q0 and q1 (MAXM each
+// after W) from one block-triangular Van Loan exponential (sig_b = t_hi - t2,
+// tau_a = t1 - t_a, h = t2 - t1, seconds).
+void launch_cg_block(const KState* kl, double gam_l, const KState* kf, double gam_f, double sig_b,
+                     double tau_a, double h, double* Wq, hipStream_t st);
+// GV[:, j] = G V[:, j], j < ks->m.
+void launch_spmv_cols(int64_t n, const int32_t* rp, const int32_t* ci, const double* gv,
+                      const double* V, int64_t ldv, const KState* ks, double* GV, hipStream_t st);
+// gc[i] += lscale beta_l / c_i GV_l[i, :] (beta_f W V_f[i, :]^T + q0 (y0_i - z2_i) + q1 z1_i).
+void launch_cg_nodes(int64_t n, const double* GVl, const double* Vf, int64_t ldv, const KState* kl,
+                     const KState* kf, const double* y0, const double* z1, const double* z2,
+                     const double* cperm, const double* Wq, double lscale, double* gc, hipStream_t st);
 // lambda[rows[q]] += -(sum of dJdx[pidx[e], s]) / cperm[rows[q]] * inv_scale.
 void launch_adj_jump(int n_rows, const int32_t* rows, const int32_t* ptr, const int32_t* pidx,
                      const double* dJdx, int64_t n_out, int s, const double* cperm, double inv_scale,

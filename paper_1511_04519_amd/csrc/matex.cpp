@@ -105,6 +105,7 @@ struct matex_factor_s {
     // device structure
     DevMem d_c0, d_nc, d_nr, d_roff, d_w, d_u, d_rows, d_child_ptr, d_child_idx, d_relidx;
     DevMem d_perm, d_iperm, d_cperm;
+    DevMem d_grp, d_gci, d_gv;        // G in the permuted order (CSR), for the adjoint
     std::vector<DevMem> d_W;          // [n_shifts] M factors, then G
     DevMem d_fwd_sn, d_fwd_first, d_bwd_sn, d_bwd_first;
     std::vector<LevelTasks> fwd, bwd;
@@ -123,7 +124,7 @@ struct matex_factor_s {
     int64_t held_bytes() const {
         int64_t b = 0;
         for (const DevMem* m : {&d_c0, &d_nc, &d_nr, &d_roff, &d_w, &d_u, &d_rows, &d_child_ptr, &d_child_idx,
-                                &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_fwd_sn, &d_fwd_first, &d_bwd_sn,
+                                &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_grp, &d_gci, &d_gv, &d_fwd_sn, &d_fwd_first, &d_bwd_sn,
                                 &d_bwd_first, &d_task_sn, &d_task_first, &d_dep_ptr, &d_dep_idx, &d_b_pos,
                                 &d_b_cptr, &d_b_cidx, &d_b_ft, &d_b_fr, &d_b_bt, &d_b_br})
             b += int64_t(m->bytes);
@@ -591,6 +592,24 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         for (int64_t k = 0; k < n; ++k) cperm[k] = nl->c_node[s.perm[k]];
         F->d_cperm = upload(cperm);
         F->c_host.assign(nl->c_node, nl->c_node + n);
+        {
+            // G with rows and columns in the factor's order
+            std::vector<int32_t> rp(n + 1, 0), ci;
+            std::vector<double> gv;
+            ci.reserve(G.ci.size());
+            gv.reserve(G.v.size());
+            for (int64_t r = 0; r < n; ++r) {
+                const int32_t o = s.perm[r];
+                for (int64_t q = G.rp[o]; q < G.rp[o + 1]; ++q) {
+                    ci.push_back(s.iperm[G.ci[q]]);
+                    gv.push_back(G.v[q]);
+                }
+                rp[r + 1] = int32_t(ci.size());
+            }
+            F->d_grp = upload(rp);
+            F->d_gci = upload(ci);
+            F->d_gv = upload(gv);
+        }
         for (int k = 0; k <= n_shifts; ++k) {
             F->d_W.push_back(upload(Wh[k]));
             std::vector<double>().swap(Wh[k]);
@@ -1182,8 +1201,11 @@ void transient_batched(const matex_factor_s& F, const matex_problem* p, const ma
         for (int32_t k = 0; k < n_probe; ++k) pp[k] = F.sym.iperm[p->probe[k]];
         bw.probe_perm = upload(pp);
     }
-    launch_b_fill(npo, F.vdd, d_probe_out, st);
-    if (d_final) launch_b_fill(n, F.vdd, d_final, st);
+    // outputs start at Vdd and each batch subtracts its droops (x), or start
+    // at 0 and add them (droop)
+    const double base = o->output_droop ? 0.0 : F.vdd, sgn = o->output_droop ? 1.0 : -1.0;
+    launch_b_fill(npo, base, d_probe_out, st);
+    if (d_final) launch_b_fill(n, base, d_final, st);
     int m_guess = 6;
     for (int b0 = 0; b0 < G; b0 += RMAX) {
         const int R = std::min(RMAX, G - b0);
@@ -1306,13 +1328,193 @@ void transient_batched(const matex_factor_s& F, const matex_problem* p, const ma
                 pending.swap(rest);
             }
         }
-        launch_b_sum_out(npo, R, bw.Yout.as<double>(), d_probe_out, st);
-        if (d_final) launch_b_sum_final(n, R, F.d_perm.as<int32_t>(), bw.y.as<double>(), d_final, st);
+        launch_b_sum_out(npo, R, bw.Yout.as<double>(), sgn, d_probe_out, st);
+        if (d_final) launch_b_sum_final(n, R, F.d_perm.as<int32_t>(), bw.y.as<double>(), sgn, d_final, st);
     }
     HIPCHK(hipStreamSynchronize(st));
 }
 
 }  // namespace
+
+// Recorder of a plain run's segments for the adjoint: per segment its
+// start and end, shift and dimension, and (device checkpoint) the basis's
+// normalised start vector followed by its norm, so that the basis can be
+// rebuilt exactly as the run built it.
+struct FwdRecord {
+    int64_t n = 0;
+    std::vector<int64_t> ta, tb;
+    std::vector<int> ksh, m;
+    std::vector<DevMem> blocks;     // checkpoints, CK_BLOCK of n + 1 doubles each
+    static constexpr int CK_BLOCK = 256;
+    int64_t max_bytes = 0;
+    void add(int64_t a, int64_t b, int k, int mm, const double* v0, const double* beta, hipStream_t st) {
+        const size_t i = ta.size();
+        if (i % CK_BLOCK == 0) {
+            if (int64_t(blocks.size() + 1) * CK_BLOCK * (n + 1) * 8 > max_bytes)
+                throw std::bad_alloc();
+            blocks.emplace_back(sizeof(double) * size_t(n + 1) * CK_BLOCK);
+        }
+        HIPCHK(hipMemcpyAsync(state(i), v0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(state(i) + n, beta, sizeof(double), hipMemcpyDeviceToDevice, st));
+        ta.push_back(a); tb.push_back(b); ksh.push_back(k); m.push_back(mm);
+    }
+    double* state(size_t i) const {
+        return blocks[i / CK_BLOCK].as<double>() + int64_t(i % CK_BLOCK) * (n + 1);
+    }
+};
+
+// The plain mode (Alg. 2 per subtask, one after another). Throws HipError
+// and NoConv; rec (optional) records every segment.
+static void transient_plain(matex_factor_s* f, const matex_problem* p, const matex_run_opts* o,
+                            const std::map<int32_t, std::vector<int32_t>>& groups, int64_t h_min,
+                            double shift_ratio, bool trace, double* d_probe_out, double* d_final,
+                            matex_stats& S, hipStream_t st, FwdRecord* rec)
+{
+    const int64_t n = f->sym.n;
+    const int n_shifts = int(f->gammas.size());
+    const int32_t n_out = p->n_out, n_probe = p->n_probe;
+    // largest check set: outputs inside one spot interval + 1
+    Work wk(*f, int64_t(n_out) + 1);
+    PinnedMem pin(4096);
+    KsHost* hks = pin.as<KsHost>();
+    double* hest = pin.as<double>() + 16;
+    int64_t stage_cap = 1 << 16;
+    std::unique_ptr<PinnedMem> stage(new PinnedMem(stage_cap));
+    DevMem d_ev(stage_cap);
+    DevMem y(sizeof(double) * n), y0(sizeof(double) * n), z1(sizeof(double) * n),
+        z2(sizeof(double) * n), sl(sizeof(double) * n), ysum(sizeof(double) * n);
+    DevMem probe_perm(sizeof(int32_t) * std::max(1, n_probe));
+    {
+        std::vector<int32_t> pp(n_probe);
+        for (int32_t k = 0; k < n_probe; ++k) pp[k] = f->sym.iperm[p->probe[k]];
+        if (n_probe)
+            HIPCHK(hipMemcpy(probe_perm.p, pp.data(), sizeof(int32_t) * n_probe, hipMemcpyHostToDevice));
+    }
+    HIPCHK(hipMemsetAsync(d_probe_out, 0, sizeof(double) * int64_t(n_probe) * n_out, st));
+    HIPCHK(hipMemsetAsync(ysum.p, 0, ysum.bytes, st));
+    const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
+    const double* cperm = f->d_cperm.as<double>();
+    double* V = wk.V.as<double>();
+    int m_guess = 6;
+
+    for (auto& grp : groups) {
+        S.subtasks++;
+        std::vector<Segment> spots = plan_spots(p, grp.second, f->sym.iperm);
+        for (DevMem* b : {&y, &y0, &z1, &z2, &sl}) HIPCHK(hipMemsetAsync(b->p, 0, b->bytes, st));
+        int64_t t_a = 0;
+        size_t k_spot = 0;
+        while (t_a < p->t_end) {
+            // new input slope at a transition spot: z1 = G^-1 s, z2 = G^-1 C z1
+            if (k_spot < spots.size() && spots[k_spot].t == t_a) {
+                const Segment& sg = spots[k_spot];
+                const int32_t cnt = int32_t(sg.node.size());
+                if (cnt > 0) {
+                    size_t need = cnt * (sizeof(int32_t) + sizeof(double)) + 16;
+                    if (int64_t(need) > stage_cap) {
+                        HIPCHK(hipStreamSynchronize(st));
+                        stage_cap = int64_t(need) * 2;
+                        stage.reset(new PinnedMem(stage_cap));
+                        d_ev = DevMem(stage_cap);
+                    }
+                    HIPCHK(hipStreamSynchronize(st));   // staging buffer reuse
+                    double* hv = stage->as<double>();
+                    int32_t* hi = reinterpret_cast<int32_t*>(hv + cnt);
+                    std::memcpy(hv, sg.dslope.data(), sizeof(double) * cnt);
+                    std::memcpy(hi, sg.node.data(), sizeof(int32_t) * cnt);
+                    HIPCHK(hipMemcpyAsync(d_ev.p, stage->p, need, hipMemcpyHostToDevice, st));
+                    double* dv = d_ev.as<double>();
+                    launch_scatter_add(cnt, reinterpret_cast<int32_t*>(dv + cnt), dv, sl.as<double>(), st);
+                    dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
+                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
+                    dev_solve(*f, n_shifts, z1.as<double>(), cperm, z2.as<double>(),
+                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
+                    S.solve_pairs_g += 2;
+                }
+                k_spot++;
+            }
+            int32_t snap0 = 0;
+            std::vector<int64_t> offs = step_offsets(tout, t_a, spots[k_spot].t, &snap0);
+            int ksh = ladder_shift(f->gammas, offs[0], shift_ratio);
+            ladder_cut(offs, f->gammas, ksh);
+            KsHost h{};
+            while (true) {
+                std::vector<double> taus(offs.size());
+                for (size_t q = 0; q < offs.size(); ++q) taus[q] = double(offs[q]) * FS;
+                HIPCHK(hipStreamSynchronize(st));
+                std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
+                HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
+                                      hipMemcpyHostToDevice, st));
+                launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
+                               wk.partial.as<double>(), wk.kst(), st);
+                launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
+                h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, m_guess, hks, st);
+                S.bases++;
+                S.solve_pairs_m += h.m;
+                S.krylov_dims += h.m;
+                S.m_peak = std::max(S.m_peak, h.m);
+                if (h.m > 0) m_guess = h.m;
+                if (trace && !h.converged)
+                    fprintf(stderr, "[matex] not converged t_a=%lld shift=%d m=%d est=%.3e checks=%zu first=%lld last=%lld\n",
+                            (long long)t_a, ksh, h.m, read_est(wk, hest, st), offs.size(),
+                            (long long)offs[0], (long long)offs.back());
+                if (h.converged || ksh + 1 == n_shifts) break;
+                ksh++;
+                S.shift_downs++;
+                ladder_cut(offs, f->gammas, ksh);
+            }
+            if (!h.converged) {
+                // halve the step with the same basis until the checks pass
+                int64_t hstep = offs.back();
+                while (true) {
+                    hstep /= 2;
+                    S.halvings++;
+                    if (hstep < h_min)
+                        throw NoConv{"no convergence at t = " + std::to_string(t_a) + " fs"};
+                    std::vector<int64_t> o2 = halved_offsets(offs, hstep);
+                    std::vector<double> taus(o2.size());
+                    for (size_t q = 0; q < o2.size(); ++q) taus[q] = double(o2[q]) * FS;
+                    HIPCHK(hipStreamSynchronize(st));
+                    std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
+                    HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
+                                          hipMemcpyHostToDevice, st));
+                    launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), nullptr, int(taus.size()),
+                                  o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
+                    KsHost hh = read_state(wk, hks, st);
+                    if (trace)
+                        fprintf(stderr, "[matex] halving t_a=%lld step=%lld est=%.3e\n", (long long)t_a,
+                                (long long)hstep, read_est(wk, hest, st));
+                    if (hh.converged) { offs = o2; break; }
+                }
+            }
+            const int64_t t_b = t_a + offs.back();
+            if (trace) {
+                const double e = read_est(wk, hest, st);
+                fprintf(stderr, "[matex] seg t_a=%lld t_b=%lld shift=%d m=%d conv=%d est=%.3e checks=%zu\n",
+                        (long long)t_a, (long long)t_b, ksh, h.m, h.converged, e, offs.size());
+            }
+            if (rec) rec->add(t_a, t_b, ksh, h.m, V, &wk.kst()->beta, st);
+            // snapshots (Alg. 2 reuse) at the probes, then the full state at t_b
+            int n_snap = 0;
+            while (snap0 + n_snap < n_out && tout[snap0 + n_snap] <= t_b) n_snap++;
+            launch_recon_probes(n_probe, probe_perm.as<int32_t>(), n_snap, snap0, wk.taus.as<double>(),
+                                wk.u.as<double>(), wk.kst(), V, n, y0.as<double>(), z1.as<double>(),
+                                z2.as<double>(), d_probe_out, n_out, st);
+            launch_recon_full(n, double(offs.back()) * FS,
+                              wk.u.as<double>() + int64_t(offs.size() - 1) * MAXM, wk.kst(), V, n,
+                              y.as<double>(), y0.as<double>(), z1.as<double>(), z2.as<double>(), st);
+            S.segments++;
+            t_a = t_b;
+        }
+        launch_axpy_scaled(n, 1.0, y.as<double>(), ysum.as<double>(), st);
+    }
+    if (!o->output_droop) launch_vdd_minus(int64_t(n_probe) * n_out, f->vdd, d_probe_out, st);
+    if (d_final) {
+        launch_scatter_perm(n, f->d_perm.as<int32_t>(), ysum.as<double>(), d_final, n, n, 1, st);
+        if (!o->output_droop) launch_vdd_minus(n, f->vdd, d_final, st);
+    }
+    HIPCHK(hipGetLastError());
+    check_sweep(wk.sync, st);
+}
 
 // Argument checks shared by matex_transient and matex_adjoint.
 static matex_status check_problem(matex_factor_t f, const matex_problem* p, const matex_run_opts* o)
@@ -1381,146 +1583,9 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
         return MATEX_OK;
     }
     try {
-        // largest check set: outputs inside one spot interval + 1
-        Work wk(*f, int64_t(n_out) + 1);
-        PinnedMem pin(4096);
-        KsHost* hks = pin.as<KsHost>();
-        double* hest = pin.as<double>() + 16;
-        int64_t stage_cap = 1 << 16;
-        std::unique_ptr<PinnedMem> stage(new PinnedMem(stage_cap));
-        DevMem d_ev(stage_cap);
-        DevMem y(sizeof(double) * n), y0(sizeof(double) * n), z1(sizeof(double) * n),
-            z2(sizeof(double) * n), sl(sizeof(double) * n), ysum(sizeof(double) * n);
-        DevMem probe_perm(sizeof(int32_t) * std::max(1, n_probe));
-        {
-            std::vector<int32_t> pp(n_probe);
-            for (int32_t k = 0; k < n_probe; ++k) pp[k] = f->sym.iperm[p->probe[k]];
-            if (n_probe)
-                HIPCHK(hipMemcpy(probe_perm.p, pp.data(), sizeof(int32_t) * n_probe, hipMemcpyHostToDevice));
-        }
-        HIPCHK(hipMemsetAsync(d_probe_out, 0, sizeof(double) * int64_t(n_probe) * n_out, st));
-        HIPCHK(hipMemsetAsync(ysum.p, 0, ysum.bytes, st));
-        const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
-        const double* cperm = f->d_cperm.as<double>();
-        double* V = wk.V.as<double>();
-        int m_guess = 6;
-
-        for (auto& grp : groups) {
-            S.subtasks++;
-            std::vector<Segment> spots = plan_spots(p, grp.second, f->sym.iperm);
-            for (DevMem* b : {&y, &y0, &z1, &z2, &sl}) HIPCHK(hipMemsetAsync(b->p, 0, b->bytes, st));
-            int64_t t_a = 0;
-            size_t k_spot = 0;
-            while (t_a < p->t_end) {
-                // new input slope at a transition spot: z1 = G^-1 s, z2 = G^-1 C z1
-                if (k_spot < spots.size() && spots[k_spot].t == t_a) {
-                    const Segment& sg = spots[k_spot];
-                    const int32_t cnt = int32_t(sg.node.size());
-                    if (cnt > 0) {
-                        size_t need = cnt * (sizeof(int32_t) + sizeof(double)) + 16;
-                        if (int64_t(need) > stage_cap) {
-                            HIPCHK(hipStreamSynchronize(st));
-                            stage_cap = int64_t(need) * 2;
-                            stage.reset(new PinnedMem(stage_cap));
-                            d_ev = DevMem(stage_cap);
-                        }
-                        HIPCHK(hipStreamSynchronize(st));   // staging buffer reuse
-                        double* hv = stage->as<double>();
-                        int32_t* hi = reinterpret_cast<int32_t*>(hv + cnt);
-                        std::memcpy(hv, sg.dslope.data(), sizeof(double) * cnt);
-                        std::memcpy(hi, sg.node.data(), sizeof(int32_t) * cnt);
-                        HIPCHK(hipMemcpyAsync(d_ev.p, stage->p, need, hipMemcpyHostToDevice, st));
-                        double* dv = d_ev.as<double>();
-                        launch_scatter_add(cnt, reinterpret_cast<int32_t*>(dv + cnt), dv, sl.as<double>(), st);
-                        dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
-                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
-                        dev_solve(*f, n_shifts, z1.as<double>(), cperm, z2.as<double>(),
-                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
-                        S.solve_pairs_g += 2;
-                    }
-                    k_spot++;
-                }
-                int32_t snap0 = 0;
-                std::vector<int64_t> offs = step_offsets(tout, t_a, spots[k_spot].t, &snap0);
-                int ksh = ladder_shift(f->gammas, offs[0], shift_ratio);
-                ladder_cut(offs, f->gammas, ksh);
-                KsHost h{};
-                while (true) {
-                    std::vector<double> taus(offs.size());
-                    for (size_t q = 0; q < offs.size(); ++q) taus[q] = double(offs[q]) * FS;
-                    HIPCHK(hipStreamSynchronize(st));
-                    std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
-                    HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
-                                          hipMemcpyHostToDevice, st));
-                    launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
-                                   wk.partial.as<double>(), wk.kst(), st);
-                    launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-                    h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, m_guess, hks, st);
-                    S.bases++;
-                    S.solve_pairs_m += h.m;
-                    S.krylov_dims += h.m;
-                    S.m_peak = std::max(S.m_peak, h.m);
-                    if (h.m > 0) m_guess = h.m;
-                    if (trace && !h.converged)
-                        fprintf(stderr, "[matex] not converged t_a=%lld shift=%d m=%d est=%.3e checks=%zu first=%lld last=%lld\n",
-                                (long long)t_a, ksh, h.m, read_est(wk, hest, st), offs.size(),
-                                (long long)offs[0], (long long)offs.back());
-                    if (h.converged || ksh + 1 == n_shifts) break;
-                    ksh++;
-                    S.shift_downs++;
-                    ladder_cut(offs, f->gammas, ksh);
-                }
-                if (!h.converged) {
-                    // halve the step with the same basis until the checks pass
-                    int64_t hstep = offs.back();
-                    while (true) {
-                        hstep /= 2;
-                        S.halvings++;
-                        if (hstep < h_min)
-                            return fail(MATEX_E_NOCONV, "no convergence at t = " + std::to_string(t_a) + " fs");
-                        std::vector<int64_t> o2 = halved_offsets(offs, hstep);
-                        std::vector<double> taus(o2.size());
-                        for (size_t q = 0; q < o2.size(); ++q) taus[q] = double(o2[q]) * FS;
-                        HIPCHK(hipStreamSynchronize(st));
-                        std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
-                        HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
-                                              hipMemcpyHostToDevice, st));
-                        launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), nullptr, int(taus.size()),
-                                      o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
-                        KsHost hh = read_state(wk, hks, st);
-                        if (trace)
-                            fprintf(stderr, "[matex] halving t_a=%lld step=%lld est=%.3e\n", (long long)t_a,
-                                    (long long)hstep, read_est(wk, hest, st));
-                        if (hh.converged) { offs = o2; break; }
-                    }
-                }
-                const int64_t t_b = t_a + offs.back();
-                if (trace) {
-                    const double e = read_est(wk, hest, st);
-                    fprintf(stderr, "[matex] seg t_a=%lld t_b=%lld shift=%d m=%d conv=%d est=%.3e checks=%zu\n",
-                            (long long)t_a, (long long)t_b, ksh, h.m, h.converged, e, offs.size());
-                }
-                // snapshots (Alg. 2 reuse) at the probes, then the full state at t_b
-                int n_snap = 0;
-                while (snap0 + n_snap < n_out && tout[snap0 + n_snap] <= t_b) n_snap++;
-                launch_recon_probes(n_probe, probe_perm.as<int32_t>(), n_snap, snap0, wk.taus.as<double>(),
-                                    wk.u.as<double>(), wk.kst(), V, n, y0.as<double>(), z1.as<double>(),
-                                    z2.as<double>(), d_probe_out, n_out, st);
-                launch_recon_full(n, double(offs.back()) * FS,
-                                  wk.u.as<double>() + int64_t(offs.size() - 1) * MAXM, wk.kst(), V, n,
-                                  y.as<double>(), y0.as<double>(), z1.as<double>(), z2.as<double>(), st);
-                S.segments++;
-                t_a = t_b;
-            }
-            launch_axpy_scaled(n, 1.0, y.as<double>(), ysum.as<double>(), st);
-        }
-        launch_vdd_minus(int64_t(n_probe) * n_out, f->vdd, d_probe_out, st);
-        if (d_final) {
-            launch_scatter_perm(n, f->d_perm.as<int32_t>(), ysum.as<double>(), d_final, n, n, 1, st);
-            launch_vdd_minus(n, f->vdd, d_final, st);
-        }
-        HIPCHK(hipGetLastError());
-        check_sweep(wk.sync, st);
+        transient_plain(f, p, o, groups, h_min, shift_ratio, trace, d_probe_out, d_final, S, st, nullptr);
+    } catch (const NoConv& e) {
+        return fail(MATEX_E_NOCONV, e.msg);
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
     } catch (const std::bad_alloc&) {
@@ -1610,7 +1675,6 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
     if (!d_dJdx) return fail(MATEX_E_INVALID, "null argument");
     if (matex_status cs = check_problem(f, p, o)) return cs;
     if (o->m_max > MAXM - 2) return fail(MATEX_E_INVALID, "m_max must be <= 30 for the adjoint");
-    if (d_grad_c) return fail(MATEX_E_UNSUPPORTED, "capacitance gradients are not provided by this build");
     const int64_t n = f->sym.n;
     const int n_shifts = int(f->gammas.size());
     const int32_t n_out = p->n_out, n_probe = p->n_probe, n_src = p->n_src;
@@ -1631,7 +1695,8 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
             if (nz) sample[p->t_out[c]] = c;
         }
         if (d_grad_amp && n_src > 0) HIPCHK(hipMemsetAsync(d_grad_amp, 0, sizeof(double) * n_src, st));
-        if (sample.empty() || n_src == 0) {
+        if (d_grad_c) HIPCHK(hipMemsetAsync(d_grad_c, 0, sizeof(double) * n, st));
+        if (sample.empty() || (n_src == 0 && !d_grad_c)) {
             HIPCHK(hipStreamSynchronize(st));
             return MATEX_OK;
         }
@@ -1704,6 +1769,145 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
         // jump), each with the shift of the ladder that fits it
         int64_t since = 0;
         size_t b = bnd.size() - 1;   // bnd[b] == t_last
+
+        // capacitance gradients: dJ/dc_i = -int lambda_i y_i' dt, integrated by
+        // parts. A forward run over [0, t_last] (all sources as one subtask:
+        // the sum of the subtasks' droops) records every segment with its
+        // basis's start vector; the sweep rebuilds each forward basis exactly
+        // (recorded shift and dimension) and integrates every overlap of an
+        // adjoint step with a forward segment exactly (Van Loan).
+        std::unique_ptr<FwdRecord> rec;
+        std::unique_ptr<Work> wf;
+        DevMem gcp, Wq, fy0, fz1, fz2, fi, fsl, fev, GV;
+        std::unique_ptr<PinnedMem> fstage, dbg;
+        size_t fev_cap = 0;
+        int64_t fseg = 0;
+        auto unit_val = [&](int32_t k, int64_t t) -> double {
+            const int64_t d = p->delay[k], r = p->rise[k], w = p->width[k], fl = p->fall[k];
+            if (t <= d) return 0.0;
+            if (t < d + r) return double(t - d) / double(r);
+            if (t <= d + r + w) return 1.0;
+            if (t < d + r + w + fl) return 1.0 - double(t - d - r - w) / double(fl);
+            return 0.0;
+        };
+        auto unit_slope = [&](int32_t k, double tm) -> double {   // per second
+            const double d = double(p->delay[k]), r = double(p->rise[k]), w = double(p->width[k]),
+                         fl = double(p->fall[k]);
+            if (tm > d && tm < d + r) return 1.0 / (r * FS);
+            if (tm > d + r + w && tm < d + r + w + fl) return -1.0 / (fl * FS);
+            return 0.0;
+        };
+        auto build_fwd = [&](int64_t i) {
+            const int64_t ta = rec->ta[size_t(i)], tb = rec->tb[size_t(i)];
+            if (trace)
+                fprintf(stderr, "[matex-adj] %.4f s rebuild forward segment %lld [%lld, %lld] shift=%d m=%d\n",
+                        now_s(), (long long)i, (long long)ta, (long long)tb, rec->ksh[size_t(i)], rec->m[size_t(i)]);
+            const double tm = 0.5 * (double(ta) + double(tb));
+            std::vector<int32_t> rr;
+            std::vector<double> iv, sv;
+            for (int32_t k = 0; k < n_src; ++k) {
+                const double a = p->amp[k] * unit_val(k, ta), sl = p->amp[k] * unit_slope(k, tm);
+                if (a != 0.0 || sl != 0.0) {
+                    rr.push_back(int32_t(f->sym.iperm[p->node[k]]));
+                    iv.push_back(a);
+                    sv.push_back(sl);
+                }
+            }
+            const size_t cnt = rr.size();
+            const size_t need = cnt * (2 * sizeof(double) + sizeof(int32_t)) + 64;
+            HIPCHK(hipStreamSynchronize(st));
+            if (need > fev_cap) {
+                fev_cap = need * 2;
+                fstage.reset(new PinnedMem(fev_cap));
+                fev = DevMem(fev_cap);
+            }
+            double* hv = fstage->as<double>();
+            std::memcpy(hv, iv.data(), sizeof(double) * cnt);
+            std::memcpy(hv + cnt, sv.data(), sizeof(double) * cnt);
+            std::memcpy(reinterpret_cast<int32_t*>(hv + 2 * cnt), rr.data(), sizeof(int32_t) * cnt);
+            HIPCHK(hipMemsetAsync(fi.p, 0, fi.bytes, st));
+            HIPCHK(hipMemsetAsync(fsl.p, 0, fsl.bytes, st));
+            if (cnt) {
+                HIPCHK(hipMemcpyAsync(fev.p, fstage->p, need, hipMemcpyHostToDevice, st));
+                double* dv = fev.as<double>();
+                const int32_t* drow = reinterpret_cast<const int32_t*>(dv + 2 * cnt);
+                launch_scatter_add(int32_t(cnt), drow, dv, fi.as<double>(), st);
+                launch_scatter_add(int32_t(cnt), drow, dv + cnt, fsl.as<double>(), st);
+            }
+            // y0 = G^-1 i(t_a), z1 = G^-1 s, z2 = G^-1 C z1 (Eq. 6)
+            dev_solve(*f, n_shifts, fi.as<double>(), nullptr, fy0.as<double>(), wf->tmp.as<double>(),
+                      wf->upd.as<double>(), nullptr, wf->sync, st);
+            dev_solve(*f, n_shifts, fsl.as<double>(), nullptr, fz1.as<double>(), wf->tmp.as<double>(),
+                      wf->upd.as<double>(), nullptr, wf->sync, st);
+            dev_solve(*f, n_shifts, fz1.as<double>(), cperm, fz2.as<double>(), wf->tmp.as<double>(),
+                      wf->upd.as<double>(), nullptr, wf->sync, st);
+            // the run's own start vector and norm: the same basis, bit for bit
+            double* Vf = wf->V.as<double>();
+            HIPCHK(hipMemcpyAsync(Vf, rec->state(size_t(i)), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+            launch_restore_start(wf->kst(), rec->state(size_t(i)) + n, st);
+            const int sh = rec->ksh[size_t(i)];
+            for (int j = 0; j < rec->m[size_t(i)]; ++j) {
+                dev_solve(*f, sh, Vf + int64_t(j) * n, cperm, wf->w.as<double>(), wf->tmp.as<double>(),
+                          wf->upd.as<double>(), wf->done(), wf->sync, st);
+                launch_gs_dots(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
+                               wf->done(), st);
+                launch_gs_update(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
+                                 wf->done(), st);
+                launch_gs_finish(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
+                                 wf->done(), st);
+            }
+        };
+        if (d_grad_c) {
+            rec.reset(new FwdRecord());
+            rec->n = n;
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            rec->max_bytes = int64_t(0.8 * double(fr));
+            matex_problem q = *p;
+            q.t_end = t_last;
+            q.n_out = 0;
+            while (q.n_out < n_out && p->t_out[q.n_out] <= t_last) q.n_out++;
+            std::map<int32_t, std::vector<int32_t>> one;
+            for (int32_t k = 0; k < n_src; ++k) one[0].push_back(k);
+            if (one.empty()) one[0];
+            DevMem xo(sizeof(double) * std::max<int64_t>(1, int64_t(n_probe) * q.n_out));
+            matex_stats S2{};
+            // the gradient's sample and integral terms partly cancel, so the
+            // recorded droop is taken two digits tighter than the adjoint
+            matex_run_opts ro = *o;
+            ro.output_droop = 1;
+            ro.tol = o->tol * 1e-2;
+            transient_plain(f, &q, &ro, one, h_min, ratio, false, xo.as<double>(), nullptr, S2, st, rec.get());
+            wf.reset(new Work(*f, 2));
+            gcp = DevMem(sizeof(double) * n);
+            HIPCHK(hipMemsetAsync(gcp.p, 0, gcp.bytes, st));
+            Wq = DevMem(sizeof(double) * (MAXM * MAXM + 2 * MAXM));
+            HIPCHK(hipMemsetAsync(Wq.p, 0, Wq.bytes, st));
+            GV = DevMem(sizeof(double) * n * (MAXM + 1));
+            // sample term: -(1/c_i) sum_s g_{s,i} y_i(t_s) = (1/c_i) sum dJ/dx * y at
+            // the probes (g = -dJ/dx), with the droop of the recorded run
+            std::vector<double> yp(size_t(n_probe) * q.n_out);
+            if (!yp.empty())
+                HIPCHK(hipMemcpyAsync(yp.data(), xo.p, sizeof(double) * yp.size(), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            std::map<int32_t, double> term;
+            for (auto& kv : sample)
+                for (int32_t qq = 0; qq < n_probe; ++qq)
+                    term[f->sym.iperm[p->probe[qq]]] += g[size_t(qq) * n_out + kv.second] *
+                                                         yp[size_t(qq) * q.n_out + kv.second] /
+                                                         f->c_host[p->probe[qq]];
+            std::vector<int32_t> trow;
+            std::vector<double> tval;
+            for (auto& e : term) { trow.push_back(e.first); tval.push_back(e.second); }
+            if (!trow.empty()) {
+                DevMem dr = upload(trow), dv = upload(tval);
+                launch_scatter_add(int32_t(trow.size()), dr.as<int32_t>(), dv.as<double>(), gcp.as<double>(), st);
+                HIPCHK(hipStreamSynchronize(st));
+            }
+            for (DevMem* v : {&fy0, &fz1, &fz2, &fi, &fsl}) *v = DevMem(sizeof(double) * n);
+            fseg = int64_t(rec->ta.size()) - 1;
+            build_fwd(fseg);
+        }
         while (t_hi > 0) {
             while (bnd[b] >= t_hi) --b;
             int64_t dt = std::min(t_hi - bnd[b], std::max<int64_t>(1, since));
@@ -1720,8 +1924,9 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                 ksh++;
             }
             if (trace)
-                fprintf(stderr, "[matex-adj] t_hi=%lld dt=%lld shift=%d m=%d conv=%d est=%.3e\n", (long long)t_hi,
-                        (long long)dt, ksh, h.m, h.converged, read_est(wk, pin.as<double>() + 128, st));
+                fprintf(stderr, "[matex-adj] %.4f s t_hi=%lld dt=%lld shift=%d m=%d conv=%d est=%.3e\n", now_s(),
+                        (long long)t_hi, (long long)dt, ksh, h.m, h.converged,
+                        read_est(wk, pin.as<double>() + 128, st));
             while (!h.converged) {
                 dt /= 2;
                 if (dt < h_min)
@@ -1737,6 +1942,45 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                                d_wid.as<int64_t>(), d_fal.as<int64_t>(), t_hi, dt, V, n, wk.kst(),
                                I.as<double>(), lscale, d_grad_amp, st);
             }
+            if (d_grad_c) {
+                const int64_t t_lo = t_hi - dt;
+                launch_spmv_cols(n, f->d_grp.as<int32_t>(), f->d_gci.as<int32_t>(), f->d_gv.as<double>(), V, n,
+                                 wk.kst(), GV.as<double>(), st);
+                while (fseg > 0 && rec->ta[size_t(fseg)] >= t_hi) build_fwd(--fseg);
+                while (true) {
+                    const int64_t ta = rec->ta[size_t(fseg)], tb = rec->tb[size_t(fseg)];
+                    const int64_t t1 = std::max(t_lo, ta), t2 = std::min(t_hi, tb);
+                    if (t2 > t1) {
+                        const double gl = f->gammas[ksh], gf = f->gammas[rec->ksh[size_t(fseg)]];
+                        const double sb = double(t_hi - t2) * FS, ta_s = double(t1 - ta) * FS,
+                                     hh = double(t2 - t1) * FS;
+                        launch_cg_block(wk.kst(), gl, wf->kst(), gf, sb, ta_s, hh, Wq.as<double>(), st);
+                        if (trace) {
+                            if (!dbg) dbg.reset(new PinnedMem(sizeof(double) * (MAXM * MAXM + 2 * MAXM)));
+                            double* hw = dbg->as<double>();
+                            HIPCHK(hipMemcpyAsync(hw, Wq.p, sizeof(double) * (MAXM * MAXM + 2 * MAXM),
+                                                  hipMemcpyDeviceToHost, st));
+                            HIPCHK(hipStreamSynchronize(st));
+                            bool bad = false;
+                            for (int q = 0; q < MAXM * MAXM + 2 * MAXM; ++q) bad |= !std::isfinite(hw[q]);
+                            if (bad)
+                                fprintf(stderr, "[matex-adj] non-finite overlap: adjoint [%lld, %lld] shift %d m %d, "
+                                        "forward %lld [%lld, %lld] shift %d m %d, t1 %lld t2 %lld\n",
+                                        (long long)t_lo, (long long)t_hi, ksh, h.m, (long long)fseg, (long long)ta,
+                                        (long long)tb, rec->ksh[size_t(fseg)], rec->m[size_t(fseg)],
+                                        (long long)t1, (long long)t2);
+                        }
+                        launch_cg_nodes(n, GV.as<double>(), wf->V.as<double>(), n, wk.kst(), wf->kst(),
+                                        fy0.as<double>(), fz1.as<double>(), fz2.as<double>(), cperm,
+                                        Wq.as<double>(), lscale, gcp.as<double>(), st);
+                    }
+                    if (ta > t_lo && fseg > 0) {
+                        build_fwd(--fseg);
+                        continue;
+                    }
+                    break;
+                }
+            }
             // lambda at the step's lower end
             launch_recon_full(n, double(dt) * FS, wk.u.as<double>(), wk.kst(), V, n, lam.as<double>(),
                               zero.as<double>(), zero.as<double>(), zero.as<double>(), st);
@@ -1745,13 +1989,16 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
             if (sample.count(t_hi)) since = 0;
             jump(t_hi);
         }
+        if (d_grad_c) launch_scatter_perm(n, f->d_perm.as<int32_t>(), gcp.as<double>(), d_grad_c, n, n, 1, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
         check_sweep(wk.sync, st);
+    } catch (const NoConv& e) {
+        return fail(MATEX_E_NOCONV, "forward run for the capacitance gradients: " + e.msg);
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
     } catch (const std::bad_alloc&) {
-        return fail(MATEX_E_OOM, "host allocation failed");
+        return fail(MATEX_E_OOM, "host or device allocation failed (forward checkpoints need segments x n x 8 bytes)");
     }
     return MATEX_OK;
 }

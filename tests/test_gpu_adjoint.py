@@ -1,8 +1,8 @@
 """GPU parity of the adjoint (gradients of an objective of the probe
 voltages) with the oracle's definitions: the amplitude gradient by linearity
-on the exact modal solution, and central differences of the GPU forward run
-itself (the gradient of a linear objective in one amplitude is exact under
-differencing)."""
+on the exact modal solution, the capacitance gradient by complex-step
+differentiation of the dense Eq. 5 solution, and at full size central
+differences of the GPU forward run itself."""
 import numpy as np
 import pytest
 
@@ -67,8 +67,9 @@ def test_adjoint_edge_cases():
     p = I.small(605, nx=6, ny=5, n_src=3, t_end=1 * I.NS)
     F = M.matex_factor(p.netlist, GAMMA)
     w = np.zeros((p.probe.size, p.t_out.size))
-    ga, _ = M.matex_adjoint(F, p, _dev(w), m_max=30)
+    ga, gc = M.matex_adjoint(F, p, _dev(w), m_max=30, grad_c=True)
     assert np.array_equal(ga.cpu().numpy(), np.zeros(3))
+    assert np.array_equal(gc.cpu().numpy(), np.zeros(p.netlist.n))
     # weight only at t = 0 (no influence) and only at t_end
     w[:, 0] = 1.0
     ga, _ = M.matex_adjoint(F, p, _dev(w), m_max=30)
@@ -77,10 +78,7 @@ def test_adjoint_edge_cases():
     ga, _ = M.matex_adjoint(F, p, _dev(w), tol=1e-10, m_max=30)
     ref = A.amp_gradient(p, w)
     assert np.abs(ga.cpu().numpy() - ref).max() <= 1e-8 * np.abs(ref).max()
-    # capacitance gradients are declined, m_max beyond the adjoint's limit too
-    with pytest.raises(M.MatexError) as e:
-        M.matex_adjoint(F, p, _dev(w), m_max=30, grad_c=True)
-    assert e.value.status == M.MATEX_E_UNSUPPORTED
+    # m_max beyond the adjoint's limit
     with pytest.raises(M.MatexError) as e:
         M.matex_adjoint(F, p, _dev(w), m_max=31)
     assert e.value.status == M.MATEX_E_INVALID
@@ -113,3 +111,59 @@ def test_adjoint_full_grid_against_forward_differences():
         fd = (vals[0] - vals[1]) / 2e-3
         print(f"source {k}: adjoint {ga[k]:.9e} differences {fd:.9e}", flush=True)
         assert abs(fd - ga[k]) <= 1e-6 * np.abs(ga).max()
+
+
+@pytest.mark.parametrize("seed,layers,nx,ny,nsrc,every", [
+    (611, 1, 6, 5, 4, 4), (612, 2, 5, 4, 5, 1), (613, 1, 9, 3, 3, 13)])
+def test_adjoint_capacitances_match_oracle_differences(seed, layers, nx, ny, nsrc, every):
+    """dJ/dc_i at every node against the oracle's complex-step derivative of
+    the dense Eq. 5 solution (J linear in x with random weights)."""
+    _note(f"adjoint capacitances seed={seed} {layers}x{nx}x{ny}")
+    p = I.small(seed, layers=layers, nx=nx, ny=ny, n_src=nsrc, t_end=1 * I.NS)
+    F = M.matex_factor(p.netlist, GAMMA)
+    w = _weights(p, every, seed)
+    ga, gc = M.matex_adjoint(F, p, _dev(w), tol=1e-11, m_max=30, grad_c=True)
+    ref = A.c_gradient_cs(p, w)
+    gc = gc.cpu().numpy()
+    err = np.abs(gc - ref).max() / np.abs(ref).max()
+    print("capacitance rel err", err, "max |g|", np.abs(ref).max(), flush=True)
+    # bound: each adjoint step is held to 1e-11 of the largest jump, and with a
+    # sample at every output (100 samples) about 1,500 steps contribute
+    assert err <= 2e-6
+    # the amplitude gradients of the same call
+    ra = A.amp_gradient(p, w)
+    assert np.abs(ga.cpu().numpy() - ra).max() <= 1e-8 * np.abs(ra).max()
+
+
+def test_adjoint_capacitances_full_grid_against_forward_differences():
+    """2 x 300 x 300 grid, 512 probes, samples every 0.1 ns over the first
+    0.5 ns: dJ/dc_i against central differences of the GPU forward run (the
+    factor rebuilt with c_i perturbed), at sampled nodes."""
+    _note("adjoint capacitances config1 grid vs forward differences")
+    p = I.config1()
+    T = 500 * I.PS
+    q = I.Problem(p.name, p.netlist, p.sources, T, p.t_out[p.t_out <= T], p.probe)
+    F = M.matex_factor(q.netlist, q.gamma)
+    w = _weights(q, 10, 8)
+    _, gc = M.matex_adjoint(F, q, _dev(w), tol=1e-10, m_max=30, grad_c=True)
+    gc = gc.cpu().numpy()
+    # sampled nodes: probes (largest gradients), and a few others
+    rng = np.random.default_rng(4)
+    nodes = list(rng.choice(q.probe, 2, replace=False)) + [int(np.argmax(np.abs(gc)))]
+    for i in nodes:
+        ys = []
+        c = q.netlist.c_node
+        for sgn in (1, -1):
+            c2 = c.copy()
+            c2[i] *= 1.0 + sgn * 1e-4
+            nl = I.Netlist(q.netlist.n, q.netlist.br_a, q.netlist.br_b, q.netlist.br_g, c2,
+                           q.netlist.pad_node, q.netlist.pad_g, q.netlist.vdd, q.netlist.coord)
+            F2 = M.matex_factor(nl, q.gamma)
+            y, _, _ = M.matex_transient(F2, I.Problem(q.name, nl, q.sources, T, q.t_out, q.probe),
+                                        tol=1e-13, m_max=24, final=False, droop=True)
+            ys.append(y.cpu().numpy())
+        # dJ/dc_i = sum w dx/dc_i, dx = -dy: the droop is differenced (x carries
+        # the supply offset, whose rounding would swamp the change)
+        fd = -float(np.sum(w * (ys[0] - ys[1]))) / (2e-4 * c[i])
+        print(f"node {i}: adjoint {gc[i]:.9e} differences {fd:.9e}", flush=True)
+        assert abs(fd - gc[i]) <= 1e-5 * np.abs(gc).max()

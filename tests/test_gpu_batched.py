@@ -98,6 +98,13 @@ def test_batched_edge_cases():
     x, _, _ = M.matex_transient(F, q, tol=1e-12, mode=M.MATEX_BATCHED)
     ym, _ = R.modal(q)
     assert np.abs(x.cpu().numpy() - (1.0 - ym)).max() <= 1e-10
+    # droop outputs: Vdd - x, plain and batched
+    for md in (M.MATEX_PLAIN, M.MATEX_BATCHED):
+        x, xf, _ = M.matex_transient(F, q, tol=1e-12, mode=md)
+        y, yf, _ = M.matex_transient(F, q, tol=1e-12, mode=md, droop=True)
+        assert np.abs((p.netlist.vdd - x.cpu().numpy()) - y.cpu().numpy()).max() <= 1e-15
+        assert np.abs((p.netlist.vdd - xf.cpu().numpy()) - yf.cpu().numpy()).max() <= 1e-15
+        assert np.abs(y.cpu().numpy() - ym).max() <= 1e-10
     # invalid mode
     with pytest.raises(M.MatexError) as e:
         M.matex_transient(F, q, mode=7)

@@ -390,9 +390,37 @@ def test_P14_capacitance_gradient_single_rc_closed_form():
     from oracle import adjoint as A
     c, g, p, w = _rc_pulse_case()
     _, dy = _rc_ramps(c, g, p.t_out.astype(float), 1e-3, 50, 30, 100, 40)
-    fd = A.c_gradient_fd(p, lambda x: float(np.sum(w * x)))[0]
+    fd = A.c_gradient_fd(p, w)[0]
     exact = -np.sum(w[0] * dy)
     assert abs(fd - exact) <= 1e-7 * abs(exact)
+    # the same at the ps scale (nearly quasi-static droop, small derivative)
+    src = sources([0], [1e-3], [50000], [30000], [100000], [40000])
+    q = problem(p.netlist, src, 400000, step=10000)
+    wq = np.random.default_rng(15).standard_normal((1, q.t_out.size))
+    _, dq = _rc_ramps(c, g, q.t_out.astype(float), 1e-3, 50000, 30000, 100000, 40000)
+    exact = -np.sum(wq[0] * dq)
+    assert abs(A.c_gradient_fd(q, wq)[0] - exact) <= 1e-7 * abs(exact)
+    # complex step on the dense route: no cancellation, exact to rounding
+    assert abs(A.c_gradient_cs(q, wq)[0] - exact) <= 1e-12 * abs(exact)
+    assert abs(A.c_gradient_cs(p, w)[0] + np.sum(w[0] * dy)) <= 1e-12 * abs(np.sum(w[0] * dy))
+
+
+def test_P14_complex_step_on_a_mesh_agrees_with_coarse_differences():
+    """On a mesh the two routes agree to the differences' own accuracy, and
+    the complex step reproduces the real dense route's droop."""
+    from oracle import adjoint as A
+    p = I.small(611, layers=1, nx=6, ny=5, n_src=4, t_end=1 * I.NS)
+    w = np.random.default_rng(611).standard_normal((p.probe.size, p.t_out.size))
+    ym, _ = R.modal(p)
+    yd = A._dense_eq5_droop(p, p.netlist.c_node.astype(np.complex128))
+    assert np.abs(yd.imag).max() == 0.0
+    assert np.abs(yd.real - ym).max() <= 1e-12 * np.abs(ym).max()
+    nodes = [3, 6, 11, 29]
+    cs = A.c_gradient_cs(p, w, nodes)
+    fd2 = A.c_gradient_fd(p, w, nodes, rel=2e-3)
+    fd1 = A.c_gradient_fd(p, w, nodes, rel=1e-3)
+    rich = (4 * fd1 - fd2) / 3      # Richardson: removes the O(rel^2) term
+    assert np.abs(rich - cs).max() <= 2e-4 * np.abs(cs).max()
 
 
 def test_P14_amplitude_gradient_is_the_derivative_on_a_mesh():
