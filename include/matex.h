@@ -238,25 +238,30 @@ matex_status matex_transient_many(int32_t n_inst, const matex_factor_t* f, const
 
 /*
  * matex_adjoint - gradients of an objective J of the probe voltages (for
- * example a droop penalty) with respect to the source amplitudes, by the
- * continuous adjoint of Eq. 5 propagated with the same rational Krylov steps
- * (Sec. 3.3.2) backwards in time. The method itself is not in the paper;
- * only its propagator is.
+ * example a droop penalty) with respect to the source amplitudes and the node
+ * capacitances, by the continuous adjoint of Eq. 5 propagated with the same
+ * rational Krylov steps (Sec. 3.3.2) backwards in time. The method itself is
+ * not in the paper; only its propagator is.
  *   d_dJdx: device [n_probe][n_out] (row-major, as d_probe_out of
  *           matex_transient) = dJ/dx at the probes and output times; the
  *           output times > 0 whose column is not all zero are the samples.
  *   d_grad_amp: device [n_src] = dJ/da_k (a_k = amp[k]; the pulses' timing
  *           from p), or NULL.
- *   d_grad_c: must be NULL (capacitance gradients: MATEX_E_UNSUPPORTED).
+ *   d_grad_c: device [n] = dJ/dc_i (natural node order), or NULL.
  * The adjoint lambda is zero after the last sample, jumps by C^-1 dJ/dy at
- * each sample and satisfies C lambda' = G lambda between samples; dJ/da_k
- * is the time integral of the source's unit pulse times lambda at its node.
- * Steps end at the samples and at every source's transition spots, and
- * after each jump grow geometrically from 1 fs; o->tol bounds each step's
- * estimate relative to the largest jump norm ||C^-1 dJ/dy(t_s)||_2 (about
- * 1e-10 is the practical floor), o->m_max must be <= 30, o->mode is ignored.
- * Synchronises `stream`. Errors: MATEX_E_INVALID, MATEX_E_UNSUPPORTED,
- * MATEX_E_NOCONV, MATEX_E_OOM, MATEX_E_HIP.
+ * each sample (y = Vdd - x) and satisfies C lambda' = G lambda between
+ * samples. dJ/da_k = int u_k(t) lambda_{n_k}(t) dt (u_k: source k's unit
+ * pulse); dJ/dc_i = -int lambda_i y_i' dt, evaluated integrated by parts as
+ * (1/c_i) (-sum_s dJ/dy_i(t_s) y_i(t_s) + int (G lambda)_i y_i dt) over a
+ * forward run of all sources together that records each segment's start
+ * vector (device memory: about segments x (n + 1) doubles, refused with
+ * MATEX_E_OOM beyond 80 % of the free memory) and is taken at o->tol / 100.
+ * Adjoint steps end at the samples and at every source's transition spots,
+ * and after each jump grow geometrically from 1 fs; o->tol bounds each
+ * step's estimate relative to the largest jump norm ||C^-1 dJ/dy(t_s)||_2
+ * (about 1e-11 is the practical floor), o->m_max must be <= 30, o->mode and
+ * o->output_droop are ignored. Synchronises `stream`.
+ * Errors: MATEX_E_INVALID, MATEX_E_NOCONV, MATEX_E_OOM, MATEX_E_HIP.
  */
 matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
                            const double* d_dJdx, double* d_grad_amp, double* d_grad_c,
