@@ -149,6 +149,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-window-ps", type=int, default=0, help="shorten the batched window")
+    ap.add_argument("--pairs-only", action="store_true",
+                    help="only time the substitution pairs (one-vector on the 180k-node grid, "
+                         "1 + 50 pairs; 64 right-hand sides on the 1M-node grid, 1 + 20 pairs): "
+                         "the profiling run for the sweep kernels' counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
@@ -162,6 +166,20 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     M.lib()   # fails loudly if libmatex.so is missing
+    if args.pairs_only:
+        out = {}
+        for name, prob, nrhs, reps in (("config1", I.config1(), 1, 50), ("config2", I.config2(), 64, 20)):
+            F = M.matex_factor(prob.netlist, prob.gamma)
+            sec, byt = M.matex_time_solves(F, which=0, reps=reps, nrhs=nrhs)
+            out[name] = {"nrhs": nrhs, "pairs": reps + 1, "pair_ms": sec * 1e3, "pair_bytes": byt,
+                         "GB_s": byt / sec / 1e9, "frac": byt / sec / 1e9 / HBM_PEAK_GBS}
+            print(f"[bench] {name}: pair {sec * 1e3:.3f} ms, {byt / sec / 1e9:.0f} GB/s", flush=True)
+            del F
+        a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+        torch.empty_like(a).copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(out), flush=True)
+        return
     p = I.config1()
     if args.window_ps:
         T = args.window_ps * I.PS
