@@ -33,26 +33,30 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_pair_config1.md")
+TRAFFIC_PROFILE64 = os.path.join(ROOT, "profiles", "solve_pair64_config2.md")
+PLAIN_SOURCES = ("kernels.hip", "kernels.hpp", "device_common.hpp", "factor.cpp", "factor.hpp")
+BATCHED_SOURCES = ("batched.hip", "batched.hpp", "kernels.hpp", "device_common.hpp", "factor.cpp",
+                   "factor.hpp")
 
 
-def kernel_source_digest():
+def kernel_source_digest(files=PLAIN_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "kernels.hpp", "device_common.hpp", "factor.cpp", "factor.hpp"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_1511_04519_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per substitution pair from the committed rocprofv3 counter
+def measured_traffic(path=TRAFFIC_PROFILE, files=PLAIN_SOURCES):
+    """HBM bytes per substitution pair from a committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
     try:
-        txt = open(TRAFFIC_PROFILE).read()
+        txt = open(path).read()
     except OSError:
         return None
     fields = dict(line.split(":", 1) for line in txt.splitlines()
                   if line.startswith(("kernel-sources:", "traffic-bytes-per-pair:")))
-    if fields.get("kernel-sources", "").strip() != kernel_source_digest():
+    if fields.get("kernel-sources", "").strip() != kernel_source_digest(files):
         return None
     return float(fields["traffic-bytes-per-pair"])
 METRIC = "SpTRSV HBM GB/s + transient node·steps/s, batched vs plain, at 1e-9 rel err"
@@ -131,8 +135,10 @@ def batched_vs_plain(window_ps=0):
         "stats_batched": sb, "stats_plain": sp,
         "pair64": {"bound": "hbm", "achieved": round(pair_b / pair_s / 1e9, 2), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(pair_b / pair_s / 1e9 / HBM_PEAK_GBS, 5),
+                   "traffic": measured_traffic(TRAFFIC_PROFILE64, BATCHED_SOURCES),
                    "pair_ms": round(pair_s * 1e3, 3), "pair_bytes": int(pair_b),
-                   "ms_per_subtask": round(pair_s * 1e3 / 64, 4)},
+                   "ms_per_subtask": round(pair_s * 1e3 / 64, 4),
+                   "kernel_sources": kernel_source_digest(BATCHED_SOURCES)},
         "pair1": {"achieved": round(one_b / one_s / 1e9, 2), "unit": "GB/s",
                   "frac": round(one_b / one_s / 1e9 / HBM_PEAK_GBS, 5), "pair_ms": round(one_s * 1e3, 3)},
     }
