@@ -34,261 +34,266 @@ using namespace dev;
 
 // ---------------------------------------------------------------- sweeps
 
-// One forward task: panel rows [r0, r0 + FWD_ROWS) of supernode sn.
-// lds: lds_nc + FWD_ROWS + 256 doubles.
-__device__ inline void fwd_task(const DevSym& s, int sn, int r0, double* lds, int lds_nc,
-                                const double* W, const double* b, const double* scale,
-                                double* y, double* upd)
-{
-    double* bt = lds;                       // btilde over the supernode's columns
-    double* acc_off = lds + lds_nc;         // children's updates on this task's off rows
-    double* part = acc_off + FWD_ROWS;      // k-slice partial sums
-    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
-    for (int k = threadIdx.x; k < nc; k += 256) {
-        const double v = b[c0 + k];
-        bt[k] = scale ? v * scale[c0 + k] : v;
-    }
-    if (threadIdx.x < FWD_ROWS) acc_off[threadIdx.x] = 0.0;
-    __syncthreads();
-    // assemble the children's subtree updates (one child at a time: two
-    // children may touch the same row, one child never touches a row twice)
-    const int cp1 = s.child_ptr[sn + 1];
-    for (int cp = s.child_ptr[sn]; cp < cp1; ++cp) {
-        const int c = s.child_idx[cp];
-        const int64_t uc = s.u[c];
-        const int noc = s.nr[c] - s.nc[c];
-        for (int q = threadIdx.x; q < noc; q += 256) {
-            const int pos = s.relidx[uc + q];
-            const double val = upd[uc + q];
-            if (pos < nc) bt[pos] -= val;
-            else if (pos >= r0 && pos < r0 + FWD_ROWS) acc_off[pos - r0] += val;
-        }
-        __syncthreads();
-    }
-    const int lane = threadIdx.x & (FWD_ROWS - 1), ks = threadIdx.x / FWD_ROWS;
-    const int row = r0 + lane;
-    double acc = 0.0;
-    if (row < nr) {
-        const int kmax = row < nc ? row + 1 : nc;
-        const int ld = dpanel_ld(nr);
-        const double* wr = W + s.w[sn] + row;
-        int k = ks;
-        for (; k + 3 * FWD_KSPLIT < kmax; k += 4 * FWD_KSPLIT) {
-            const double a0 = wr[int64_t(k) * ld], a1 = wr[int64_t(k + FWD_KSPLIT) * ld];
-            const double a2 = wr[int64_t(k + 2 * FWD_KSPLIT) * ld];
-            const double a3 = wr[int64_t(k + 3 * FWD_KSPLIT) * ld];
-            acc += (a0 * bt[k] + a1 * bt[k + FWD_KSPLIT]) +
-                   (a2 * bt[k + 2 * FWD_KSPLIT] + a3 * bt[k + 3 * FWD_KSPLIT]);
-        }
-        for (; k < kmax; k += FWD_KSPLIT) acc += wr[int64_t(k) * ld] * bt[k];
-    }
-    part[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x < FWD_ROWS && row < nr) {
-        double v = 0.0;
-#pragma unroll
-        for (int q = 0; q < FWD_KSPLIT; ++q) v += part[q * FWD_ROWS + lane];
-        if (row < nc) y[c0 + row] = v;
-        else upd[s.u[sn] + row - nc] = acc_off[lane] + v;
-    }
-}
+// Panel entries each thread has in flight ahead of the ones it multiplies.
+constexpr int PF = 4;
 
-// One backward task: columns [col0, col0 + BWD_COLS) of supernode sn, one
-// wavefront per column. lds: nr doubles.
-__device__ inline void bwd_task(const DevSym& s, int sn, int col0, double* g, const double* W,
-                                const double* y, double* x)
-{
-    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
-    const int32_t* roff = s.rows + s.roff[sn];
-    for (int k = threadIdx.x; k < nr; k += 256) g[k] = k < nc ? y[c0 + k] : -x[roff[k - nc]];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int col = col0 + wv;
-    if (col < nc) {
-        const double* wc = W + s.w[sn] + int64_t(col) * dpanel_ld(nr);
-        double acc = 0.0;
-        int k = col + lane;
-        for (; k + 192 < nr; k += 256)
-            acc += wc[k] * g[k] + wc[k + 64] * g[k + 64] + wc[k + 128] * g[k + 128]
-                 + wc[k + 192] * g[k + 192];
-        for (; k < nr; k += 64) acc += wc[k] * g[k];
-        acc = wave_sum(acc);
-        if (lane == 0) x[c0 + col] = acc;
-    }
-}
-
-__global__ __launch_bounds__(256) void k_forward(DevSym s, const int32_t* __restrict__ tsn,
-                                                 const int32_t* __restrict__ tfirst,
-                                                 int32_t lds_nc, const double* __restrict__ W,
+// Forward, panels with more than 64 rows: one block per ROWS panel rows of a
+// supernode, KS = 256 / ROWS column slices per row. The block issues its
+// first panel entries, then assembles btilde over the supernode's columns
+// (b minus the children's updates, each position's contributor list in child
+// order) and the children's updates on its own off rows, then multiplies
+// and sums the column slices in LDS. lds: lds_nc + 256 + ROWS doubles.
+template <int ROWS>
+__global__ __launch_bounds__(256) void k_forward(const PTask* __restrict__ tasks,
+                                                 const int32_t* __restrict__ cptr,
+                                                 const int32_t* __restrict__ cidx, int32_t lds_nc,
+                                                 const double* __restrict__ W,
                                                  const double* __restrict__ b,
                                                  const double* __restrict__ scale,
                                                  double* __restrict__ y, double* upd,
                                                  const int32_t* done)
 {
+    constexpr int KS = 256 / ROWS;
+    const PTask t = tasks[blockIdx.x];
     if (done && *done) return;
     extern __shared__ double lds[];
-    fwd_task(s, tsn[blockIdx.x], tfirst[blockIdx.x], lds, lds_nc, W, b, scale, y, upd);
+    double* bt = lds;
+    double* part = lds + lds_nc;
+    double* off = part + 256;
+    const int lane = threadIdx.x % ROWS, ks = threadIdx.x / ROWS;
+    const int row = t.first + lane;
+    const int kmax = row >= t.nr ? 0 : (row < t.nc ? row + 1 : t.nc);
+    const int64_t ld = dpanel_ld(t.nr);
+    const double* wr = W + t.w + row;
+    double a[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+        const int k = ks + q * KS;
+        a[q] = k < kmax ? wr[k * ld] : 0.0;
+    }
+    for (int k = threadIdx.x; k < t.nc; k += 256) {
+        double v = b[t.c0 + k];
+        if (scale) v *= scale[t.c0 + k];
+        const int j1 = cptr[t.pos + k + 1];
+        for (int j = cptr[t.pos + k]; j < j1; ++j) v -= upd[cidx[j]];
+        bt[k] = v;
+    }
+    if (threadIdx.x >= 256 - ROWS) {
+        const int i = threadIdx.x - (256 - ROWS), r = t.first + i;
+        double v = 0.0;
+        if (r >= t.nc && r < t.nr) {
+            const int j1 = cptr[t.pos + r + 1];
+            for (int j = cptr[t.pos + r]; j < j1; ++j) v += upd[cidx[j]];
+        }
+        off[i] = v;
+    }
+    __syncthreads();
+    double acc = 0.0;
+    for (int k = ks; k < kmax; k += PF * KS) {
+        double nx[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int kk = k + (PF + q) * KS;
+            nx[q] = kk < kmax ? wr[kk * ld] : 0.0;
+        }
+        double s[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int kk = k + q * KS;
+            s[q] = kk < kmax ? a[q] * bt[kk] : 0.0;
+        }
+        acc += (s[0] + s[1]) + (s[2] + s[3]);
+#pragma unroll
+        for (int q = 0; q < PF; ++q) a[q] = nx[q];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < ROWS && row < t.nr) {
+        double v = 0.0;
+#pragma unroll 8
+        for (int q = 0; q < KS; ++q) v += part[q * ROWS + lane];
+        if (row < t.nc) y[t.c0 + row] = v;
+        else upd[t.aux + row - t.nc] = off[lane] + v;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_backward(DevSym s, const int32_t* __restrict__ tsn,
-                                                  const int32_t* __restrict__ tfirst,
+// Backward, panels with more than 64 rows: one block per 256 / LPC columns
+// of a supernode, LPC lanes per column (a column is contiguous, so the lanes
+// of a column read consecutive entries). g = [y_s ; -x(off rows)] is staged
+// in LDS from the task's first column down. lds: nr doubles.
+template <int LPC>
+__global__ __launch_bounds__(256) void k_backward(const PTask* __restrict__ tasks,
+                                                  const int32_t* __restrict__ rows,
                                                   const double* __restrict__ W,
                                                   const double* __restrict__ y, double* x,
                                                   const int32_t* done)
 {
+    const PTask t = tasks[blockIdx.x];
     if (done && *done) return;
     extern __shared__ double g[];
-    bwd_task(s, tsn[blockIdx.x], tfirst[blockIdx.x], g, W, y, x);
+    const int q = threadIdx.x % LPC;
+    const int col = t.first + threadIdx.x / LPC;
+    const int kend = col < t.nc ? t.nr : 0;
+    const double* wc = W + t.w + int64_t(col) * dpanel_ld(t.nr);
+    double a[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+        const int k = col + q + p * LPC;
+        a[p] = k < kend ? wc[k] : 0.0;
+    }
+    for (int k = t.first + threadIdx.x; k < t.nr; k += 256)
+        g[k] = k < t.nc ? y[t.c0 + k] : -x[rows[t.aux + k - t.nc]];
+    __syncthreads();
+    double acc = 0.0;
+    for (int k = col + q; k < kend; k += PF * LPC) {
+        double nx[PF];
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int kk = k + (PF + p) * LPC;
+            nx[p] = kk < kend ? wc[kk] : 0.0;
+        }
+        double s[PF];
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int kk = k + p * LPC;
+            s[p] = kk < kend ? a[p] * g[kk] : 0.0;
+        }
+        acc += (s[0] + s[1]) + (s[2] + s[3]);
+#pragma unroll
+        for (int p = 0; p < PF; ++p) a[p] = nx[p];
+    }
+#pragma unroll
+    for (int o = LPC / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (q == 0 && col < t.nc) x[t.c0 + col] = acc;
 }
 
-// Levels whose panels have at most 64 rows: one wavefront per supernode, four
-// supernodes per block (tsn lists the level's supernodes; no chunking).
-__global__ __launch_bounds__(256) void k_forward_small(DevSym s, const int32_t* __restrict__ tsn,
-                                                       int32_t count, const double* __restrict__ W,
-                                                       const double* __restrict__ b,
-                                                       const double* __restrict__ scale,
-                                                       double* __restrict__ y, double* upd,
-                                                       const int32_t* done)
+// A supernode with at most 64 panel rows on one wavefront (lane = panel
+// row). f: the wavefront's 64 doubles of LDS.
+__device__ inline void fwd_wave(const PTask& t, int lane, double* f, const int32_t* cptr,
+                                const int32_t* cidx, const double* W, const double* b,
+                                const double* scale, double* y, double* upd)
 {
-    if (done && *done) return;
-    __shared__ double f_all[4][64];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + wv;
-    if (idx >= count) return;      // no block barrier below: waves are independent
-    double* f = f_all[wv];
-    const int sn = tsn[idx];
-    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
-    // f over the panel rows: own columns from b, off rows start at 0
-    if (lane < nr) {
-        double v = 0.0;
-        if (lane < nc) {
-            v = b[c0 + lane];
-            if (scale) v *= scale[c0 + lane];
+    const int kmax = lane >= t.nr ? 0 : (lane < t.nc ? lane + 1 : t.nc);
+    const int64_t ld = dpanel_ld(t.nr);
+    const double* wr = W + t.w + lane;
+    double a[PF];
+#pragma unroll
+    for (int q = 0; q < PF; ++q) a[q] = q < kmax ? wr[q * ld] : 0.0;
+    // f over the panel rows: own columns b minus the children's updates,
+    // off rows the children's updates
+    double v = 0.0;
+    if (lane < t.nr) {
+        const bool own = lane < t.nc;
+        if (own) {
+            v = b[t.c0 + lane];
+            if (scale) v *= scale[t.c0 + lane];
+        }
+        const int j1 = cptr[t.pos + lane + 1];
+        for (int j = cptr[t.pos + lane]; j < j1; ++j) {
+            const double u = upd[cidx[j]];
+            v = own ? v - u : v + u;
         }
         f[lane] = v;
     }
     __builtin_amdgcn_wave_barrier();
-    const int cp1 = s.child_ptr[sn + 1];
-    for (int cp = s.child_ptr[sn]; cp < cp1; ++cp) {
-        const int c = s.child_idx[cp];
-        const int64_t uc = s.u[c];
-        const int noc = s.nr[c] - s.nc[c];
-        if (lane < noc) {
-            const int pos = s.relidx[uc + lane];
-            const double val = upd[uc + lane];
-            f[pos] += pos < nc ? -val : val;
-        }
-        __builtin_amdgcn_wave_barrier();
+    double acc = 0.0;
+    for (int k = 0; k < kmax; k += PF) {
+        double nx[PF];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) nx[q] = k + PF + q < kmax ? wr[(k + PF + q) * ld] : 0.0;
+#pragma unroll
+        for (int q = 0; q < PF; ++q)
+            if (k + q < kmax) acc += a[q] * f[k + q];
+#pragma unroll
+        for (int q = 0; q < PF; ++q) a[q] = nx[q];
     }
-    if (lane < nr) {
-        const double* wr = W + s.w[sn] + lane;
-        const int kmax = lane < nc ? lane + 1 : nc;
-        const int ld = dpanel_ld(nr);
-        double acc = 0.0;
-        for (int k = 0; k < kmax; ++k) acc += wr[int64_t(k) * ld] * f[k];
-        if (lane < nc) y[c0 + lane] = acc;
-        else upd[s.u[sn] + lane - nc] = f[lane] + acc;
+    if (lane < t.nr) {
+        if (lane < t.nc) y[t.c0 + lane] = acc;
+        else upd[t.aux + lane - t.nc] = v + acc;
     }
 }
 
-__global__ __launch_bounds__(256) void k_backward_small(DevSym s, const int32_t* __restrict__ tsn,
-                                                        int32_t count, const double* __restrict__ W,
-                                                        const double* __restrict__ y, double* x,
-                                                        const int32_t* done)
+// Backward of such a supernode on one wavefront: lpc lanes per column, lpc
+// the largest power of two with nc * lpc <= 64. g: 64 doubles of LDS.
+__device__ inline void bwd_wave(const PTask& t, int lane, double* g, const int32_t* rows,
+                                const double* W, const double* y, double* x)
 {
+    const int sh = t.nc > 1 ? 32 - __clz(t.nc - 1) : 0;     // ceil(log2 nc)
+    const int lpc = 64 >> sh;
+    const int c = lane >> (6 - sh), q = lane & (lpc - 1);
+    const int kend = c < t.nc ? t.nr : 0;
+    const double* wc = W + t.w + int64_t(c) * dpanel_ld(t.nr);
+    double a[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+        const int k = c + q + p * lpc;
+        a[p] = k < kend ? wc[k] : 0.0;
+    }
+    if (lane < t.nr) g[lane] = lane < t.nc ? y[t.c0 + lane] : -x[rows[t.aux + lane - t.nc]];
+    __builtin_amdgcn_wave_barrier();
+    double acc = 0.0;
+    for (int k = c + q; k < kend; k += PF * lpc) {
+        double nx[PF];
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int kk = k + (PF + p) * lpc;
+            nx[p] = kk < kend ? wc[kk] : 0.0;
+        }
+        double s[PF];
+#pragma unroll
+        for (int p = 0; p < PF; ++p) {
+            const int kk = k + p * lpc;
+            s[p] = kk < kend ? a[p] * g[kk] : 0.0;
+        }
+        acc += (s[0] + s[1]) + (s[2] + s[3]);
+#pragma unroll
+        for (int p = 0; p < PF; ++p) a[p] = nx[p];
+    }
+    for (int o = lpc >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (q == 0 && c < t.nc) x[t.c0 + c] = acc;
+}
+
+// The bottom levels whose panels have at most 64 rows, in one launch: block
+// b walks steps blk[b] .. blk[b + 1] - 1 (whole subtrees, children's levels
+// first), each step up to four supernodes (slot nr = 0: idle), one per
+// wavefront, with a block barrier between steps. The backward sweep walks
+// the same steps in reverse.
+__global__ __launch_bounds__(256) void k_forward_tree(const PTask* __restrict__ slots,
+                                                      const int32_t* __restrict__ blk,
+                                                      const int32_t* __restrict__ cptr,
+                                                      const int32_t* __restrict__ cidx,
+                                                      const double* __restrict__ W,
+                                                      const double* __restrict__ b,
+                                                      const double* __restrict__ scale,
+                                                      double* __restrict__ y, double* upd,
+                                                      const int32_t* done)
+{
+    const int s0 = blk[blockIdx.x], s1 = blk[blockIdx.x + 1];
     if (done && *done) return;
+    __shared__ double f_all[4][64];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int idx = blockIdx.x * 4 + wv;
-    if (idx >= count) return;
-    const int sn = tsn[idx];
-    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
-    const int32_t* roff = s.rows + s.roff[sn];
-    // lane k holds g_k = y (own columns) or -x (off rows); column c of the
-    // panel is contiguous, so each column is one coalesced load per lane
-    double gk = 0.0;
-    if (lane < nr) gk = lane < nc ? y[c0 + lane] : -x[roff[lane - nc]];
-    const double* Ws = W + s.w[sn];
-    const int ld = dpanel_ld(nr);
-    int c = 0;
-    for (; c + 3 < nc; c += 4) {      // four columns' loads in flight
-        double v[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            v[q] = (lane >= c + q && lane < nr) ? Ws[int64_t(c + q) * ld + lane] * gk : 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const double t = wave_sum(v[q]);          // total in lane 0
-            if (lane == 0) x[c0 + c + q] = t;
-        }
-    }
-    for (; c < nc; ++c) {
-        const double v = (lane >= c && lane < nr) ? Ws[int64_t(c) * ld + lane] * gk : 0.0;
-        const double t = wave_sum(v);
-        if (lane == 0) x[c0 + c] = t;
+    for (int s = s0; s < s1; ++s) {
+        const PTask t = slots[4 * s + wv];
+        if (t.nr > 0) fwd_wave(t, lane, f_all[wv], cptr, cidx, W, b, scale, y, upd);
+        __syncthreads();
     }
 }
 
-// Whole substitution pair in one launch. Tasks are listed forward level 0 up
-// to the root, then backward from the root down. Blocks claim tasks in
-// increasing order from an atomic ticket counter. A task first waits until
-// every task it depends on (forward: the children's forward tasks; backward:
-// the parent's backward tasks, or for a root its own forward tasks) has
-// stamped its flag with this launch's epoch, then runs, publishes its results
-// (release fence) and stamps its own flag. Dependencies point only to smaller
-// task indices and a task is only ever claimed by a running block, so the
-// smallest unfinished claimed task can always proceed: no deadlock, and no
-// assumption about how many blocks are resident. The last block to leave
-// resets the two counters for the next launch. A wait longer than
-// `spin_limit` polls sets *err and abandons the launch instead of hanging.
-// ctr[0]: next ticket, ctr[1]: blocks that have left.
-__global__ __launch_bounds__(256) void k_sweep(DevSym s, SweepPlan P, int32_t lds_nc,
-                                               const double* W, const double* b,
-                                               const double* scale, double* y, double* x,
-                                               double* upd, int32_t* flags, int32_t epoch,
-                                               int32_t* err, int32_t spin_limit,
-                                               const int32_t* done, int32_t* ctr)
+__global__ __launch_bounds__(256) void k_backward_tree(const PTask* __restrict__ slots,
+                                                       const int32_t* __restrict__ blk,
+                                                       const int32_t* __restrict__ rows,
+                                                       const double* __restrict__ W,
+                                                       const double* __restrict__ y, double* x,
+                                                       const int32_t* done)
 {
+    const int s0 = blk[blockIdx.x], s1 = blk[blockIdx.x + 1];
     if (done && *done) return;
-    extern __shared__ double lds[];
-    __shared__ int32_t bail, task;
-    if (threadIdx.x == 0) bail = 0;
-    while (true) {
-        if (threadIdx.x == 0)
-            task = __hip_atomic_fetch_add(&ctr[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __shared__ double g_all[4][64];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int s = s1 - 1; s >= s0; --s) {
+        const PTask t = slots[4 * s + wv];
+        if (t.nr > 0) bwd_wave(t, lane, g_all[wv], rows, W, y, x);
         __syncthreads();
-        const int t = task;
-        if (t >= P.n_tasks) break;
-        const int d0 = P.dep_ptr[t], d1 = P.dep_ptr[t + 1];
-        for (int d = d0 + threadIdx.x; d < d1; d += 256) {
-            const int dep = P.dep_idx[d];
-            int32_t it = 0;
-            while (__hip_atomic_load(&flags[dep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-                if (++it > spin_limit || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    bail = 1;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        }
-        __syncthreads();
-        if (bail) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // see the producers' results
-        const int sn = P.task_sn[t], first = P.task_first[t];
-        if (t < P.n_fwd) fwd_task(s, sn, first, lds, lds_nc, W, b, scale, y, upd);
-        else bwd_task(s, sn, first, lds, W, y, x);
-        __threadfence();                           // publish this task's results
-        __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_store(&flags[t], epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (threadIdx.x == 0) {
-        const int32_t left = __hip_atomic_fetch_add(&ctr[1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (left == int32_t(gridDim.x) - 1) {
-            __hip_atomic_store(&ctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(&ctr[1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
     }
 }
 
@@ -545,50 +550,55 @@ inline int grid_for(int64_t n) { return int(std::min<int64_t>((n + 255) / 256, R
 
 }  // namespace
 
-void launch_forward(const DevSym& s, const LevelTasks& lv, const double* W, const double* b,
-                    const double* scale, double* y, double* upd, const int32_t* done,
-                    hipStream_t st)
+void launch_forward(const LevelTasks& lv, const int32_t* cptr, const int32_t* cidx,
+                    const double* W, const double* b, const double* scale, double* y, double* upd,
+                    const int32_t* done, hipStream_t st)
 {
-    if (lv.small) {
-        k_forward_small<<<(lv.count + 3) / 4, 256, 0, st>>>(s, lv.sn, lv.count, W, b, scale, y, upd,
-                                                            done);
-        return;
+    const size_t lds = sizeof(double) * (size_t(lv.lds_doubles) + 256 + size_t(lv.kind));
+    switch (lv.kind) {
+    case 4:
+        k_forward<4><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, W, b, scale,
+                                                 y, upd, done);
+        break;
+    case 16:
+        k_forward<16><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, W, b, scale,
+                                                  y, upd, done);
+        break;
+    default:
+        k_forward<64><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, W, b, scale,
+                                                  y, upd, done);
+        break;
     }
-    const size_t lds = sizeof(double) * (size_t(lv.lds_doubles) + FWD_ROWS + 256);
-    k_forward<<<lv.count, 256, lds, st>>>(s, lv.sn, lv.first, lv.lds_doubles, W, b, scale, y, upd,
-                                          done);
 }
 
-void launch_backward(const DevSym& s, const LevelTasks& lv, const double* W, const double* y,
+void launch_backward(const LevelTasks& lv, const int32_t* rows, const double* W, const double* y,
                      double* x, const int32_t* done, hipStream_t st)
 {
-    if (lv.small) {
-        k_backward_small<<<(lv.count + 3) / 4, 256, 0, st>>>(s, lv.sn, lv.count, W, y, x, done);
-        return;
-    }
     const size_t lds = sizeof(double) * size_t(lv.lds_doubles);
-    k_backward<<<lv.count, 256, lds, st>>>(s, lv.sn, lv.first, W, y, x, done);
+    switch (lv.kind) {
+    case 16:
+        k_backward<16><<<lv.count, 256, lds, st>>>(lv.tasks, rows, W, y, x, done);
+        break;
+    default:
+        k_backward<64><<<lv.count, 256, lds, st>>>(lv.tasks, rows, W, y, x, done);
+        break;
+    }
 }
 
-int sweep_max_blocks(size_t lds_bytes)
+void launch_forward_tree(const TreeTasks& tr, const int32_t* cptr, const int32_t* cidx,
+                         const double* W, const double* b, const double* scale, double* y,
+                         double* upd, const int32_t* done, hipStream_t st)
 {
-    int dev = 0, cus = 0, per = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep, 256, lds_bytes) != hipSuccess)
-        return 0;
-    return cus * per;
+    if (tr.n_blocks > 0)
+        k_forward_tree<<<tr.n_blocks, 256, 0, st>>>(tr.fslots, tr.blk, cptr, cidx, W, b, scale, y,
+                                                    upd, done);
 }
 
-hipError_t launch_sweep(const DevSym& s, const SweepPlan& P, int blocks, const double* W,
-                        const double* b, const double* scale, double* y, double* x, double* upd,
-                        int32_t* flags, int32_t epoch, int32_t* err, int32_t spin_limit,
-                        const int32_t* done, int32_t* ctr, hipStream_t st)
+void launch_backward_tree(const TreeTasks& tr, const int32_t* rows, const double* W,
+                          const double* y, double* x, const int32_t* done, hipStream_t st)
 {
-    const size_t lds = sizeof(double) * size_t(P.lds_doubles);
-    k_sweep<<<blocks, 256, lds, st>>>(s, P, P.lds_nc, W, b, scale, y, x, upd, flags, epoch, err,
-                                      spin_limit, done, ctr);
-    return hipGetLastError();
+    if (tr.n_blocks > 0)
+        k_backward_tree<<<tr.n_blocks, 256, 0, st>>>(tr.bslots, tr.blk, rows, W, y, x, done);
 }
 
 void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const double* w,

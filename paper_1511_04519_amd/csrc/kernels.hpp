@@ -8,9 +8,6 @@
 namespace matex {
 
 constexpr int MAXM = 32;          // largest Krylov dimension supported
-constexpr int FWD_ROWS = 16;      // panel rows of a forward task
-constexpr int FWD_KSPLIT = 16;    // column slices of a forward task (16 x 16 = 256 threads)
-constexpr int BWD_COLS = 4;       // columns of a backward task (one per wavefront)
 constexpr int RED_BLOCKS = 256;   // blocks of the vector reductions
 
 // Shared (factor-independent) device view of the supernodal structure.
@@ -28,27 +25,36 @@ struct DevSym {
     const int32_t* relidx;
 };
 
-// One level's task list: task t covers supernode sn[t] starting at first[t]
-// (a row for the forward sweep, a column for the backward sweep).
-struct LevelTasks {
-    const int32_t* sn;
-    const int32_t* first;
-    int32_t count;
-    int32_t lds_doubles;   // LDS the level needs (max nc fwd / max nr bwd)
-    int32_t small;         // every panel of the level has <= 64 rows: sn lists
-                           // the supernodes, one wavefront each (first unused)
+// One task of a level sweep: a block (panels with more than 64 rows) or a
+// wavefront (the whole supernode, panels with at most 64 rows).
+struct PTask {
+    int64_t w;       // panel offset of the supernode
+    int64_t aux;     // forward: the supernode's update slots; backward: its off-row list
+    int32_t c0, nc, nr;
+    int32_t first;   // forward: first panel row of the task; backward: first column
+    int32_t pos;     // forward: contributor list index of the supernode's panel position 0
+    int32_t pad_;
 };
 
-// Task list of the one-launch substitution pair (see k_sweep).
-struct SweepPlan {
-    int32_t n_tasks;       // forward tasks then backward tasks
-    int32_t n_fwd;
-    const int32_t* task_sn;
-    const int32_t* task_first;
-    const int32_t* dep_ptr;  // [n_tasks + 1]
-    const int32_t* dep_idx;  // task ids each task waits for
-    int32_t lds_nc;          // forward staging (max nc)
-    int32_t lds_doubles;     // dynamic LDS of the launch
+// One level's task list and its kernel: the forward sweep's panel rows per
+// block (4, 16 or 64) or the backward sweep's lanes per column (16 or 64).
+struct LevelTasks {
+    const PTask* tasks;
+    int32_t count;
+    int32_t lds_doubles;   // forward: max nc of the level; backward: max nr
+    int32_t kind;
+    int32_t pad_;
+};
+
+// The bottom levels whose panels have at most 64 rows, as steps of four
+// wavefront slots (slot nr = 0: idle); block b runs steps blk[b] .. blk[b + 1]
+// - 1. fslots / bslots: the same supernodes' forward / backward records.
+struct TreeTasks {
+    const PTask* fslots;
+    const PTask* bslots;
+    const int32_t* blk;
+    int32_t n_blocks;
+    int32_t n_levels;      // levels covered (0 .. n_levels - 1)
 };
 
 // Per-Krylov-process device state (one per instance).
@@ -69,21 +75,19 @@ struct KState {
 };
 
 // ---- sweeps: w = (L L^T)^-1 (scale .* b) in the permuted ordering --------
-void launch_forward(const DevSym& s, const LevelTasks& lv, const double* W, const double* b,
-                    const double* scale, double* y, double* upd, const int32_t* done,
-                    hipStream_t st);
-void launch_backward(const DevSym& s, const LevelTasks& lv, const double* W, const double* y,
+// Forward assembly: the update slots that add into panel position p of a
+// supernode are cidx[cptr[pos + p] .. cptr[pos + p + 1]) (child order).
+void launch_forward(const LevelTasks& lv, const int32_t* cptr, const int32_t* cidx,
+                    const double* W, const double* b, const double* scale, double* y, double* upd,
+                    const int32_t* done, hipStream_t st);
+// rows: the concatenated off-diagonal row lists.
+void launch_backward(const LevelTasks& lv, const int32_t* rows, const double* W, const double* y,
                      double* x, const int32_t* done, hipStream_t st);
-
-// One launch per pair; any grid size works (tasks are claimed dynamically);
-// sweep_max_blocks(lds bytes) is the number that fits the device at once.
-// ctr: two int32 counters, zero before the first launch (each launch leaves
-// them at zero).
-int sweep_max_blocks(size_t lds_bytes);
-hipError_t launch_sweep(const DevSym& s, const SweepPlan& P, int blocks, const double* W,
-                        const double* b, const double* scale, double* y, double* x, double* upd,
-                        int32_t* flags, int32_t epoch, int32_t* err, int32_t spin_limit,
-                        const int32_t* done, int32_t* ctr, hipStream_t st);
+void launch_forward_tree(const TreeTasks& tr, const int32_t* cptr, const int32_t* cidx,
+                         const double* W, const double* b, const double* scale, double* y,
+                         double* upd, const int32_t* done, hipStream_t st);
+void launch_backward_tree(const TreeTasks& tr, const int32_t* rows, const double* W,
+                          const double* y, double* x, const int32_t* done, hipStream_t st);
 
 // ---- Gram-Schmidt (two classical passes) -----------------------------------
 // partial: 2 * RED_BLOCKS * (MAXM + 2) doubles of scratch (two passes).

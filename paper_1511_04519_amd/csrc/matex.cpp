@@ -107,13 +107,9 @@ struct matex_factor_s {
     DevMem d_perm, d_iperm, d_cperm;
     DevMem d_grp, d_gci, d_gv;        // G in the permuted order (CSR), for the adjoint
     std::vector<DevMem> d_W;          // [n_shifts] M factors, then G
-    DevMem d_fwd_sn, d_fwd_first, d_bwd_sn, d_bwd_first;
-    std::vector<LevelTasks> fwd, bwd;
-    // one-launch sweep
-    DevMem d_task_sn, d_task_first, d_dep_ptr, d_dep_idx;
-    SweepPlan plan{};
-    int sweep_blocks = 0;
-    bool use_levels = false;
+    DevMem d_fwd_tasks, d_bwd_tasks, d_tree_f, d_tree_b, d_tree_blk;
+    std::vector<LevelTasks> fwd, bwd;   // levels tree.n_levels .. n_levels - 1
+    TreeTasks tree{};
     // batched (multi-subtask) sweeps
     DevMem d_b_pos, d_b_cptr, d_b_cidx, d_b_ft, d_b_fr, d_b_bt, d_b_br;
     BatchAssembly bas{};
@@ -124,8 +120,8 @@ struct matex_factor_s {
     int64_t held_bytes() const {
         int64_t b = 0;
         for (const DevMem* m : {&d_c0, &d_nc, &d_nr, &d_roff, &d_w, &d_u, &d_rows, &d_child_ptr, &d_child_idx,
-                                &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_grp, &d_gci, &d_gv, &d_fwd_sn, &d_fwd_first, &d_bwd_sn,
-                                &d_bwd_first, &d_task_sn, &d_task_first, &d_dep_ptr, &d_dep_idx, &d_b_pos,
+                                &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_grp, &d_gci, &d_gv, &d_fwd_tasks, &d_bwd_tasks, &d_tree_f, &d_tree_b,
+                                &d_tree_blk, &d_b_pos,
                                 &d_b_cptr, &d_b_cidx, &d_b_ft, &d_b_fr, &d_b_bt, &d_b_br})
             b += int64_t(m->bytes);
         for (const DevMem& m : d_W) b += int64_t(m.bytes);
@@ -135,72 +131,150 @@ struct matex_factor_s {
 
 namespace {
 
+// Blocks the device holds at once at 256 threads each (256 compute units x 8).
+constexpr int64_t RESIDENT_BLOCKS = 2048;
+
 void build_tasks(matex_factor_s& F)
 {
     const Symbolic& s = F.sym;
-    std::vector<int32_t> fsn, ffirst, bsn, bfirst;
-    std::vector<int64_t> foff(s.n_levels + 1, 0), boff(s.n_levels + 1, 0);
-    std::vector<int32_t> flds(s.n_levels, 1), blds(s.n_levels, 1);
-    std::vector<int32_t> small(s.n_levels, 0);
-    for (int lv = 0; lv < s.n_levels; ++lv) {
+    const int L = s.n_levels;
+    // every panel position's contributing child update slots, in child order
+    // (the inverse of relidx), shared by the one-vector and batched sweeps
+    std::vector<int32_t> pos_base(s.sn.size()), cptr{0}, cidx;
+    {
+        std::vector<std::vector<int32_t>> contrib;
+        for (size_t k = 0; k < s.sn.size(); ++k) {
+            const Supernode& q = s.sn[k];
+            contrib.assign(q.nr, {});
+            for (int32_t cp = s.child_ptr[k]; cp < s.child_ptr[k + 1]; ++cp) {
+                const Supernode& c = s.sn[s.child_idx[cp]];
+                for (int32_t t = 0; t < c.nr - c.nc; ++t)
+                    contrib[s.relidx[c.u + t]].push_back(int32_t(c.u + t));
+            }
+            pos_base[k] = int32_t(cptr.size()) - 1;
+            for (int32_t p = 0; p < q.nr; ++p) {
+                cidx.insert(cidx.end(), contrib[p].begin(), contrib[p].end());
+                cptr.push_back(int32_t(cidx.size()));
+            }
+        }
+        if (cidx.empty()) cidx.push_back(0);
+        F.d_b_pos = upload(pos_base); F.d_b_cptr = upload(cptr); F.d_b_cidx = upload(cidx);
+        F.bas = BatchAssembly{F.d_b_pos.as<int32_t>(), F.d_b_cptr.as<int32_t>(), F.d_b_cidx.as<int32_t>()};
+    }
+    // one-vector sweeps, bottom levels whose panels have at most 64 rows:
+    // whole subtrees per block, one wavefront per supernode. Roots are the
+    // supernodes of those levels whose parent lies above them; roots are
+    // packed into a block while every level holds at most four supernodes.
+    int32_t S = 0;
+    for (; S < L; ++S) {
         int32_t mx = 0;
-        for (int32_t k : s.level_sn[lv]) mx = std::max(mx, s.sn[k].nr);
-        small[lv] = mx <= 64 ? 1 : 0;
+        for (int32_t k : s.level_sn[S]) mx = std::max(mx, s.sn[k].nr);
+        if (mx > 64) break;
+    }
+    {
+        std::vector<PTask> fs, bs;
+        std::vector<int32_t> blk{0};
+        std::vector<std::vector<int32_t>> cur(S), sub(S);
+        auto emit = [&]() {
+            bool any = false;
+            for (int32_t l = 0; l < S; ++l) {
+                for (size_t i = 0; i < cur[l].size(); i += 4) {
+                    for (size_t w = i; w < i + 4; ++w) {
+                        if (w < cur[l].size()) {
+                            const int32_t k = cur[l][w];
+                            const Supernode& q = s.sn[k];
+                            fs.push_back({q.w, q.u, q.c0, q.nc, q.nr, 0, pos_base[k], 0});
+                            bs.push_back({q.w, q.roff, q.c0, q.nc, q.nr, 0, 0, 0});
+                        } else {
+                            fs.push_back({0, 0, 0, 0, 0, 0, 0, 0});
+                            bs.push_back({0, 0, 0, 0, 0, 0, 0, 0});
+                        }
+                    }
+                    any = true;
+                }
+                cur[l].clear();
+            }
+            if (any) blk.push_back(int32_t(fs.size() / 4));
+        };
+        std::vector<int32_t> stack;
+        for (int32_t lv = S - 1; lv >= 0; --lv)
+            for (int32_t k : s.level_sn[lv]) {
+                const int32_t par = s.sn[k].parent;
+                if (par >= 0 && s.sn[par].level < S) continue;
+                for (auto& v : sub) v.clear();
+                stack.assign(1, k);
+                while (!stack.empty()) {
+                    const int32_t c = stack.back();
+                    stack.pop_back();
+                    sub[s.sn[c].level].push_back(c);
+                    for (int32_t cp = s.child_ptr[c]; cp < s.child_ptr[c + 1]; ++cp)
+                        stack.push_back(s.child_idx[cp]);
+                }
+                bool fits = true;
+                for (int32_t l = 0; l < S; ++l) fits = fits && cur[l].size() + sub[l].size() <= 4;
+                if (!fits) emit();
+                for (int32_t l = 0; l < S; ++l) cur[l].insert(cur[l].end(), sub[l].begin(), sub[l].end());
+            }
+        emit();
+        F.d_tree_f = upload(fs.empty() ? std::vector<PTask>(4, PTask{}) : fs);
+        F.d_tree_b = upload(bs.empty() ? std::vector<PTask>(4, PTask{}) : bs);
+        F.d_tree_blk = upload(blk);
+        F.tree = TreeTasks{F.d_tree_f.as<PTask>(), F.d_tree_b.as<PTask>(), F.d_tree_blk.as<int32_t>(),
+                           int32_t(blk.size()) - 1, S};
+    }
+    // levels above: the forward sweep takes 16 panel rows per block, 64 when
+    // that many blocks would not all be resident at once, 4 on levels with
+    // few such blocks; the backward sweep one wavefront per column, 16 lanes
+    // per column when four-column blocks would not all be resident.
+    std::vector<PTask> ft, bt;
+    std::vector<int64_t> fo(L + 1, 0), bo(L + 1, 0);
+    std::vector<int32_t> fkind(L), bkind(L), flds(L, 1), blds(L, 1);
+    auto ceil_div = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+    for (int lv = S; lv < L; ++lv) {
+        int32_t mx_nr = 0, mx_nc = 0;
+        int64_t r16 = 0, c4 = 0;
         for (int32_t k : s.level_sn[lv]) {
             const Supernode& q = s.sn[k];
-            if (small[lv]) {
-                fsn.push_back(k); ffirst.push_back(0);
-                bsn.push_back(k); bfirst.push_back(0);
-            } else {
-                for (int32_t r = 0; r < q.nr; r += FWD_ROWS) { fsn.push_back(k); ffirst.push_back(r); }
-                for (int32_t c = 0; c < q.nc; c += BWD_COLS) { bsn.push_back(k); bfirst.push_back(c); }
-            }
-            flds[lv] = std::max(flds[lv], q.nc);
-            blds[lv] = std::max(blds[lv], q.nr);
+            mx_nr = std::max(mx_nr, q.nr);
+            mx_nc = std::max(mx_nc, q.nc);
+            r16 += ceil_div(q.nr, 16);
+            c4 += ceil_div(q.nc, 4);
         }
-        foff[lv + 1] = int64_t(fsn.size());
-        boff[lv + 1] = int64_t(bsn.size());
+        fkind[lv] = r16 > RESIDENT_BLOCKS ? 64 : (r16 < 128 ? 4 : 16);
+        bkind[lv] = c4 > RESIDENT_BLOCKS ? 16 : 64;
+        flds[lv] = std::max(1, mx_nc);
+        blds[lv] = std::max(1, mx_nr);
+        const int32_t cols_per = 256 / bkind[lv];
+        for (int32_t k : s.level_sn[lv]) {
+            const Supernode& q = s.sn[k];
+            for (int32_t r = 0; r < q.nr; r += fkind[lv])
+                ft.push_back({q.w, q.u, q.c0, q.nc, q.nr, r, pos_base[k], 0});
+            for (int32_t c = 0; c < q.nc; c += cols_per)
+                bt.push_back({q.w, q.roff, q.c0, q.nc, q.nr, c, 0, 0});
+        }
+        fo[lv + 1] = int64_t(ft.size());
+        bo[lv + 1] = int64_t(bt.size());
     }
-    F.d_fwd_sn = upload(fsn);
-    F.d_fwd_first = upload(ffirst);
-    F.d_bwd_sn = upload(bsn);
-    F.d_bwd_first = upload(bfirst);
-    for (int lv = 0; lv < s.n_levels; ++lv) {
-        LevelTasks f{F.d_fwd_sn.as<int32_t>() + foff[lv], F.d_fwd_first.as<int32_t>() + foff[lv],
-                     int32_t(foff[lv + 1] - foff[lv]), flds[lv], small[lv]};
-        LevelTasks b{F.d_bwd_sn.as<int32_t>() + boff[lv], F.d_bwd_first.as<int32_t>() + boff[lv],
-                     int32_t(boff[lv + 1] - boff[lv]), blds[lv], small[lv]};
-        F.fwd.push_back(f);
-        F.bwd.push_back(b);
+    for (int lv = 0; lv < S; ++lv) fo[lv + 1] = bo[lv + 1] = 0;
+    F.d_fwd_tasks = upload(ft.empty() ? std::vector<PTask>(1, PTask{}) : ft);
+    F.d_bwd_tasks = upload(bt.empty() ? std::vector<PTask>(1, PTask{}) : bt);
+    for (int lv = S; lv < L; ++lv) {
+        F.fwd.push_back({F.d_fwd_tasks.as<PTask>() + fo[lv], int32_t(fo[lv + 1] - fo[lv]), flds[lv], fkind[lv], 0});
+        F.bwd.push_back({F.d_bwd_tasks.as<PTask>() + bo[lv], int32_t(bo[lv + 1] - bo[lv]), blds[lv], bkind[lv], 0});
     }
-    // batched sweeps: every panel position's contributing child slots (the
-    // inverse of relidx); per level, forward blocks of 64 panel rows and
+    // batched sweeps: per level, forward blocks of 64 panel rows and
     // backward blocks of 64 panel columns, each split into tasks of at most
     // KCHUNK panel columns / rows whose partial results are summed
     {
-        const int L = s.n_levels;
-        std::vector<int32_t> pos_base(s.sn.size()), cptr{0}, cidx;
         std::vector<BTask> ft, bt;
         std::vector<BRed> fr, br;
         std::vector<int64_t> fo(L + 1), fro(L + 1), bo(L + 1), bro(L + 1);
-        std::vector<std::vector<int32_t>> contrib;
         for (int lv = 0; lv < L; ++lv) {
             fo[lv] = int64_t(ft.size()); fro[lv] = int64_t(fr.size());
             bo[lv] = int64_t(bt.size()); bro[lv] = int64_t(br.size());
             int32_t fslots = 0, bslots = 0;
             for (int32_t k : s.level_sn[lv]) {
                 const Supernode& q = s.sn[k];
-                contrib.assign(q.nr, {});
-                for (int32_t cp = s.child_ptr[k]; cp < s.child_ptr[k + 1]; ++cp) {
-                    const Supernode& c = s.sn[s.child_idx[cp]];
-                    for (int32_t t = 0; t < c.nr - c.nc; ++t)
-                        contrib[s.relidx[c.u + t]].push_back(int32_t(c.u + t));
-                }
-                pos_base[k] = int32_t(cptr.size()) - 1;
-                for (int32_t p = 0; p < q.nr; ++p) {
-                    cidx.insert(cidx.end(), contrib[p].begin(), contrib[p].end());
-                    cptr.push_back(int32_t(cidx.size()));
-                }
                 for (int32_t r0 = 0; r0 < q.nr; r0 += BR) {
                     const int32_t K = std::min(q.nc, r0 + BR);
                     const int32_t nch = (K + KCHUNK - 1) / KCHUNK;
@@ -228,11 +302,8 @@ void build_tasks(matex_factor_s& F)
         }
         fo[L] = int64_t(ft.size()); fro[L] = int64_t(fr.size());
         bo[L] = int64_t(bt.size()); bro[L] = int64_t(br.size());
-        if (cidx.empty()) cidx.push_back(0);
         if (fr.empty()) fr.push_back({0, 0, 0, 0});
         if (br.empty()) br.push_back({0, 0, 0, 0});
-        F.d_b_pos = upload(pos_base); F.d_b_cptr = upload(cptr); F.d_b_cidx = upload(cidx);
-        F.bas = BatchAssembly{F.d_b_pos.as<int32_t>(), F.d_b_cptr.as<int32_t>(), F.d_b_cidx.as<int32_t>()};
         F.d_b_ft = upload(ft); F.d_b_fr = upload(fr); F.d_b_bt = upload(bt); F.d_b_br = upload(br);
         for (int lv = 0; lv < L; ++lv) {
             BatchLevel b;
@@ -247,93 +318,20 @@ void build_tasks(matex_factor_s& F)
             F.blevels.push_back(b);
         }
     }
-    // one-launch plan: forward tasks (levels up), then backward (levels down)
-    const int32_t nsn = int32_t(s.sn.size());
-    std::vector<int32_t> tsn, tfirst, fb(nsn), fe(nsn), bb(nsn), be(nsn);
-    for (int lv = 0; lv < s.n_levels; ++lv)
-        for (int32_t k : s.level_sn[lv]) {
-            fb[k] = int32_t(tsn.size());
-            for (int32_t r = 0; r < s.sn[k].nr; r += FWD_ROWS) { tsn.push_back(k); tfirst.push_back(r); }
-            fe[k] = int32_t(tsn.size());
-        }
-    const int32_t n_fwd = int32_t(tsn.size());
-    for (int lv = s.n_levels - 1; lv >= 0; --lv)
-        for (int32_t k : s.level_sn[lv]) {
-            bb[k] = int32_t(tsn.size());
-            for (int32_t c = 0; c < s.sn[k].nc; c += BWD_COLS) { tsn.push_back(k); tfirst.push_back(c); }
-            be[k] = int32_t(tsn.size());
-        }
-    std::vector<int32_t> dptr(1, 0), didx;
-    for (size_t t = 0; t < tsn.size(); ++t) {
-        const int32_t k = tsn[t];
-        if (int32_t(t) < n_fwd) {
-            for (int32_t cp = s.child_ptr[k]; cp < s.child_ptr[k + 1]; ++cp) {
-                const int32_t c = s.child_idx[cp];
-                for (int32_t d = fb[c]; d < fe[c]; ++d) didx.push_back(d);
-            }
-        } else {
-            const int32_t par = s.sn[k].parent;
-            const int32_t d0 = par >= 0 ? bb[par] : fb[k], d1 = par >= 0 ? be[par] : fe[k];
-            for (int32_t d = d0; d < d1; ++d) didx.push_back(d);
-        }
-        dptr.push_back(int32_t(didx.size()));
-    }
-    F.d_task_sn = upload(tsn);
-    F.d_task_first = upload(tfirst);
-    F.d_dep_ptr = upload(dptr);
-    F.d_dep_idx = upload(didx.empty() ? std::vector<int32_t>{0} : didx);
-    F.plan.n_tasks = int32_t(tsn.size());
-    F.plan.n_fwd = n_fwd;
-    F.plan.task_sn = F.d_task_sn.as<int32_t>();
-    F.plan.task_first = F.d_task_first.as<int32_t>();
-    F.plan.dep_ptr = F.d_dep_ptr.as<int32_t>();
-    F.plan.dep_idx = F.d_dep_idx.as<int32_t>();
-    F.plan.lds_nc = s.max_nc;
-    F.plan.lds_doubles = std::max(s.max_nc + FWD_ROWS + 256, s.max_nr);
-    const int maxb = sweep_max_blocks(sizeof(double) * size_t(F.plan.lds_doubles));
-    F.sweep_blocks = std::min(maxb, F.plan.n_tasks);
-    // The one-launch sweep is exact but its per-task release/acquire fences
-    // (an L2 write-back and invalidate each) cost more than the level
-    // launches they replace on this factor shape; it is used on request only.
-    const char* env = std::getenv("MATEX_SWEEP");
-    F.use_levels = !(env && std::string(env) == "persistent") || F.sweep_blocks <= 0;
 }
-
-// Completion flags, error word and launch epoch of the one-launch sweep,
-// owned by one caller (one stream) at a time.
-struct SweepSync {
-    DevMem flags, err;     // err: [0] error word, [1..2] task and exit counters
-    int32_t epoch = 0;
-    explicit SweepSync(const matex_factor_s& F) {
-        flags = DevMem(sizeof(int32_t) * std::max(1, F.plan.n_tasks));
-        err = DevMem(sizeof(int32_t) * 4);
-        HIPCHK(hipMemset(flags.p, 0, flags.bytes));
-        HIPCHK(hipMemset(err.p, 0, err.bytes));
-    }
-};
-
-constexpr int32_t SPIN_LIMIT = 1 << 22;   // polls before a dependency wait gives up
 
 // x = A_which^-1 (scale .* b), all in the permuted ordering. tmp: [n], upd: [n_upd].
 void dev_solve(const matex_factor_s& F, int which, const double* b, const double* scale,
-               double* x, double* tmp, double* upd, const int32_t* done, SweepSync& sy,
-               hipStream_t st)
+               double* x, double* tmp, double* upd, const int32_t* done, hipStream_t st)
 {
     const double* W = F.d_W[which].as<double>();
-    if (!F.use_levels) {
-        if (sy.epoch >= INT32_MAX - 1) {
-            HIPCHK(hipMemsetAsync(sy.flags.p, 0, sy.flags.bytes, st));
-            sy.epoch = 0;
-        }
-        ++sy.epoch;
-        HIPCHK(launch_sweep(F.dsym, F.plan, F.sweep_blocks, W, b, scale, tmp, x, upd,
-                            sy.flags.as<int32_t>(), sy.epoch, sy.err.as<int32_t>(), SPIN_LIMIT, done,
-                            sy.err.as<int32_t>() + 1, st));
-        return;
-    }
-    const int L = F.sym.n_levels;
-    for (int lv = 0; lv < L; ++lv) launch_forward(F.dsym, F.fwd[lv], W, b, scale, tmp, upd, done, st);
-    for (int lv = L - 1; lv >= 0; --lv) launch_backward(F.dsym, F.bwd[lv], W, tmp, x, done, st);
+    launch_forward_tree(F.tree, F.bas.cptr, F.bas.cidx, W, b, scale, tmp, upd, done, st);
+    for (const LevelTasks& lv : F.fwd)
+        launch_forward(lv, F.bas.cptr, F.bas.cidx, W, b, scale, tmp, upd, done, st);
+    const int32_t* rows = F.d_rows.as<int32_t>();
+    for (auto it = F.bwd.rbegin(); it != F.bwd.rend(); ++it)
+        launch_backward(*it, rows, W, tmp, x, done, st);
+    launch_backward_tree(F.tree, rows, W, tmp, x, done, st);
 }
 
 // Multi-subtask pair: x = A_which^-1 (scale .* B) for R row-interleaved
@@ -366,22 +364,12 @@ void dev_solve_batched(const matex_factor_s& F, int which, int R, const double* 
     dev_solve_batched(F, which, R, B, scale, x, sc.yf.as<double>(), sc.U.as<double>(), sc.P.as<double>(), st);
 }
 
-// Raises if a one-launch sweep gave up waiting (reads the error word).
-void check_sweep(SweepSync& sy, hipStream_t st)
-{
-    int32_t e = 0;
-    HIPCHK(hipMemcpyAsync(&e, sy.err.p, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    if (e) throw HipError{hipErrorLaunchFailure, "substitution sweep: a dependency wait timed out"};
-}
-
 // Scratch of one Krylov process.
 struct Work {
     int64_t n = 0;
     DevMem V, w, tmp, upd, partial, ks, u, est, taus, sel;
     int64_t max_checks = 0;
-    SweepSync sync;
-    Work(const matex_factor_s& F, int64_t max_chk) : sync(F) {
+    Work(const matex_factor_s& F, int64_t max_chk) {
         n = F.sym.n;
         V = DevMem(sizeof(double) * n * (MAXM + 1));
         w = DevMem(sizeof(double) * n);
@@ -427,7 +415,7 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, const
     const int64_t n = wk.n;
     double* V = wk.V.as<double>();
     dev_solve(F, shift, V + int64_t(j) * n, F.d_cperm.as<double>(), wk.w.as<double>(),
-              wk.tmp.as<double>(), wk.upd.as<double>(), wk.done(), wk.sync, st);
+              wk.tmp.as<double>(), wk.upd.as<double>(), wk.done(), st);
     launch_gs_dots(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_update(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
@@ -666,7 +654,6 @@ matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const do
     try {
         DevMem bp(sizeof(double) * n), xp(sizeof(double) * n), tmp(sizeof(double) * n),
             upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd)), sc;
-        SweepSync sy(*f);
         const double* scale_p = nullptr;
         if (d_scale) {
             sc = DevMem(sizeof(double) * n);
@@ -693,12 +680,12 @@ matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const do
             launch_gather_perm(n, f->d_perm.as<int32_t>(), d_b + int64_t(r) * n, bp.as<double>(), n,
                                n, 1, st);
             dev_solve(*f, idx, bp.as<double>(), scale_p, xp.as<double>(), tmp.as<double>(),
-                      upd.as<double>(), nullptr, sy, st);
+                      upd.as<double>(), nullptr, st);
             launch_scatter_perm(n, f->d_perm.as<int32_t>(), xp.as<double>(), d_x + int64_t(r) * n,
                                 n, n, 1, st);
         }
         HIPCHK(hipGetLastError());
-        check_sweep(sy, st);
+        HIPCHK(hipStreamSynchronize(st));
         return MATEX_OK;
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -745,21 +732,20 @@ matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t nrhs, in
     try {
         DevMem b(sizeof(double) * n), x(sizeof(double) * n), tmp(sizeof(double) * n),
             upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd));
-        SweepSync sy(*f);
         HIPCHK(hipMemsetAsync(b.p, 0, b.bytes, st));
         const double* sc = idx < n_shifts ? f->d_cperm.as<double>() : nullptr;
         dev_solve(*f, idx, b.as<double>(), sc, x.as<double>(), tmp.as<double>(), upd.as<double>(),
-                  nullptr, sy, st);   // warm
+                  nullptr, st);   // warm
         hipEvent_t e0, e1;
         HIPCHK(hipEventCreate(&e0));
         HIPCHK(hipEventCreate(&e1));
         HIPCHK(hipEventRecord(e0, st));
         for (int r = 0; r < reps; ++r)
             dev_solve(*f, idx, b.as<double>(), sc, x.as<double>(), tmp.as<double>(), upd.as<double>(),
-                      nullptr, sy, st);
+                      nullptr, st);
         HIPCHK(hipEventRecord(e1, st));
         HIPCHK(hipEventSynchronize(e1));
-        check_sweep(sy, st);
+        HIPCHK(hipStreamSynchronize(st));
         float ms = 0.f;
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         (void)hipEventDestroy(e0);
@@ -814,7 +800,7 @@ matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, co
             }
         }
         HIPCHK(hipGetLastError());
-        check_sweep(wk.sync, st);
+        HIPCHK(hipStreamSynchronize(st));
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
     }
@@ -1425,9 +1411,9 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
                     double* dv = d_ev.as<double>();
                     launch_scatter_add(cnt, reinterpret_cast<int32_t*>(dv + cnt), dv, sl.as<double>(), st);
                     dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
-                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
+                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
                     dev_solve(*f, n_shifts, z1.as<double>(), cperm, z2.as<double>(),
-                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, wk.sync, st);
+                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
                     S.solve_pairs_g += 2;
                 }
                 k_spot++;
@@ -1513,7 +1499,7 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
         if (!o->output_droop) launch_vdd_minus(n, f->vdd, d_final, st);
     }
     HIPCHK(hipGetLastError());
-    check_sweep(wk.sync, st);
+    HIPCHK(hipStreamSynchronize(st));
 }
 
 // Argument checks shared by matex_transient and matex_adjoint.
@@ -1836,11 +1822,11 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
             }
             // y0 = G^-1 i(t_a), z1 = G^-1 s, z2 = G^-1 C z1 (Eq. 6)
             dev_solve(*f, n_shifts, fi.as<double>(), nullptr, fy0.as<double>(), wf->tmp.as<double>(),
-                      wf->upd.as<double>(), nullptr, wf->sync, st);
+                      wf->upd.as<double>(), nullptr, st);
             dev_solve(*f, n_shifts, fsl.as<double>(), nullptr, fz1.as<double>(), wf->tmp.as<double>(),
-                      wf->upd.as<double>(), nullptr, wf->sync, st);
+                      wf->upd.as<double>(), nullptr, st);
             dev_solve(*f, n_shifts, fz1.as<double>(), cperm, fz2.as<double>(), wf->tmp.as<double>(),
-                      wf->upd.as<double>(), nullptr, wf->sync, st);
+                      wf->upd.as<double>(), nullptr, st);
             // the run's own start vector and norm: the same basis, bit for bit
             double* Vf = wf->V.as<double>();
             HIPCHK(hipMemcpyAsync(Vf, rec->state(size_t(i)), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
@@ -1848,7 +1834,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
             const int sh = rec->ksh[size_t(i)];
             for (int j = 0; j < rec->m[size_t(i)]; ++j) {
                 dev_solve(*f, sh, Vf + int64_t(j) * n, cperm, wf->w.as<double>(), wf->tmp.as<double>(),
-                          wf->upd.as<double>(), wf->done(), wf->sync, st);
+                          wf->upd.as<double>(), wf->done(), st);
                 launch_gs_dots(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
                                wf->done(), st);
                 launch_gs_update(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
@@ -1992,7 +1978,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
         if (d_grad_c) launch_scatter_perm(n, f->d_perm.as<int32_t>(), gcp.as<double>(), d_grad_c, n, n, 1, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
-        check_sweep(wk.sync, st);
+        HIPCHK(hipStreamSynchronize(st));
     } catch (const NoConv& e) {
         return fail(MATEX_E_NOCONV, "forward run for the capacitance gradients: " + e.msg);
     } catch (const HipError& e) {
