@@ -78,6 +78,12 @@ typedef struct {
                                 one factor of C + gamma_k G each, plus one of
                                 G, all factored once                            */
     int32_t leaf_max;        /* nested-dissection leaf size (default 16 when 0) */
+    int32_t subtree_levels;  /* bottom levels the one-vector sweeps take as
+                                whole subtrees, one workgroup each, in one
+                                launch per sweep: 0 = automatic, -1 = none,
+                                k > 0 = at most k (levels whose supernodes
+                                have more than 64 columns or 256 rows are
+                                never taken)                                   */
 } matex_factor_opts;
 
 typedef struct {
@@ -92,6 +98,8 @@ typedef struct {
     double seconds_analyse;  /* host ordering + symbolic                         */
     double seconds_numeric;  /* host numeric factorisation, all factors           */
     int64_t device_bytes;    /* device memory held by the handle                 */
+    int32_t subtree_levels;  /* bottom levels swept as whole subtrees          */
+    int32_t subtree_blocks;  /* workgroups of those subtree sweeps             */
 } matex_factor_info;
 
 /*

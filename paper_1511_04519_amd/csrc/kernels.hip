@@ -167,133 +167,228 @@ __global__ __launch_bounds__(256) void k_backward(const PTask* __restrict__ task
     if (q == 0 && col < t.nc) x[t.c0 + col] = acc;
 }
 
-// A supernode with at most 64 panel rows on one wavefront (lane = panel
-// row). f: the wavefront's 64 doubles of LDS.
-__device__ inline void fwd_wave(const PTask& t, int lane, double* f, const int32_t* cptr,
-                                const int32_t* cidx, const double* W, const double* b,
-                                const double* scale, double* y, double* upd)
+// The bottom levels as whole subtrees, one block of TW wavefronts each. A
+// step is one wavefront per work item (items of one level, or of
+// independent subtrees); a block barrier separates steps. Everything a
+// subtree passes between its own supernodes stays in the block's LDS: the
+// forward sweep's update slots of non-root supernodes and, in the backward
+// sweep, every supernode's x (read as off rows by its descendants). Only the
+// subtree roots' update slots (read by the level above) and y, x go to
+// global memory. The block copies its items to LDS first; each wavefront
+// then issues the next step's global loads (panel entries, right-hand side,
+// contributor descriptors) before the barrier that ends the current step.
+// LDS: items, TW wave scratch regions of ws doubles, the shared region.
+
+// Up to TPF panel entries per lane are loaded ahead (all of them for panels
+// of at most TPF columns / for TPF rows per lane in the backward sweep).
+constexpr int TPF = 16;
+
+__device__ inline void tree_copy_items(const TItem* __restrict__ src, int n_items, TItem* dst)
 {
-    const int kmax = lane >= t.nr ? 0 : (lane < t.nc ? lane + 1 : t.nc);
+    const int32_t* s = reinterpret_cast<const int32_t*>(src);
+    int32_t* d = reinterpret_cast<int32_t*>(dst);
+    constexpr int WORDS = int(sizeof(TItem) / 4);
+    for (int i = threadIdx.x; i < n_items * WORDS; i += 64 * TW) d[i] = s[i];
+}
+
+struct FwdPre {
+    double a[TPF];
+    double bv, sv;   // b and scale at column `lane` (multiplied at use)
+    int2 d;
+};
+
+// Loads are unconditional (out-of-range lanes read a valid clamped address
+// and discard it), so the compiler can count them and let a step's loads
+// stay in flight while the previous step computes.
+__device__ inline void fwd_tree_load(const TItem& t, int lane, const int2* __restrict__ fdesc,
+                                     int64_t item, const double* W, const double* b,
+                                     const double* scale, FwdPre& p)
+{
+    const int row = t.first + lane;
+    const int kmax = row >= t.last ? 0 : (row < t.nc ? row + 1 : t.nc);
     const int64_t ld = dpanel_ld(t.nr);
-    const double* wr = W + t.w + lane;
-    double a[PF];
+    const double* wr = W + t.w + (row < t.last ? row : t.first);
 #pragma unroll
-    for (int q = 0; q < PF; ++q) a[q] = q < kmax ? wr[q * ld] : 0.0;
-    // f over the panel rows: own columns b minus the children's updates,
-    // off rows the children's updates
+    for (int q = 0; q < TPF; ++q) p.a[q] = wr[(q < kmax ? q : 0) * ld];
+    const int col = t.c0 + (lane < t.nc ? lane : 0);
+    p.bv = b[col];
+    p.sv = scale ? scale[col] : 1.0;
+    p.d = fdesc[item * 64 + lane];
+}
+
+// Sum of the (up to two) LDS slots a descriptor names: offset + 1 in each
+// 16-bit half, 0 for none.
+__device__ inline double desc_sum(int32_t d, const double* sh)
+{
     double v = 0.0;
-    if (lane < t.nr) {
-        const bool own = lane < t.nc;
-        if (own) {
-            v = b[t.c0 + lane];
-            if (scale) v *= scale[t.c0 + lane];
-        }
-        const int j1 = cptr[t.pos + lane + 1];
-        for (int j = cptr[t.pos + lane]; j < j1; ++j) {
-            const double u = upd[cidx[j]];
-            v = own ? v - u : v + u;
-        }
-        f[lane] = v;
-    }
+    const int o0 = d & 0xffff, o1 = (d >> 16) & 0xffff;
+    if (o0) v += sh[o0 - 1];
+    if (o1) v += sh[o1 - 1];
+    return v;
+}
+
+// One forward step of a wavefront: item t with its loaded values p.
+__device__ inline void fwd_tree_step(const TItem& t, const FwdPre& p, int lane, double* bt, double* sh,
+                                     const double* W, double* y, double* upd)
+{
+    if (t.nr == 0) return;
+    const int row = t.first + lane;
+    const bool live = row < t.last;
+    const int kmax = !live ? 0 : (row < t.nc ? row + 1 : t.nc);
+    // btilde = b minus the children's updates; the off row's updates
+    if (lane < t.nc) bt[lane] = p.bv * p.sv - desc_sum(p.d.x, sh);
+    const double off = live && row >= t.nc ? desc_sum(p.d.y, sh) : 0.0;
     __builtin_amdgcn_wave_barrier();
     double acc = 0.0;
-    for (int k = 0; k < kmax; k += PF) {
-        double nx[PF];
 #pragma unroll
-        for (int q = 0; q < PF; ++q) nx[q] = k + PF + q < kmax ? wr[(k + PF + q) * ld] : 0.0;
-#pragma unroll
-        for (int q = 0; q < PF; ++q)
-            if (k + q < kmax) acc += a[q] * f[k + q];
-#pragma unroll
-        for (int q = 0; q < PF; ++q) a[q] = nx[q];
+    for (int q = 0; q < TPF; ++q) acc += q < kmax ? p.a[q] * bt[q] : 0.0;
+    if (kmax > TPF) {
+        const int64_t ld = dpanel_ld(t.nr);
+        const double* wr = W + t.w + row;
+        for (int k = TPF; k < kmax; ++k) acc += wr[k * ld] * bt[k];
     }
-    if (lane < t.nr) {
-        if (lane < t.nc) y[t.c0 + lane] = acc;
-        else upd[t.aux + lane - t.nc] = v + acc;
+    if (live) {
+        if (row < t.nc) {
+            y[t.c0 + row] = acc;
+        } else {
+            const double v = off + acc;
+            if (t.lds_u >= 0) sh[t.lds_u + row - t.nc] = v;
+            else upd[t.aux + row - t.nc] = v;
+        }
     }
 }
 
-// Backward of such a supernode on one wavefront: lpc lanes per column, lpc
-// the largest power of two with nc * lpc <= 64. g: 64 doubles of LDS.
-__device__ inline void bwd_wave(const PTask& t, int lane, double* g, const int32_t* rows,
-                                const double* W, const double* y, double* x)
+// Steps run in pairs on two register sets, so a step's loads stay in
+// flight across the previous step's barrier.
+__global__ __launch_bounds__(64 * TW) void k_forward_tree(TreeTasks tr, const double* __restrict__ W,
+                                                         const double* __restrict__ b,
+                                                         const double* __restrict__ scale,
+                                                         double* __restrict__ y, double* upd,
+                                                         const int32_t* done)
 {
-    const int sh = t.nc > 1 ? 32 - __clz(t.nc - 1) : 0;     // ceil(log2 nc)
-    const int lpc = 64 >> sh;
-    const int c = lane >> (6 - sh), q = lane & (lpc - 1);
-    const int kend = c < t.nc ? t.nr : 0;
-    const double* wc = W + t.w + int64_t(c) * dpanel_ld(t.nr);
-    double a[PF];
-#pragma unroll
-    for (int p = 0; p < PF; ++p) {
-        const int k = c + q + p * lpc;
-        a[p] = k < kend ? wc[k] : 0.0;
+    const int s0 = tr.fblk[blockIdx.x], s1 = tr.fblk[blockIdx.x + 1];
+    if (done && *done) return;
+    extern __shared__ double lds[];
+    TItem* items = reinterpret_cast<TItem*>(lds);
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double* bt = lds + tr.item_doubles + wv * tr.ws;
+    double* sh = lds + tr.item_doubles + TW * tr.ws;
+    tree_copy_items(tr.fitems + int64_t(s0) * TW, (s1 - s0) * TW, items);
+    __syncthreads();
+    auto item = [&](int s) -> const TItem& { return items[(s - s0) * TW + wv]; };
+    FwdPre pa, pb;
+    fwd_tree_load(item(s0), lane, tr.fdesc, int64_t(s0) * TW + wv, W, b, scale, pa);
+    // the loads for the step after the last repeat the last step's (unused)
+    for (int s = s0;; s += 2) {
+        const int s_b = s + 1 < s1 ? s + 1 : s1 - 1;
+        fwd_tree_load(item(s_b), lane, tr.fdesc, int64_t(s_b) * TW + wv, W, b, scale, pb);
+        fwd_tree_step(item(s), pa, lane, bt, sh, W, y, upd);
+        __syncthreads();
+        if (s + 1 >= s1) break;
+        const int s_a = s + 2 < s1 ? s + 2 : s1 - 1;
+        fwd_tree_load(item(s_a), lane, tr.fdesc, int64_t(s_a) * TW + wv, W, b, scale, pa);
+        fwd_tree_step(item(s + 1), pb, lane, bt, sh, W, y, upd);
+        __syncthreads();
+        if (s + 2 >= s1) break;
     }
-    if (lane < t.nr) g[lane] = lane < t.nc ? y[t.c0 + lane] : -x[rows[t.aux + lane - t.nc]];
+}
+
+// Backward: the items of a step are column groups [first, last) of one
+// supernode, lpc lanes per column (lpc the largest power of two with
+// (last - first) * lpc <= 64; at most TPF rows per lane). g = [y ; -x(off
+// rows)] is staged per wavefront; x of an ancestor inside the subtree comes
+// from LDS (trow < 0), other values are loaded ahead.
+struct BwdPre {
+    double a[TPF];
+    double gv[TREE_MAX_NR / 64];
+    int32_t tr[TREE_MAX_NR / 64];
+};
+
+__device__ inline void bwd_tree_load(const TItem& t, int lane, const int32_t* __restrict__ trow,
+                                     const double* W, const double* y, const double* x, BwdPre& p)
+{
+    // off-row indices first: the x loads below wait for them only
+    const int noff = t.nr - t.nc;
+#pragma unroll
+    for (int i = 0; i < TREE_MAX_NR / 64; ++i) {
+        const int k = t.first + lane + 64 * i;
+        const int o = k - t.nc;
+        p.tr[i] = trow[t.aux + (o >= 0 && o < noff ? o : 0)];
+    }
+    const int cols = t.last - t.first;
+    const int shf = cols > 1 ? 32 - __clz(cols - 1) : 0;
+    const int lpc = 64 >> shf;
+    const int c = t.first + (lane >> (6 - shf)), q = lane & (lpc - 1);
+    const int kend = c < t.last ? t.nr : 0;
+    const double* wc = W + t.w + int64_t(c < t.last ? c : t.first) * dpanel_ld(t.nr);
+#pragma unroll
+    for (int i = 0; i < TPF; ++i) {
+        const int k = c + q + i * lpc;
+        p.a[i] = wc[k < kend ? k : 0];
+    }
+#pragma unroll
+    for (int i = 0; i < TREE_MAX_NR / 64; ++i) {
+        const int k = t.first + lane + 64 * i;
+        const bool own = k < t.nc;
+        const double* src = own ? y + t.c0 + k : x + (p.tr[i] >= 0 ? p.tr[i] : 0);
+        p.gv[i] = *src;   // y, or x of an off row (negated at use)
+        if (k >= t.nr || own) p.tr[i] = 0;
+    }
+}
+
+__device__ inline void bwd_tree_step(const TItem& t, const BwdPre& p, int lane, double* g, double* sh,
+                                     double* x)
+{
+    if (t.nr == 0) return;
+#pragma unroll
+    for (int i = 0; i < TREE_MAX_NR / 64; ++i) {
+        const int k = t.first + lane + 64 * i;
+        if (k < t.nr) g[k] = p.tr[i] < 0 ? -sh[-1 - p.tr[i]] : (k < t.nc ? p.gv[i] : -p.gv[i]);
+    }
     __builtin_amdgcn_wave_barrier();
+    const int cols = t.last - t.first;
+    const int shf = cols > 1 ? 32 - __clz(cols - 1) : 0;
+    const int lpc = 64 >> shf;
+    const int c = t.first + (lane >> (6 - shf)), q = lane & (lpc - 1);
+    const int kend = c < t.last ? t.nr : 0;
     double acc = 0.0;
-    for (int k = c + q; k < kend; k += PF * lpc) {
-        double nx[PF];
 #pragma unroll
-        for (int p = 0; p < PF; ++p) {
-            const int kk = k + (PF + p) * lpc;
-            nx[p] = kk < kend ? wc[kk] : 0.0;
-        }
-        double s[PF];
-#pragma unroll
-        for (int p = 0; p < PF; ++p) {
-            const int kk = k + p * lpc;
-            s[p] = kk < kend ? a[p] * g[kk] : 0.0;
-        }
-        acc += (s[0] + s[1]) + (s[2] + s[3]);
-#pragma unroll
-        for (int p = 0; p < PF; ++p) a[p] = nx[p];
+    for (int i = 0; i < TPF; ++i) {
+        const int k = c + q + i * lpc;
+        acc += k < kend ? p.a[i] * g[k] : 0.0;
     }
     for (int o = lpc >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if (q == 0 && c < t.nc) x[t.c0 + c] = acc;
-}
-
-// The bottom levels whose panels have at most 64 rows, in one launch: block
-// b walks steps blk[b] .. blk[b + 1] - 1 (whole subtrees, children's levels
-// first), each step up to four supernodes (slot nr = 0: idle), one per
-// wavefront, with a block barrier between steps. The backward sweep walks
-// the same steps in reverse.
-__global__ __launch_bounds__(256) void k_forward_tree(const PTask* __restrict__ slots,
-                                                      const int32_t* __restrict__ blk,
-                                                      const int32_t* __restrict__ cptr,
-                                                      const int32_t* __restrict__ cidx,
-                                                      const double* __restrict__ W,
-                                                      const double* __restrict__ b,
-                                                      const double* __restrict__ scale,
-                                                      double* __restrict__ y, double* upd,
-                                                      const int32_t* done)
-{
-    const int s0 = blk[blockIdx.x], s1 = blk[blockIdx.x + 1];
-    if (done && *done) return;
-    __shared__ double f_all[4][64];
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int s = s0; s < s1; ++s) {
-        const PTask t = slots[4 * s + wv];
-        if (t.nr > 0) fwd_wave(t, lane, f_all[wv], cptr, cidx, W, b, scale, y, upd);
-        __syncthreads();
+    if (q == 0 && c < t.last) {
+        x[t.c0 + c] = acc;
+        sh[t.lds_x + c] = acc;
     }
 }
 
-__global__ __launch_bounds__(256) void k_backward_tree(const PTask* __restrict__ slots,
-                                                       const int32_t* __restrict__ blk,
-                                                       const int32_t* __restrict__ rows,
-                                                       const double* __restrict__ W,
-                                                       const double* __restrict__ y, double* x,
-                                                       const int32_t* done)
+__global__ __launch_bounds__(64 * TW) void k_backward_tree(TreeTasks tr, const double* __restrict__ W,
+                                                          const double* __restrict__ y, double* x,
+                                                          const int32_t* done)
 {
-    const int s0 = blk[blockIdx.x], s1 = blk[blockIdx.x + 1];
+    const int s0 = tr.bblk[blockIdx.x], s1 = tr.bblk[blockIdx.x + 1];
     if (done && *done) return;
-    __shared__ double g_all[4][64];
+    extern __shared__ double lds[];
+    TItem* items = reinterpret_cast<TItem*>(lds);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int s = s1 - 1; s >= s0; --s) {
-        const PTask t = slots[4 * s + wv];
-        if (t.nr > 0) bwd_wave(t, lane, g_all[wv], rows, W, y, x);
+    double* g = lds + tr.item_doubles + wv * tr.ws;
+    double* sh = lds + tr.item_doubles + TW * tr.ws;
+    tree_copy_items(tr.bitems + int64_t(s0) * TW, (s1 - s0) * TW, items);
+    __syncthreads();
+    auto item = [&](int s) -> const TItem& { return items[(s - s0) * TW + wv]; };
+    BwdPre pa, pb;
+    bwd_tree_load(item(s0), lane, tr.trow, W, y, x, pa);
+    for (int s = s0;; s += 2) {
+        bwd_tree_load(item(s + 1 < s1 ? s + 1 : s1 - 1), lane, tr.trow, W, y, x, pb);
+        bwd_tree_step(item(s), pa, lane, g, sh, x);
         __syncthreads();
+        if (s + 1 >= s1) break;
+        bwd_tree_load(item(s + 2 < s1 ? s + 2 : s1 - 1), lane, tr.trow, W, y, x, pa);
+        bwd_tree_step(item(s + 1), pb, lane, g, sh, x);
+        __syncthreads();
+        if (s + 2 >= s1) break;
     }
 }
 
@@ -585,20 +680,21 @@ void launch_backward(const LevelTasks& lv, const int32_t* rows, const double* W,
     }
 }
 
-void launch_forward_tree(const TreeTasks& tr, const int32_t* cptr, const int32_t* cidx,
-                         const double* W, const double* b, const double* scale, double* y,
-                         double* upd, const int32_t* done, hipStream_t st)
+void launch_forward_tree(const TreeTasks& tr, const double* W,
+                         const double* b, const double* scale, double* y, double* upd,
+                         const int32_t* done, hipStream_t st)
 {
     if (tr.n_blocks > 0)
-        k_forward_tree<<<tr.n_blocks, 256, 0, st>>>(tr.fslots, tr.blk, cptr, cidx, W, b, scale, y,
-                                                    upd, done);
+        k_forward_tree<<<tr.n_blocks, 64 * TW, sizeof(double) * size_t(tr.lds_doubles), st>>>(
+            tr, W, b, scale, y, upd, done);
 }
 
-void launch_backward_tree(const TreeTasks& tr, const int32_t* rows, const double* W,
-                          const double* y, double* x, const int32_t* done, hipStream_t st)
+void launch_backward_tree(const TreeTasks& tr, const double* W, const double* y, double* x,
+                          const int32_t* done, hipStream_t st)
 {
     if (tr.n_blocks > 0)
-        k_backward_tree<<<tr.n_blocks, 256, 0, st>>>(tr.bslots, tr.blk, rows, W, y, x, done);
+        k_backward_tree<<<tr.n_blocks, 64 * TW, sizeof(double) * size_t(tr.lds_doubles), st>>>(
+            tr, W, y, x, done);
 }
 
 void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const double* w,

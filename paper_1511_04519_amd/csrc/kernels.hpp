@@ -46,15 +46,40 @@ struct LevelTasks {
     int32_t pad_;
 };
 
-// The bottom levels whose panels have at most 64 rows, as steps of four
-// wavefront slots (slot nr = 0: idle); block b runs steps blk[b] .. blk[b + 1]
-// - 1. fslots / bslots: the same supernodes' forward / backward records.
+// Subtree sweeps of the bottom levels: one block of TW wavefronts per
+// subtree (or per few small subtrees), one wavefront per work item.
+constexpr int TW = 8;
+constexpr int TREE_MAX_NR = 256;   // largest panel (rows) a subtree item takes
+
+struct TItem {
+    int64_t w;        // panel offset of the supernode
+    int64_t aux;      // forward: global update slots (used by subtree roots);
+                      // backward: offset of the off-row list (trow)
+    int32_t c0, nc, nr;
+    int32_t first, last;   // forward: panel rows [first, last); backward: columns
+    int32_t pos;      // forward: contributor list index of panel position 0
+    int32_t lds_u;    // forward: LDS offset of the update slots, -1 for a subtree root
+    int32_t lds_x;    // LDS offset of the supernode's x
+};
+
+// Steps of TW items (nr = 0: idle); block b runs forward steps
+// fblk[b] .. fblk[b + 1] - 1 (children's levels first) and backward steps
+// bblk[b] .. bblk[b + 1] - 1 (root first).
 struct TreeTasks {
-    const PTask* fslots;
-    const PTask* bslots;
-    const int32_t* blk;
+    const TItem* fitems;
+    const TItem* bitems;
+    const int32_t* fblk;
+    const int32_t* bblk;
+    const int2* fdesc;     // per forward item and lane: the LDS slots (offset + 1
+                           // in each 16-bit half, 0 none) adding into btilde at
+                           // column `lane` (.x) and into panel row first + lane (.y)
+    const int32_t* trow;   // per off row: >= 0 global x index, < 0: -1 - LDS offset
     int32_t n_blocks;
     int32_t n_levels;      // levels covered (0 .. n_levels - 1)
+    int32_t ws;            // doubles of each wavefront's scratch (>= 64, >= max nr)
+    int32_t item_doubles;  // LDS doubles holding a block's items
+    int32_t lds_doubles;   // dynamic LDS of a block
+    int32_t pad_;
 };
 
 // Per-Krylov-process device state (one per instance).
@@ -83,11 +108,11 @@ void launch_forward(const LevelTasks& lv, const int32_t* cptr, const int32_t* ci
 // rows: the concatenated off-diagonal row lists.
 void launch_backward(const LevelTasks& lv, const int32_t* rows, const double* W, const double* y,
                      double* x, const int32_t* done, hipStream_t st);
-void launch_forward_tree(const TreeTasks& tr, const int32_t* cptr, const int32_t* cidx,
-                         const double* W, const double* b, const double* scale, double* y,
-                         double* upd, const int32_t* done, hipStream_t st);
-void launch_backward_tree(const TreeTasks& tr, const int32_t* rows, const double* W,
-                          const double* y, double* x, const int32_t* done, hipStream_t st);
+void launch_forward_tree(const TreeTasks& tr, const double* W,
+                         const double* b, const double* scale, double* y, double* upd,
+                         const int32_t* done, hipStream_t st);
+void launch_backward_tree(const TreeTasks& tr, const double* W, const double* y, double* x,
+                          const int32_t* done, hipStream_t st);
 
 // ---- Gram-Schmidt (two classical passes) -----------------------------------
 // partial: 2 * RED_BLOCKS * (MAXM + 2) doubles of scratch (two passes).

@@ -37,13 +37,14 @@ class Netlist(ctypes.Structure):
 
 
 class FactorOpts(ctypes.Structure):
-    _fields_ = [("n_shifts", _i32), ("leaf_max", _i32)]
+    _fields_ = [("n_shifts", _i32), ("leaf_max", _i32), ("subtree_levels", _i32)]
 
 
 class FactorInfo(ctypes.Structure):
     _fields_ = [("n", _i64), ("nnz_l", _i64), ("panel_doubles", _i64), ("n_supernodes", _i32),
                 ("n_levels", _i32), ("n_shifts", _i32), ("max_nr", _i32), ("gamma", _f64),
-                ("seconds_analyse", _f64), ("seconds_numeric", _f64), ("device_bytes", _i64)]
+                ("seconds_analyse", _f64), ("seconds_numeric", _f64), ("device_bytes", _i64),
+                ("subtree_levels", _i32), ("subtree_blocks", _i32)]
 
 
 class Problem(ctypes.Structure):
@@ -163,7 +164,7 @@ class FactorHandle:
 
 
 def matex_factor(netlist, gamma: float, n_shifts: int = 6, leaf_max: int = 16,
-                 use_coords: bool = True) -> FactorHandle:
+                 use_coords: bool = True, subtree_levels: int = 0) -> FactorHandle:
     """Factor C + gamma_k G for the shift ladder and G (see matex.h)."""
     a = np.ascontiguousarray(netlist.br_a, np.int32)
     b = np.ascontiguousarray(netlist.br_b, np.int32)
@@ -176,7 +177,7 @@ def matex_factor(netlist, gamma: float, n_shifts: int = 6, leaf_max: int = 16,
                  _p(g, ctypes.c_double), _p(c, ctypes.c_double), pn.size, _p(pn, ctypes.c_int32),
                  _p(pg, ctypes.c_double), float(netlist.vdd),
                  _p(crd, ctypes.c_int32) if crd is not None else None)
-    opts = FactorOpts(n_shifts, leaf_max)
+    opts = FactorOpts(n_shifts, leaf_max, subtree_levels)
     h = ctypes.c_void_p()
     _check(lib().matex_factor(ctypes.byref(nl), float(gamma), ctypes.byref(opts), _stream(),
                               ctypes.byref(h)))
