@@ -15,11 +15,40 @@ namespace dev {
 // Leading dimension of a panel with nr rows (device twin of panel_ld).
 __device__ inline int dpanel_ld(int nr) { return (nr + PANEL_ALIGN - 1) / PANEL_ALIGN * PANEL_ALIGN; }
 
+// A double moved across lanes by one DPP pattern (both 32-bit halves).
+template <int CTRL>
+__device__ inline double dpp(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each aligned group of g lanes (g a power of two, 1..64), left in
+// every lane of the group. Within 16-lane rows the steps are DPP moves (quad
+// permutes, then the half-row and row mirrors, each pairing a lane with one
+// holding the other half's partial); across rows, lane shuffles. Every lane
+// of the wavefront must be active.
+__device__ inline double group_sum(double v, int g)
+{
+    if (g >= 2) v += dpp<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    if (g >= 4) v += dpp<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    if (g >= 8) v += dpp<0x141>(v);   // row_half_mirror
+    if (g >= 16) v += dpp<0x140>(v);  // row_mirror
+    if (g >= 32) v += __shfl_xor(v, 16, 64);
+    if (g >= 64) v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Wavefront sum, returned in every lane (every lane must be active).
 __device__ inline double wave_sum(double v)
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    return v;
+    v = group_sum(v, 16);
+    auto row = [&](int l) {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                                __builtin_amdgcn_readlane(__double2loint(v), l));
+    };
+    return (row(0) + row(16)) + (row(32) + row(48));
 }
 
 // Block-wide sum of one value per thread (256 threads); result valid in thread 0.
@@ -56,10 +85,11 @@ __device__ inline bool last_block(int32_t* counter) { return last_of(counter, in
 
 constexpr int NVMAX = MAXM + 1;
 
-// Sums acc[0..cnt) over the block with one barrier: wavefront shuffles, then
-// the four wavefront partials of value i are added by thread i. Result in
-// out[i] (LDS) for i < cnt. red: LDS scratch of 4 * (NVMAX + 1) doubles.
-template <int N>
+// Sums acc[0..cnt) over a block of NW wavefronts with one barrier: wavefront
+// sums, then the NW wavefront partials of value i are added by thread i in
+// wavefront order. Result in out[i] (LDS) for i < cnt. red: LDS scratch of
+// NW * (NVMAX + 1) doubles.
+template <int N, int NW = 4>
 __device__ inline void block_sums(const double (&acc)[N], int cnt, double* red, double* out)
 {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -73,13 +103,38 @@ __device__ inline void block_sums(const double (&acc)[N], int cnt, double* red, 
     __syncthreads();
     if (threadIdx.x < cnt) {
         const int i = threadIdx.x;
-        out[i] = (red[i] + red[(NVMAX + 1) + i]) + (red[2 * (NVMAX + 1) + i] + red[3 * (NVMAX + 1) + i]);
+        if (NW == 4) {
+            out[i] = (red[i] + red[(NVMAX + 1) + i]) + (red[2 * (NVMAX + 1) + i] + red[3 * (NVMAX + 1) + i]);
+        } else {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NW; ++q) s += red[q * (NVMAX + 1) + i];
+            out[i] = s;
+        }
     }
     __syncthreads();
 }
 
 // In the last block: out[i] = sum_b partial[b * stride + i] for i < cnt,
 // b < nblk (<= 256), with one partial row per thread and one block reduction.
+// out[i] = sum_b partial[b * stride + i] for i < cnt, b < nblk, by a block of
+// NW wavefronts: value i by wavefront i mod NW, the rows split over its lanes
+// (fixed order), then a wavefront sum. Few registers.
+template <int NW>
+__device__ inline void reduce_partials_waves(const double* partial, int stride, int nblk, int cnt,
+                                             double* out)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = wv; i < cnt; i += NW) {
+        double s = 0.0;
+        for (int b = lane; b < nblk; b += 64) s += partial[int64_t(b) * stride + i];
+        s = wave_sum(s);
+        if (lane == 0) out[i] = s;
+    }
+    __syncthreads();
+}
+
+template <int NW = 4>
 __device__ inline void reduce_partials(const double* partial, int stride, int nblk, int cnt,
                                        double* red, double* out)
 {
@@ -88,7 +143,7 @@ __device__ inline void reduce_partials(const double* partial, int stride, int nb
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i)
         acc[i] = (i < cnt && b < nblk) ? partial[int64_t(b) * stride + i] : 0.0;
-    block_sums(acc, cnt, red, out);
+    block_sums<NVMAX, NW>(acc, cnt, red, out);
 }
 
 // Pass 1: per-block partial dots V_i^T w, i < nv, into partial[block][i].
@@ -122,7 +177,9 @@ __device__ inline void mm(const double* A, const double* B, double* C, int m)
 }
 
 // Solve Q X = P in place (X overwrites P) by Gaussian elimination with partial
-// pivoting; Q is destroyed. Whole block.
+// pivoting (the first row of largest magnitude); Q is destroyed (its
+// eliminated entries are left as they are: only the upper triangle is read
+// afterwards). Whole block.
 template <int L = LD>
 __device__ inline void solve_inplace(double* Q, double* P, int m, int ncol)
 {
@@ -131,32 +188,32 @@ __device__ inline void solve_inplace(double* Q, double* P, int m, int ncol)
         if (threadIdx.x == 0) {
             int p = k;
             double best = fabs(Q[k * L + k]);
-            for (int i = k + 1; i < m; ++i)
-                if (fabs(Q[i * L + k]) > best) { best = fabs(Q[i * L + k]); p = i; }
+            for (int i = k + 1; i < m; ++i) {
+                const double v = fabs(Q[i * L + k]);
+                if (v > best) { best = v; p = i; }
+            }
             piv = p;
         }
         __syncthreads();
         const int p = piv;
         if (p != k) {
-            for (int j = threadIdx.x; j < m; j += blockDim.x) {
+            for (int j = k + threadIdx.x; j < m; j += blockDim.x) {
                 const double t = Q[k * L + j]; Q[k * L + j] = Q[p * L + j]; Q[p * L + j] = t;
             }
             for (int j = threadIdx.x; j < ncol; j += blockDim.x) {
                 const double t = P[k * L + j]; P[k * L + j] = P[p * L + j]; P[p * L + j] = t;
             }
+            __syncthreads();
         }
-        __syncthreads();
         const double dk = Q[k * L + k];
-        const int rows = m - k - 1;
-        for (int idx = threadIdx.x; idx < rows * (m - k + ncol); idx += blockDim.x) {
-            const int i = k + 1 + idx / (m - k + ncol);
-            const int c = idx % (m - k + ncol);
+        const int rows = m - k - 1, w = m - k - 1 + ncol;
+        for (int idx = threadIdx.x; idx < rows * w; idx += blockDim.x) {
+            const int i = k + 1 + idx / w;
+            const int c = idx - (idx / w) * w;
             const double f = Q[i * L + k] / dk;
-            if (c < m - k) { if (c > 0) Q[i * L + k + c] -= f * Q[k * L + k + c]; }
-            else P[i * L + (c - (m - k))] -= f * P[k * L + (c - (m - k))];
+            if (c < m - k - 1) Q[i * L + k + 1 + c] -= f * Q[k * L + k + 1 + c];
+            else P[i * L + (c - (m - k - 1))] -= f * P[k * L + (c - (m - k - 1))];
         }
-        __syncthreads();
-        for (int i = k + 1 + threadIdx.x; i < m; i += blockDim.x) Q[i * L + k] = 0.0;
         __syncthreads();
     }
     // back substitution, one column per thread
@@ -204,15 +261,19 @@ __device__ inline double* expm_mat(double* H, int m, double tau, double* buf)
     double* Vm = H;
     __shared__ double nrm;
     __shared__ int sq;
-    // 1-norm of tau H
-    if (threadIdx.x == 0) {
+    // 1-norm of tau H: column sums by wavefront 0, then their maximum
+    if (threadIdx.x < 64) {
         double best = 0.0;
-        for (int j = 0; j < m; ++j) {
+        for (int j = threadIdx.x; j < m; j += 64) {
             double c = 0.0;
             for (int i = 0; i < m; ++i) c += fabs(H[i * L + j]);
             best = fmax(best, c);
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o, 64));
         nrm = best * tau;
+    }
+    if (threadIdx.x == 0) {
         // a non-finite norm gives no squarings (the result is then NaN, as
         // it must be) instead of an unbounded count
         int s = 0;

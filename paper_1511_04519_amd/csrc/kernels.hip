@@ -162,8 +162,7 @@ __global__ __launch_bounds__(256) void k_backward(const PTask* __restrict__ task
 #pragma unroll
         for (int p = 0; p < PF; ++p) a[p] = nx[p];
     }
-#pragma unroll
-    for (int o = LPC / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    acc = group_sum(acc, LPC);
     if (q == 0 && col < t.nc) x[t.c0 + col] = acc;
 }
 
@@ -357,7 +356,7 @@ __device__ inline void bwd_tree_step(const TItem& t, const BwdPre& p, int lane, 
         const int k = c + q + i * lpc;
         acc += k < kend ? p.a[i] * g[k] : 0.0;
     }
-    for (int o = lpc >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    acc = group_sum(acc, lpc);
     if (q == 0 && c < t.last) {
         x[t.c0 + c] = acc;
         sh[t.lds_x + c] = acc;
@@ -397,79 +396,127 @@ __global__ __launch_bounds__(64 * TW) void k_backward_tree(TreeTasks tr, const d
 // ---------------------------------------------------------- Gram-Schmidt
 
 
-// KState scratch for the reductions lives after the struct in one buffer:
-// partials of the current pass, [RED_BLOCKS][NVMAX + 1].
+// Blocks of GS_THREADS threads (RED_BLOCKS of them at most), so the rows of
+// a 10^5-node vector are all in flight at once; partials of a pass,
+// [RED_BLOCKS][NVMAX + 1].
+constexpr int GS_THREADS = 1024, GS_WAVES = GS_THREADS / 64;
 
-__global__ __launch_bounds__(256) void k_gs_dots(int64_t n, const double* __restrict__ V,
-                                                 int64_t ldv, int nv,
-                                                 const double* __restrict__ w,
-                                                 double* partial, const int32_t* done)
+// Values per wavefront in the value-major reductions: value i (a basis
+// vector, or slot nv for the squared norm) belongs to wavefront i mod GS_WAVES.
+constexpr int GS_VPW = (NVMAX + 1 + GS_WAVES - 1) / GS_WAVES;
+
+// Dot products over one tile of GS_THREADS rows staged in LDS (wl): acc[q]
+// += sum_t wl[t] * V_i[base + t] for the wavefront's values i < nv, and
+// wl[t]^2 for i == nv when `norm`. Lanes take rows lane, lane + 64, ...
+__device__ inline void gs_tile_dots(const double* V, int64_t ldv, int nv, bool norm, int64_t base,
+                                    int rows, const double* wl, double (&acc)[GS_VPW])
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < GS_VPW; ++q) {
+        const int i = wv + q * GS_WAVES;
+        if (i < nv) {
+            const double* Vi = V + int64_t(i) * ldv + base;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < GS_THREADS / 64; ++k) {
+                const int t = lane + 64 * k;
+                if (t < rows) s += wl[t] * Vi[t];
+            }
+            acc[q] += s;
+        } else if (norm && i == nv) {
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < GS_THREADS / 64; ++k) {
+                const int t = lane + 64 * k;
+                if (t < rows) s += wl[t] * wl[t];
+            }
+            acc[q] += s;
+        }
+    }
+}
+
+// The wavefront sums of acc into partial[blockIdx.x][i], i < cnt.
+__device__ inline void gs_store_partials(const double (&acc)[GS_VPW], int cnt, double* partial)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < GS_VPW; ++q) {
+        const int i = wv + q * GS_WAVES;
+        if (i < cnt) {
+            const double t = wave_sum(acc[q]);
+            if (lane == 0) partial[int64_t(blockIdx.x) * (NVMAX + 1) + i] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const double* __restrict__ V,
+                                                        int64_t ldv, int nv,
+                                                        const double* __restrict__ w,
+                                                        double* partial, const int32_t* done)
 {
     if (done && *done) return;
-    __shared__ double red[4 * (NVMAX + 1)];
-    __shared__ double vals[NVMAX + 1];
-    double acc[NVMAX];
+    __shared__ double wl[GS_THREADS];
+    double acc[GS_VPW];
 #pragma unroll
-    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
-    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256) {
-        const double wr = w[r];
-#pragma unroll
-        for (int i = 0; i < NVMAX; ++i)
-            if (i < nv) acc[i] += wr * V[r + i * ldv];
+    for (int q = 0; q < GS_VPW; ++q) acc[q] = 0.0;
+    for (int64_t base = int64_t(blockIdx.x) * GS_THREADS; base < n; base += int64_t(gridDim.x) * GS_THREADS) {
+        const int64_t r = base + threadIdx.x;
+        wl[threadIdx.x] = r < n ? w[r] : 0.0;
+        __syncthreads();
+        gs_tile_dots(V, ldv, nv, false, base, int(min<int64_t>(GS_THREADS, n - base)), wl, acc);
+        __syncthreads();
     }
-    block_sums(acc, nv, red, vals);
-    if (threadIdx.x < nv) partial[int64_t(blockIdx.x) * (NVMAX + 1) + threadIdx.x] = vals[threadIdx.x];
+    gs_store_partials(acc, nv, partial);
 }
 
 // Every block sums the previous kernel's partials itself (fixed order), so no
 // cross-block publication is needed inside a kernel. h1 = sum of pass-1
 // partials; w' = w - V h1 in place; pass-2 partials V^T w' and ||w'||^2
 // (slot nv) into partial_out.
-__global__ __launch_bounds__(256) void k_gs_update(int64_t n, const double* __restrict__ V,
-                                                   int64_t ldv, int nv, double* w,
-                                                   const double* partial_in, double* partial_out,
-                                                   KState* ks, const int32_t* done)
+__global__ __launch_bounds__(GS_THREADS) void k_gs_update(int64_t n, const double* __restrict__ V,
+                                                          int64_t ldv, int nv, double* w,
+                                                          const double* partial_in, double* partial_out,
+                                                          KState* ks, const int32_t* done)
 {
     if (done && *done) return;
     __shared__ double h[NVMAX + 1];
-    __shared__ double red[4 * (NVMAX + 1)];
-    __shared__ double vals[NVMAX + 1];
-    reduce_partials(partial_in, NVMAX + 1, gridDim.x, nv, red, h);
+    __shared__ double wl[GS_THREADS];
+    reduce_partials_waves<GS_WAVES>(partial_in, NVMAX + 1, gridDim.x, nv, h);
     if (blockIdx.x == 0 && threadIdx.x < nv) ks->h1[threadIdx.x] = h[threadIdx.x];
-    // nv <= MAXM, so the dots (slots 0..nv-1) and ||w'||^2 (slot nv) fit NVMAX
-    double acc[NVMAX];
+    double acc[GS_VPW];
 #pragma unroll
-    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
-    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256) {
-        double wr = w[r];
-#pragma unroll
-        for (int i = 0; i < NVMAX; ++i)
-            if (i < nv) wr -= h[i] * V[r + i * ldv];
-        w[r] = wr;
-#pragma unroll
-        for (int i = 0; i < NVMAX; ++i) {
-            if (i < nv) acc[i] += wr * V[r + i * ldv];
-            else if (i == nv) acc[i] += wr * wr;
+    for (int q = 0; q < GS_VPW; ++q) acc[q] = 0.0;
+    for (int64_t base = int64_t(blockIdx.x) * GS_THREADS; base < n; base += int64_t(gridDim.x) * GS_THREADS) {
+        const int64_t r = base + threadIdx.x;
+        double wr = 0.0;
+        if (r < n) {
+            wr = w[r];
+#pragma unroll 8
+            for (int i = 0; i < nv; ++i) wr -= h[i] * V[r + i * ldv];
+            w[r] = wr;
         }
+        wl[threadIdx.x] = wr;
+        __syncthreads();
+        gs_tile_dots(V, ldv, nv, true, base, int(min<int64_t>(GS_THREADS, n - base)), wl, acc);
+        __syncthreads();
     }
-    block_sums(acc, nv + 1, red, vals);
-    if (threadIdx.x <= nv) partial_out[int64_t(blockIdx.x) * (NVMAX + 1) + threadIdx.x] = vals[threadIdx.x];
+    gs_store_partials(acc, nv + 1, partial_out);
 }
 
 // w'' = w' - V h2, ||w''||^2 = ||w'||^2 - ||h2||^2 (w' is already orthogonal
 // to working precision after the first pass, so there is no cancellation);
 // v_{j+1} = w'' / ||w''||, and column j of Ht = h1 + h2 with Ht(j+1,j) = ||w''||.
 // Every block sums the pass-2 partials itself; block 0 records the column.
-__global__ __launch_bounds__(256) void k_gs_finish(int64_t n, double* V, int64_t ldv, int nv,
+__global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, int64_t ldv, int nv,
                                                    const double* __restrict__ w,
                                                    const double* partial_in, KState* ks,
                                                    const int32_t* done)
 {
     if (done && *done) return;
     __shared__ double h[NVMAX + 1];
-    __shared__ double red[4 * (NVMAX + 1)];
     __shared__ double sc;
-    reduce_partials(partial_in, NVMAX + 1, gridDim.x, nv + 1, red, h);
+    reduce_partials_waves<GS_WAVES>(partial_in, NVMAX + 1, gridDim.x, nv + 1, h);
     if (threadIdx.x == 0) {
         double s2 = 0.0, hmax = 0.0;
         for (int i = 0; i < nv; ++i) {
@@ -491,11 +538,10 @@ __global__ __launch_bounds__(256) void k_gs_finish(int64_t n, double* V, int64_t
     __syncthreads();
     const double inv = sc;
     double* vout = V + int64_t(nv) * ldv;
-    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256) {
+    for (int64_t r = int64_t(blockIdx.x) * GS_THREADS + threadIdx.x; r < n; r += int64_t(gridDim.x) * GS_THREADS) {
         double wr = w[r];
-#pragma unroll
-        for (int i = 0; i < NVMAX; ++i)
-            if (i < nv) wr -= h[i] * V[r + i * ldv];
+#pragma unroll 8
+        for (int i = 0; i < nv; ++i) wr -= h[i] * V[r + i * ldv];
         vout[r] = wr * inv;
     }
 }
@@ -642,6 +688,7 @@ __global__ void k_vdd_minus(int64_t count, double vdd, double* buf)
 }
 
 inline int grid_for(int64_t n) { return int(std::min<int64_t>((n + 255) / 256, RED_BLOCKS)); }
+inline int gs_grid(int64_t n) { return int(std::min<int64_t>((n + GS_THREADS - 1) / GS_THREADS, RED_BLOCKS)); }
 
 }  // namespace
 
@@ -701,21 +748,21 @@ void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const doubl
                     double* partial, KState* ks, const int32_t* done, hipStream_t st)
 {
     (void)ks;
-    k_gs_dots<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial, done);
+    k_gs_dots<<<gs_grid(n), GS_THREADS, 0, st>>>(n, V, ldv, nv, w, partial, done);
 }
 
 void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w,
                       double* partial, KState* ks, const int32_t* done, hipStream_t st)
 {
     const int64_t half = int64_t(RED_BLOCKS) * (MAXM + 2);
-    k_gs_update<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial, partial + half, ks, done);
+    k_gs_update<<<gs_grid(n), GS_THREADS, 0, st>>>(n, V, ldv, nv, w, partial, partial + half, ks, done);
 }
 
 void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w,
                       const double* partial, KState* ks, const int32_t* done, hipStream_t st)
 {
     const int64_t half = int64_t(RED_BLOCKS) * (MAXM + 2);
-    k_gs_finish<<<grid_for(n), 256, 0, st>>>(n, V, ldv, nv, w, partial + half, ks, done);
+    k_gs_finish<<<gs_grid(n), GS_THREADS, 0, st>>>(n, V, ldv, nv, w, partial + half, ks, done);
 }
 
 size_t checks_lds_bytes() { return sizeof(double) * (7 * MAXM * LD + 2 * MAXM); }

@@ -84,6 +84,37 @@ def test_multi_rhs_solve_large_supernodes(case, which, nrhs):
     assert np.abs(x1 - ref[nrhs - 1]).max() <= 1e-12 * np.abs(ref[nrhs - 1]).max()
 
 
+@pytest.mark.parametrize("case,limits", [
+    ("2x70x55", [-1, 1, 2, 3, 4, 0]),   # one subtree per block down to a few blocks
+    ("2x120x100", [-1, 0, 3]),          # 24,000 nodes: the automatic depth leaves >= 512 blocks
+    ("1x150x9", [-1, 0]),               # deep thin tree
+])
+def test_one_vector_solve_every_subtree_depth(case, limits):
+    """The one-vector sweeps with the bottom levels taken as whole subtrees
+    (LDS-resident) to every depth, and with none, agree with the oracle."""
+    L, nx, ny = map(int, case.split("x"))
+    p = I.small(7, layers=L, nx=nx, ny=ny, n_src=3)
+    nl = p.netlist
+    rng = np.random.default_rng(13)
+    b = rng.standard_normal(nl.n)
+    rp, ci, gv = C.assemble_G(nl)
+    vals = C.csr_add_diag(rp, ci, gv, nl.c_node, alpha=GAMMA)
+    ref = C.Cholesky(rp, ci, vals).solve(b * nl.c_node)
+    ref_g = C.Cholesky(rp, ci, gv).solve(b)
+    for lim in limits:
+        F = M.matex_factor(nl, GAMMA, n_shifts=1, subtree_levels=lim)
+        _note(f"solve {case} subtree_levels={lim}: depth {F.info['subtree_levels']}, "
+              f"{F.info['subtree_blocks']} blocks")
+        if lim < 0:
+            assert F.info["subtree_levels"] == 0
+        elif lim > 0:
+            assert F.info["subtree_levels"] <= lim
+        x = M.matex_solve(F, 0, _dev(b), _dev(nl.c_node)).cpu().numpy()
+        assert np.abs(x - ref).max() <= 1e-12 * np.abs(ref).max()
+        x = M.matex_solve(F, -1, _dev(b)).cpu().numpy()
+        assert np.abs(x - ref_g).max() <= 1e-12 * np.abs(ref_g).max()
+
+
 # ------------------------------------------------------------ krylov step
 
 def test_krylov_step_matches_oracle_and_dense_expm():
