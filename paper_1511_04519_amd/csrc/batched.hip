@@ -441,6 +441,7 @@ __global__ __launch_bounds__(256) void kb_col_reduce(int R, int nblk, const doub
         const double beta = sqrt(vals[0]);
         k->beta = beta;
         k->m = 0;
+        k->mdec = 0;
         k->breakdown = 0;
         k->converged = beta == 0.0 ? 1 : 0;
         k->done = beta == 0.0 ? 1 : 0;
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(256) void kb_checks(KState* ks, double gamma, const
     if (update_state && k->done) return;
     extern __shared__ double sm[];
     const int64_t reg = int64_t(r) * cap;
-    check_block(k, gamma, taus + tau_off[r], c, chk_idx + col_off[r], col_cnt[r], tol, u_buf + reg * MAXM,
+    check_block(k, k->m, k->breakdown, gamma, taus + tau_off[r], c, chk_idx + col_off[r], col_cnt[r], tol, u_buf + reg * MAXM,
                 est_buf + reg, m_max, update_state, sm);
 }
 

@@ -15,6 +15,16 @@ namespace dev {
 // Leading dimension of a panel with nr rows (device twin of panel_ld).
 __device__ inline int dpanel_ld(int nr) { return (nr + PANEL_ALIGN - 1) / PANEL_ALIGN * PANEL_ALIGN; }
 
+// Orders one wavefront's LDS accesses around a point where its lanes read
+// what other lanes wrote: the wavefront's LDS operations complete in order,
+// so only the compiler must keep them on their side.
+__device__ inline void wave_sync()
+{
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // A double moved across lanes by one DPP pattern (both 32-bit halves).
 template <int CTRL>
 __device__ inline double dpp(double v)
@@ -163,6 +173,11 @@ constexpr double THETA13 = 5.371920351148152;
 // L = LD for matrices in LDS (at most MAXM rows), a larger L for matrices in
 // a global-memory workspace. A matrix buffer holds (L - 1) x L doubles.
 
+// Operands of a k-loop in LDS are loaded KB at a time (indices clamped to the
+// matrix, the surplus products dropped), so their latencies overlap; the
+// sums keep their order.
+constexpr int KB = 8;
+
 // C = A * B (m x m, row-major, stride L) by the whole block.
 template <int L = LD>
 __device__ inline void mm(const double* A, const double* B, double* C, int m)
@@ -170,7 +185,18 @@ __device__ inline void mm(const double* A, const double* B, double* C, int m)
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
         const int i = idx / m, j = idx - (idx / m) * m;
         double s = 0.0;
-        for (int k = 0; k < m; ++k) s += A[i * L + k] * B[k * L + j];
+        for (int k0 = 0; k0 < m; k0 += KB) {
+            double a[KB], b[KB];
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int k = min(k0 + q, m - 1);
+                a[q] = A[i * L + k];
+                b[q] = B[k * L + j];
+            }
+#pragma unroll
+            for (int q = 0; q < KB; ++q)
+                if (k0 + q < m) s += a[q] * b[q];
+        }
         C[i * L + j] = s;
     }
     __syncthreads();
@@ -227,6 +253,135 @@ __device__ inline void solve_inplace(double* Q, double* P, int m, int ncol)
     __syncthreads();
 }
 
+// Back substitution X = U^-1 X on one wavefront: U in the upper triangle of
+// Q, lane j < ncol solving column j of P in place.
+template <int L = LD>
+__device__ inline void back_subst_wave(const double* Q, double* P, int m, int ncol)
+{
+    const int j = threadIdx.x & 63;
+    if (j >= ncol) return;
+    for (int i = m - 1; i >= 0; --i) {
+        double s = P[i * L + j];
+        for (int k0 = i + 1; k0 < m; k0 += KB) {
+            double u[KB], x[KB];
+#pragma unroll
+            for (int q = 0; q < KB; ++q) {
+                const int k = min(k0 + q, m - 1);
+                u[q] = Q[i * L + k];
+                x[q] = P[k * L + j];
+            }
+#pragma unroll
+            for (int q = 0; q < KB; ++q)
+                if (k0 + q < m) s -= u[q] * x[q];
+        }
+        P[i * L + j] = s / Q[i * L + i];
+    }
+}
+
+// Ht_m^-1 into P (row-major, stride L) by Gaussian elimination with partial
+// pivoting on one wavefront; Q holds Ht_m (row-major) on entry and U on
+// return. Ht_m is upper Hessenberg, so the pivot of column k is row k or
+// k + 1 and only row k + 1 is eliminated: the operations of the general
+// elimination, whose other multipliers are zero. Lane j owns column j and
+// carries rows k and k + 1 of Q and of P (= I initially) in registers; the
+// pivot entries come from lane k by readlane; row k + 2 is read ahead.
+template <int L = LD>
+__device__ inline void hessenberg_inverse(int m, double* Q, double* P)
+{
+    const int j = threadIdx.x & 63;
+    const bool col = j < m;
+    auto bcast = [](double v, int lane) {
+        return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                                __builtin_amdgcn_readlane(__double2loint(v), lane));
+    };
+    double qk = col ? Q[j] : 0.0;
+    double pk = j == 0 ? 1.0 : 0.0;
+    double qn = col && m > 1 ? Q[L + j] : 0.0;
+    wave_sync();
+    for (int k = 0; k + 1 < m; ++k) {
+        const double qnn = col && k + 2 < m ? Q[(k + 2) * L + j] : 0.0;
+        double pn = j == k + 1 ? 1.0 : 0.0;
+        const double a = bcast(qk, k), b = bcast(qn, k);
+        if (fabs(b) > fabs(a)) {
+            const double t = qk; qk = qn; qn = t;
+            const double tp = pk; pk = pn; pn = tp;
+        }
+        const double f = bcast(qn, k) / bcast(qk, k);
+        if (j > k) qn -= f * qk;
+        pn -= f * pk;
+        wave_sync();
+        if (j < L) { Q[k * L + j] = qk; P[k * L + j] = pk; }
+        qk = qn; pk = pn; qn = qnn;
+    }
+    if (j < L) { Q[(m - 1) * L + j] = qk; P[(m - 1) * L + j] = pk; }
+    wave_sync();
+    back_subst_wave<L>(Q, P, m, m);
+}
+
+// Solve Q X = P in place on one wavefront (m + ncol <= 64): the operations
+// and their order are those of solve_inplace. Lane c < m owns column c of Q,
+// lane m + c column c of P; every lane scans the pivot column (LDS
+// broadcast reads, KB at a time).
+template <int L = LD>
+__device__ inline void solve_wave(double* Q, double* P, int m, int ncol)
+{
+    const int lane = threadIdx.x & 63;
+    const bool isq = lane < m, isp = lane >= m && lane < m + ncol;
+    double* col = isq ? Q + lane : P + (isp ? lane - m : 0);
+    for (int k = 0; k < m; ++k) {
+        int p = k;
+        double best = fabs(Q[k * L + k]);
+        for (int i0 = k + 1; i0 < m; i0 += KB) {
+            double v[KB];
+#pragma unroll
+            for (int q = 0; q < KB; ++q) v[q] = fabs(Q[min(i0 + q, m - 1) * L + k]);
+#pragma unroll
+            for (int q = 0; q < KB; ++q)
+                if (i0 + q < m && v[q] > best) { best = v[q]; p = i0 + q; }
+        }
+        wave_sync();
+        if (p != k && ((isq && lane >= k) || isp)) {
+            const double t = col[k * L]; col[k * L] = col[p * L]; col[p * L] = t;
+        }
+        wave_sync();
+        const double dk = Q[k * L + k];
+        if ((isq && lane > k) || isp) {
+            const double top = col[k * L];
+            for (int i0 = k + 1; i0 < m; i0 += KB) {
+                double f[KB], c[KB];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) {
+                    const int i = min(i0 + q, m - 1);
+                    f[q] = Q[i * L + k];
+                    c[q] = col[i * L];
+                }
+#pragma unroll
+                for (int q = 0; q < KB; ++q)
+                    if (i0 + q < m) col[(i0 + q) * L] = c[q] - (f[q] / dk) * top;
+            }
+        }
+        wave_sync();
+    }
+    if (isp) {
+        for (int i = m - 1; i >= 0; --i) {
+            double s = col[i * L];
+            for (int k0 = i + 1; k0 < m; k0 += KB) {
+                double u[KB], x[KB];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) {
+                    const int k = min(k0 + q, m - 1);
+                    u[q] = Q[i * L + k];
+                    x[q] = col[k * L];
+                }
+#pragma unroll
+                for (int q = 0; q < KB; ++q)
+                    if (k0 + q < m) s -= u[q] * x[q];
+            }
+            col[i * L] = s / Q[i * L + i];
+        }
+    }
+}
+
 // H = (I - Ht_m^-1) / gamma into H (row-major, stride L); uses T1.
 template <int L = LD>
 __device__ inline void form_h(const KState* ks, int m, double gamma, double* H, double* T1)
@@ -234,10 +389,10 @@ __device__ inline void form_h(const KState* ks, int m, double gamma, double* H, 
     for (int idx = threadIdx.x; idx < m * L; idx += blockDim.x) {
         const int i = idx / L, j = idx % L;
         T1[idx] = (j < m) ? ks->Ht[i + j * (MAXM + 1)] : 0.0;
-        H[idx] = (j < m && i == j) ? 1.0 : 0.0;
     }
     __syncthreads();
-    solve_inplace<L>(T1, H, m, m);        // H = Ht^-1
+    if (threadIdx.x < 64) hessenberg_inverse<L>(m, T1, H);   // H = Ht^-1
+    __syncthreads();
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
         const int i = idx / m, j = idx % m;
         H[i * L + j] = ((i == j ? 1.0 : 0.0) - H[i * L + j]) / gamma;
@@ -266,7 +421,14 @@ __device__ inline double* expm_mat(double* H, int m, double tau, double* buf)
         double best = 0.0;
         for (int j = threadIdx.x; j < m; j += 64) {
             double c = 0.0;
-            for (int i = 0; i < m; ++i) c += fabs(H[i * L + j]);
+            for (int i0 = 0; i0 < m; i0 += KB) {
+                double v[KB];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) v[q] = H[min(i0 + q, m - 1) * L + j];
+#pragma unroll
+                for (int q = 0; q < KB; ++q)
+                    if (i0 + q < m) c += fabs(v[q]);
+            }
             best = fmax(best, c);
         }
 #pragma unroll
@@ -317,7 +479,12 @@ __device__ inline double* expm_mat(double* H, int m, double tau, double* buf)
         A4[o] = v + uu;   // P
     }
     __syncthreads();
-    solve_inplace<L>(A2, A4, m, m);            // R = Q^-1 P in A4
+    if (2 * m <= 64) {                         // R = Q^-1 P in A4
+        if (threadIdx.x < 64) solve_wave<L>(A2, A4, m, m);
+        __syncthreads();
+    } else {
+        solve_inplace<L>(A2, A4, m, m);
+    }
     double* R = A4;
     double* S = A6;
     for (int k = 0; k < sq; ++k) {
@@ -336,7 +503,8 @@ __device__ inline void expm_e1(double* H, int m, double tau, double* buf, double
 }
 
 
-// One check offset of one Krylov process (block-wide): H_m from Ht, u =
+// One check offset of one Krylov process (block-wide) at dimension m (brk:
+// the basis broke down at m): H_m from Ht, u =
 // e^{tau H_m} e1 into u_buf[c], the estimate into est_buf[c]; the last of
 // the n_sel blocks of the process takes the maximum over the checked
 // offsets (sel[0 .. n_sel), or 0 .. n_sel - 1 when sel is null) and decides.
@@ -344,7 +512,7 @@ __device__ inline void expm_e1(double* H, int m, double tau, double* buf, double
 // and the decision may end the process) or only evaluating a check set on a
 // fixed basis.
 // sm: 7 * MAXM * LD + 2 * MAXM doubles.
-__device__ inline void check_block(KState* ks, double gamma, const double* taus, int c,
+__device__ inline void check_block(KState* ks, int m, int brk, double gamma, const double* taus, int c,
                                    const int32_t* sel, int n_sel, double tol, double* u_buf,
                                    double* est_buf, int m_max, int update_state, double* sm)
 {
@@ -353,7 +521,6 @@ __device__ inline void check_block(KState* ks, double gamma, const double* taus,
     double* u = buf + 6 * MAXM * LD;         // MAXM
     double* up = u + MAXM;                   // MAXM
     __shared__ double red[4];
-    const int m = ks->m;
     const double tau = taus[c];
     form_h(ks, m, gamma, H, buf);
     expm_e1(H, m, tau, buf, u);
@@ -380,7 +547,7 @@ __device__ inline void check_block(KState* ks, double gamma, const double* taus,
             const double d = u[i] - prev;
             d2 += d * d;
         }
-        const double est = ks->breakdown ? 0.0 : fmax(paper, beta * sqrt(d2));
+        const double est = brk ? 0.0 : fmax(paper, beta * sqrt(d2));
         est_buf[c] = est;
     }
     for (int i = threadIdx.x; i < m; i += blockDim.x) u_buf[c * MAXM + i] = u[i];
@@ -399,9 +566,12 @@ __device__ inline void check_block(KState* ks, double gamma, const double* taus,
             double mx = 0.0;
             for (int q = 0; q < int(blockDim.x + 63) / 64; ++q) mx = fmax(mx, red[q]);
             ks->est = mx;
-            const int conv = (mx < tol) || ks->breakdown;
+            const int conv = (mx < tol) || brk;
             ks->converged = conv;
-            if (update_state && (conv || m >= m_max)) ks->done = 1;
+            if (update_state) {
+                ks->mdec = m;
+                if (conv || m >= m_max) ks->done = 1;
+            }
         }
     }
 }

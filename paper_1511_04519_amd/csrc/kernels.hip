@@ -237,7 +237,7 @@ __device__ inline void fwd_tree_step(const TItem& t, const FwdPre& p, int lane, 
     // btilde = b minus the children's updates; the off row's updates
     if (lane < t.nc) bt[lane] = p.bv * p.sv - desc_sum(p.d.x, sh);
     const double off = live && row >= t.nc ? desc_sum(p.d.y, sh) : 0.0;
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     double acc = 0.0;
 #pragma unroll
     for (int q = 0; q < TPF; ++q) acc += q < kmax ? p.a[q] * bt[q] : 0.0;
@@ -344,7 +344,7 @@ __device__ inline void bwd_tree_step(const TItem& t, const BwdPre& p, int lane, 
         const int k = t.first + lane + 64 * i;
         if (k < t.nr) g[k] = p.tr[i] < 0 ? -sh[-1 - p.tr[i]] : (k < t.nc ? p.gv[i] : -p.gv[i]);
     }
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     const int cols = t.last - t.first;
     const int shf = cols > 1 ? 32 - __clz(cols - 1) : 0;
     const int lpc = 64 >> shf;
@@ -533,6 +533,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, 
             ks->Ht[nv + j * (MAXM + 1)] = beta;
             ks->m = nv;
             ks->breakdown = brk ? 1 : 0;
+            ks->brk[j] = brk ? 1 : 0;
         }
     }
     __syncthreads();
@@ -553,12 +554,20 @@ __global__ __launch_bounds__(256) void k_checks(KState* ks, double gamma,
                                                 const double* __restrict__ taus,
                                                 const int32_t* __restrict__ sel, int n_sel,
                                                 double tol, double* u_buf, double* est_buf,
-                                                int m_max, int update_state)
+                                                int m_max, int update_state, int m_arg)
 {
     if (update_state && ks->done) return;
     extern __shared__ double sm[];
     const int c = sel ? sel[blockIdx.x] : int(blockIdx.x);
-    check_block(ks, gamma, taus, c, sel, n_sel, tol, u_buf, est_buf, m_max, update_state, sm);
+    const int m = m_arg >= 0 ? m_arg : ks->m;
+    const int brk = m_arg >= 0 ? (m > 0 ? ks->brk[m - 1] : 0) : ks->breakdown;
+    check_block(ks, m, brk, gamma, taus, c, sel, n_sel, tol, u_buf, est_buf, m_max, update_state, sm);
+}
+
+__global__ void k_set_m(KState* ks, int m)
+{
+    ks->m = m;
+    ks->breakdown = m > 0 ? ks->brk[m - 1] : 0;
 }
 
 // ------------------------------------------------------ segment set-up
@@ -593,6 +602,7 @@ __global__ __launch_bounds__(256) void k_normalize_v(int64_t n, double* v, const
         if (blockIdx.x == 0) {
             ks->beta = sb;
             ks->m = 0;
+            ks->mdec = 0;
             ks->breakdown = 0;
             ks->converged = sb == 0.0 ? 1 : 0;
             ks->done = sb == 0.0 ? 1 : 0;
@@ -769,11 +779,13 @@ size_t checks_lds_bytes() { return sizeof(double) * (7 * MAXM * LD + 2 * MAXM); 
 
 void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* sel, int n_sel,
                    double tol, double* u_buf, double* est_buf, int m_max, int update_state,
-                   hipStream_t st)
+                   int m_arg, hipStream_t st)
 {
     k_checks<<<n_sel, 256, checks_lds_bytes(), st>>>(ks, gamma, tau, sel, n_sel, tol, u_buf, est_buf,
-                                                     m_max, update_state);
+                                                     m_max, update_state, m_arg);
 }
+
+void launch_set_m(KState* ks, int m, hipStream_t st) { k_set_m<<<1, 1, 0, st>>>(ks, m); }
 
 // ------------------------------------------------------------- adjoint
 
@@ -1080,6 +1092,7 @@ __global__ void k_restore_start(KState* ks, const double* beta)
         const double b = *beta;
         ks->beta = b;
         ks->m = 0;
+        ks->mdec = 0;
         ks->breakdown = 0;
         ks->converged = b == 0.0 ? 1 : 0;
         ks->done = b == 0.0 ? 1 : 0;

@@ -89,7 +89,7 @@ struct KState {
     int32_t m;             // current dimension
     int32_t breakdown;
     int32_t counter;       // last-block detection of the grid reductions
-    int32_t pad_;
+    int32_t mdec;          // dimension of the last iterating check (0 after set-up)
     double beta;           // ||v||
     double est;            // max estimate over the check set at dimension m
     double nrm2;           // ||w'||^2 after the first Gram-Schmidt pass
@@ -97,6 +97,7 @@ struct KState {
     double h1[MAXM + 1];   // first Gram-Schmidt pass coefficients
     double h2[MAXM + 1];   // second pass
     double Ht[(MAXM + 1) * MAXM];   // column-major (MAXM+1) x MAXM
+    int32_t brk[MAXM];     // brk[j]: the Gram-Schmidt step of iteration j broke down
 };
 
 // ---- sweeps: w = (L L^T)^-1 (scale .* b) in the permuted ordering --------
@@ -127,9 +128,14 @@ void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w
 // One workgroup per checked offset: sel[0 .. n_sel) (sel null: offsets
 // 0 .. n_sel - 1). u_buf[c*MAXM + i] = (e^{tau_c H_m} e1)_i; when iterating
 // (update_state) it also holds the previous dimension's vector.
+// m_arg >= 0: check dimension m_arg with iteration m_arg - 1's breakdown
+// flag (for a check that runs beside later iterations); -1: the state's m.
 void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* sel, int n_sel,
                    double tol, double* u_buf, double* est_buf, int m_max, int update_state,
-                   hipStream_t st);
+                   int m_arg, hipStream_t st);
+// The process's dimension after a check decided at m (iterations launched
+// ahead of that decision may have advanced it).
+void launch_set_m(KState* ks, int m, hipStream_t st);
 // Lets a process whose check subset passed but whose full check set did not
 // continue iterating.
 void launch_resume(KState* ks, hipStream_t st);

@@ -88,6 +88,45 @@ struct PinnedMem {
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned staging slots for host-to-device copies on one stream: a slot is
+// reused only after the copy that last read it has completed (its event),
+// so filling the next one never drains the stream.
+struct StageRing {
+    static constexpr int SLOTS = 4;
+    std::unique_ptr<PinnedMem> mem;
+    size_t slot_bytes = 0;
+    hipEvent_t ev[SLOTS] = {};
+    bool used[SLOTS] = {};
+    int next = 0;
+    explicit StageRing(size_t bytes) : slot_bytes(bytes) {
+        mem.reset(new PinnedMem(SLOTS * slot_bytes));
+        for (auto& e : ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    }
+    StageRing(const StageRing&) = delete;
+    StageRing& operator=(const StageRing&) = delete;
+    ~StageRing() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    // Copies `bytes` from host src to device dst on st through a free slot.
+    void copy(void* dst, const void* src, size_t bytes, hipStream_t st) {
+        if (bytes > slot_bytes) {
+            HIPCHK(hipStreamSynchronize(st));
+            slot_bytes = bytes * 2;
+            mem.reset(new PinnedMem(SLOTS * slot_bytes));
+            for (bool& u : used) u = false;
+        }
+        const int s = next;
+        next = (next + 1) % SLOTS;
+        if (used[s]) HIPCHK(hipEventSynchronize(ev[s]));
+        char* slot = mem->as<char>() + size_t(s) * slot_bytes;
+        std::memcpy(slot, src, bytes);
+        HIPCHK(hipMemcpyAsync(dst, slot, bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(hipEventRecord(ev[s], st));
+        used[s] = true;
+    }
+};
+
 double now_s()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
@@ -513,7 +552,19 @@ struct Work {
     int64_t n = 0;
     DevMem V, w, tmp, upd, partial, ks, u, est, taus, sel;
     int64_t max_checks = 0;
+    hipStream_t cs = nullptr;          // checks, beside the next iteration
+    hipEvent_t ev_it = nullptr, ev_c = nullptr;
+    Work(const Work&) = delete;
+    Work& operator=(const Work&) = delete;
+    ~Work() {
+        if (ev_it) (void)hipEventDestroy(ev_it);
+        if (ev_c) (void)hipEventDestroy(ev_c);
+        if (cs) (void)hipStreamDestroy(cs);
+    }
     Work(const matex_factor_s& F, int64_t max_chk) {
+        HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        HIPCHK(hipEventCreateWithFlags(&ev_it, hipEventDisableTiming));
+        HIPCHK(hipEventCreateWithFlags(&ev_c, hipEventDisableTiming));
         n = F.sym.n;
         V = DevMem(sizeof(double) * n * (MAXM + 1));
         w = DevMem(sizeof(double) * n);
@@ -533,7 +584,7 @@ struct Work {
 };
 
 struct KsHost {
-    int32_t done, converged, m, breakdown;
+    int32_t done, converged, m, breakdown, counter, mdec;   // KState's leading fields
 };
 
 KsHost read_state(const Work& wk, KsHost* pinned, hipStream_t st)
@@ -551,10 +602,8 @@ double read_est(const Work& wk, double* pinned, hipStream_t st)
 }
 
 // One Krylov iteration j (0-based): w = M^-1 C v_j, two Gram-Schmidt passes,
-// v_{j+1}, column j of Ht, and the estimate over the checked offsets (sel,
-// n_sel as for launch_checks).
-void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, const int32_t* sel,
-                      int n_sel, double tol, int m_max, hipStream_t st)
+// v_{j+1} and column j of Ht.
+void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, hipStream_t st)
 {
     const int64_t n = wk.n;
     double* V = wk.V.as<double>();
@@ -563,44 +612,69 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, const
     launch_gs_dots(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_update(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
-    launch_checks(wk.kst(), F.gammas[shift], wk.taus.as<double>(), sel, n_sel, tol, wk.u.as<double>(),
-                  wk.est.as<double>(), m_max, 1, st);
 }
 
-// Runs Alg. 1 from the (already normalised) V_0 until the device says done.
-// With more than two check offsets the iterations test only the first and
-// the last; once those pass, one evaluation of every offset confirms the
-// decision, and if it fails the process continues with every offset
-// tested. This stops at the same dimension as testing every offset each
-// time: a failing subset implies a failing full set, and the evaluation
-// leaves every offset's vector of the current dimension for the next
-// iteration's difference term. Returns the final host view of the state.
+// Runs Alg. 1 from the (already normalised) V_0 until a check stops it.
+// The estimate of dimension j + 1 runs on the work's check stream while
+// the main stream already computes iteration j + 1: the decision lands a
+// check later on the host, the next iteration never waits for it, and an
+// iteration computed past the decision is discarded (the dimension is set
+// back to the decided one). With more than two check offsets the
+// iterations test only the first and the last; once those pass, one
+// evaluation of every offset confirms the decision, and if it fails the
+// process continues with every offset tested. This stops at the same
+// dimension as testing every offset each time: a failing subset implies a
+// failing full set, and the evaluation leaves every offset's vector of the
+// current dimension for the next iteration's difference term. Returns the
+// final host view of the state (m the decided dimension).
 KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, double tol, int m_max,
-                   int m_guess, KsHost* pinned, hipStream_t st)
+                   KsHost* pinned, hipStream_t st)
 {
     bool full = n_tau <= 2;
     if (!full) launch_set_ends(wk.sel.as<int32_t>(), n_tau - 1, st);
-    KsHost h = read_state(wk, pinned, st);
-    int j = 0;
-    int chunk = std::max(1, std::min(m_guess, m_max));
+    // a zero start vector has the state done already: the first check then
+    // returns at once and its read shows it
+    KsHost h{};
+    const double gamma = F.gammas[shift];
+    auto launch_iter = [&](int i) {
+        krylov_iteration(F, shift, wk, i, st);
+        HIPCHK(hipEventRecord(wk.ev_it, st));
+    };
+    auto launch_check = [&](int i) {   // dimension i + 1, after iteration i
+        HIPCHK(hipStreamWaitEvent(wk.cs, wk.ev_it, 0));
+        launch_checks(wk.kst(), gamma, wk.taus.as<double>(), full ? nullptr : wk.sel.as<int32_t>(),
+                      full ? n_tau : 2, tol, wk.u.as<double>(), wk.est.as<double>(), m_max, 1, i + 1, wk.cs);
+        HIPCHK(hipMemcpyAsync(pinned, wk.ks.p, sizeof(KsHost), hipMemcpyDeviceToHost, wk.cs));
+    };
+    int j = 0;   // next iteration
     while (true) {
-        while (!h.done && j < m_max) {
-            int stop = std::min(m_max, j + chunk);
-            for (; j < stop; ++j)
-                krylov_iteration(F, shift, wk, j, full ? nullptr : wk.sel.as<int32_t>(), full ? n_tau : 2, tol,
-                                 m_max, st);
-            h = read_state(wk, pinned, st);
-            chunk = 1;
+        if (h.done || j >= m_max) break;
+        launch_iter(j);
+        launch_check(j);
+        ++j;
+        int mdec = 0;
+        while (true) {
+            if (j < m_max) launch_iter(j);   // ahead of the decision on dimension j
+            HIPCHK(hipStreamSynchronize(wk.cs));
+            h = *pinned;
+            if (h.done || j >= m_max) { mdec = h.mdec; break; }
+            launch_check(j);
+            ++j;
         }
-        if (full || !h.converged || h.m == 0) break;
-        launch_checks(wk.kst(), F.gammas[shift], wk.taus.as<double>(), nullptr, n_tau, tol, wk.u.as<double>(),
-                      wk.est.as<double>(), m_max, 0, st);
+        HIPCHK(hipEventRecord(wk.ev_c, wk.cs));
+        HIPCHK(hipStreamWaitEvent(st, wk.ev_c, 0));
+        launch_set_m(wk.kst(), mdec, st);
+        h.m = mdec;
+        if (full || !h.converged || mdec == 0) break;
+        launch_checks(wk.kst(), gamma, wk.taus.as<double>(), nullptr, n_tau, tol, wk.u.as<double>(),
+                      wk.est.as<double>(), m_max, 0, -1, st);
         h = read_state(wk, pinned, st);
         if (h.converged) break;
         full = true;
         if (h.m >= m_max) break;
         launch_resume(wk.kst(), st);
         h.done = 0;
+        j = mdec;   // the iteration launched past the decision may have been cut short
     }
     return h;
 }
@@ -933,7 +1007,7 @@ matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, co
             launch_setup_v(n, acc.as<double>(), zero.as<double>(), zero.as<double>(), V,
                            wk.partial.as<double>(), wk.kst(), st);
             launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-            KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, 6, pin.as<KsHost>(), st);
+            KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, pin.as<KsHost>(), st);
             if (!h.converged) all_conv = false;
             if (m_used) m_used[r] = h.m;
             if (est) est[r] = read_est(wk, pin.as<double>() + 8, st);
@@ -1511,9 +1585,9 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
     PinnedMem pin(4096);
     KsHost* hks = pin.as<KsHost>();
     double* hest = pin.as<double>() + 16;
-    int64_t stage_cap = 1 << 16;
-    std::unique_ptr<PinnedMem> stage(new PinnedMem(stage_cap));
-    DevMem d_ev(stage_cap);
+    StageRing ring(size_t(1) << 16);
+    int64_t ev_cap = 1 << 16;
+    DevMem d_ev(ev_cap);
     DevMem y(sizeof(double) * n), y0(sizeof(double) * n), z1(sizeof(double) * n),
         z2(sizeof(double) * n), sl(sizeof(double) * n), ysum(sizeof(double) * n);
     DevMem probe_perm(sizeof(int32_t) * std::max(1, n_probe));
@@ -1528,7 +1602,6 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
     const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
     const double* cperm = f->d_cperm.as<double>();
     double* V = wk.V.as<double>();
-    int m_guess = 6;
 
     for (auto& grp : groups) {
         S.subtasks++;
@@ -1542,19 +1615,16 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
                 const Segment& sg = spots[k_spot];
                 const int32_t cnt = int32_t(sg.node.size());
                 if (cnt > 0) {
-                    size_t need = cnt * (sizeof(int32_t) + sizeof(double)) + 16;
-                    if (int64_t(need) > stage_cap) {
+                    const size_t need = cnt * (sizeof(int32_t) + sizeof(double)) + 16;
+                    if (int64_t(need) > ev_cap) {
                         HIPCHK(hipStreamSynchronize(st));
-                        stage_cap = int64_t(need) * 2;
-                        stage.reset(new PinnedMem(stage_cap));
-                        d_ev = DevMem(stage_cap);
+                        ev_cap = int64_t(need) * 2;
+                        d_ev = DevMem(ev_cap);
                     }
-                    HIPCHK(hipStreamSynchronize(st));   // staging buffer reuse
-                    double* hv = stage->as<double>();
-                    int32_t* hi = reinterpret_cast<int32_t*>(hv + cnt);
-                    std::memcpy(hv, sg.dslope.data(), sizeof(double) * cnt);
-                    std::memcpy(hi, sg.node.data(), sizeof(int32_t) * cnt);
-                    HIPCHK(hipMemcpyAsync(d_ev.p, stage->p, need, hipMemcpyHostToDevice, st));
+                    std::vector<char> buf(need);
+                    std::memcpy(buf.data(), sg.dslope.data(), sizeof(double) * cnt);
+                    std::memcpy(buf.data() + sizeof(double) * cnt, sg.node.data(), sizeof(int32_t) * cnt);
+                    ring.copy(d_ev.p, buf.data(), need, st);
                     double* dv = d_ev.as<double>();
                     launch_scatter_add(cnt, reinterpret_cast<int32_t*>(dv + cnt), dv, sl.as<double>(), st);
                     dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
@@ -1573,19 +1643,15 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
             while (true) {
                 std::vector<double> taus(offs.size());
                 for (size_t q = 0; q < offs.size(); ++q) taus[q] = double(offs[q]) * FS;
-                HIPCHK(hipStreamSynchronize(st));
-                std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
-                HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
-                                      hipMemcpyHostToDevice, st));
+                ring.copy(wk.taus.p, taus.data(), sizeof(double) * taus.size(), st);
                 launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
                                wk.partial.as<double>(), wk.kst(), st);
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-                h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, m_guess, hks, st);
+                h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, hks, st);
                 S.bases++;
                 S.solve_pairs_m += h.m;
                 S.krylov_dims += h.m;
                 S.m_peak = std::max(S.m_peak, h.m);
-                if (h.m > 0) m_guess = h.m;
                 if (trace && !h.converged)
                     fprintf(stderr, "[matex] not converged t_a=%lld shift=%d m=%d est=%.3e checks=%zu first=%lld last=%lld\n",
                             (long long)t_a, ksh, h.m, read_est(wk, hest, st), offs.size(),
@@ -1606,12 +1672,9 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
                     std::vector<int64_t> o2 = halved_offsets(offs, hstep);
                     std::vector<double> taus(o2.size());
                     for (size_t q = 0; q < o2.size(); ++q) taus[q] = double(o2[q]) * FS;
-                    HIPCHK(hipStreamSynchronize(st));
-                    std::memcpy(stage->p, taus.data(), sizeof(double) * taus.size());
-                    HIPCHK(hipMemcpyAsync(wk.taus.p, stage->p, sizeof(double) * taus.size(),
-                                          hipMemcpyHostToDevice, st));
+                    ring.copy(wk.taus.p, taus.data(), sizeof(double) * taus.size(), st);
                     launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), nullptr, int(taus.size()),
-                                  o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
+                                  o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, -1, st);
                     KsHost hh = read_state(wk, hks, st);
                     if (trace)
                         fprintf(stderr, "[matex] halving t_a=%lld step=%lld est=%.3e\n", (long long)t_a,
@@ -1893,7 +1956,6 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
         };
         const char* trace_env = std::getenv("MATEX_TRACE");
         const bool trace = trace_env && trace_env[0] == '1';
-        int m_guess = 6;
         int64_t t_hi = t_last;
         jump(t_hi);
         // a jump puts weight on modes much faster than the steps; the step
@@ -2051,8 +2113,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                 launch_setup_v(n, lam.as<double>(), zero.as<double>(), zero.as<double>(), V,
                                wk.partial.as<double>(), wk.kst(), st);
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-                h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, m_guess, hks, st);
-                if (h.m > 0) m_guess = h.m;
+                h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, hks, st);
                 if (h.converged || ksh + 1 == n_shifts) break;
                 ksh++;
             }
@@ -2066,7 +2127,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                     return fail(MATEX_E_NOCONV, "adjoint: no convergence at t = " + std::to_string(t_hi) + " fs");
                 set_tau(dt);
                 launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), nullptr, 1, o->tol,
-                              wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, st);
+                              wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, -1, st);
                 h = read_state(wk, hks, st);
             }
             if (d_grad_amp) {
