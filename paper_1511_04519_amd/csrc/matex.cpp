@@ -628,7 +628,7 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, hipSt
 // current dimension for the next iteration's difference term. Returns the
 // final host view of the state (m the decided dimension).
 KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, double tol, int m_max,
-                   KsHost* pinned, hipStream_t st)
+                   int m_pred, KsHost* pinned, hipStream_t st)
 {
     bool full = n_tau <= 2;
     if (!full) launch_set_ends(wk.sel.as<int32_t>(), n_tau - 1, st);
@@ -653,11 +653,20 @@ KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, doub
         launch_check(j);
         ++j;
         int mdec = 0;
+        bool past = m_pred <= 0;
         while (true) {
-            if (j < m_max) launch_iter(j);   // ahead of the decision on dimension j
+            // iteration j goes ahead of the decision on dimension j unless
+            // that decision is predicted to stop (an iteration launched past
+            // the stop still costs its launches)
+            const bool ahead = j < m_max && (past || j < m_pred);
+            if (ahead) launch_iter(j);
             HIPCHK(hipStreamSynchronize(wk.cs));
             h = *pinned;
             if (h.done || j >= m_max) { mdec = h.mdec; break; }
+            if (!ahead) {
+                launch_iter(j);
+                past = true;
+            }
             launch_check(j);
             ++j;
         }
@@ -1007,7 +1016,7 @@ matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, co
             launch_setup_v(n, acc.as<double>(), zero.as<double>(), zero.as<double>(), V,
                            wk.partial.as<double>(), wk.kst(), st);
             launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-            KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, pin.as<KsHost>(), st);
+            KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, 0, pin.as<KsHost>(), st);
             if (!h.converged) all_conv = false;
             if (m_used) m_used[r] = h.m;
             if (est) est[r] = read_est(wk, pin.as<double>() + 8, st);
@@ -1602,6 +1611,7 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
     const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
     const double* cperm = f->d_cperm.as<double>();
     double* V = wk.V.as<double>();
+    int m_last = 0;   // the previous basis's dimension predicts the next one's
 
     for (auto& grp : groups) {
         S.subtasks++;
@@ -1647,7 +1657,8 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
                 launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
                                wk.partial.as<double>(), wk.kst(), st);
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-                h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, hks, st);
+                h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, m_last, hks, st);
+                if (h.m > 0) m_last = h.m;
                 S.bases++;
                 S.solve_pairs_m += h.m;
                 S.krylov_dims += h.m;
@@ -1956,6 +1967,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
         };
         const char* trace_env = std::getenv("MATEX_TRACE");
         const bool trace = trace_env && trace_env[0] == '1';
+        int m_last = 0;
         int64_t t_hi = t_last;
         jump(t_hi);
         // a jump puts weight on modes much faster than the steps; the step
@@ -2113,7 +2125,8 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                 launch_setup_v(n, lam.as<double>(), zero.as<double>(), zero.as<double>(), V,
                                wk.partial.as<double>(), wk.kst(), st);
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-                h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, hks, st);
+                h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, m_last, hks, st);
+                if (h.m > 0) m_last = h.m;
                 if (h.converged || ksh + 1 == n_shifts) break;
                 ksh++;
             }
