@@ -47,6 +47,7 @@ template <int ROWS>
 __global__ __launch_bounds__(256) void k_forward(const PTask* __restrict__ tasks,
                                                  const int32_t* __restrict__ cptr,
                                                  const int32_t* __restrict__ cidx, int32_t lds_nc,
+                                                 const int2* __restrict__ fdesc, int32_t slot,
                                                  const double* __restrict__ W,
                                                  const double* __restrict__ b,
                                                  const double* __restrict__ scale,
@@ -71,21 +72,41 @@ __global__ __launch_bounds__(256) void k_forward(const PTask* __restrict__ tasks
         const int k = ks + q * KS;
         a[q] = k < kmax ? wr[k * ld] : 0.0;
     }
-    for (int k = threadIdx.x; k < t.nc; k += 256) {
-        double v = b[t.c0 + k];
-        if (scale) v *= scale[t.c0 + k];
-        const int j1 = cptr[t.pos + k + 1];
-        for (int j = cptr[t.pos + k]; j < j1; ++j) v -= upd[cidx[j]];
-        bt[k] = v;
-    }
-    if (threadIdx.x >= 256 - ROWS) {
-        const int i = threadIdx.x - (256 - ROWS), r = t.first + i;
-        double v = 0.0;
-        if (r >= t.nc && r < t.nr) {
-            const int j1 = cptr[t.pos + r + 1];
-            for (int j = cptr[t.pos + r]; j < j1; ++j) v += upd[cidx[j]];
+    if (fdesc) {
+        // the update slots are known from the block index alone
+        const int2* dsc = fdesc + int64_t(blockIdx.x) * slot;
+        for (int k = threadIdx.x; k < lds_nc; k += 256) {
+            const int2 d = dsc[k];
+            const double u0 = d.x >= 0 ? upd[d.x] : 0.0, u1 = d.y >= 0 ? upd[d.y] : 0.0;
+            if (k < t.nc) {
+                double v = b[t.c0 + k];
+                if (scale) v *= scale[t.c0 + k];
+                bt[k] = (v - u0) - u1;
+            }
         }
-        off[i] = v;
+        if (threadIdx.x >= 256 - ROWS) {
+            const int i = threadIdx.x - (256 - ROWS);
+            const int2 d = dsc[lds_nc + i];
+            const double u0 = d.x >= 0 ? upd[d.x] : 0.0, u1 = d.y >= 0 ? upd[d.y] : 0.0;
+            off[i] = (0.0 + u0) + u1;
+        }
+    } else {
+        for (int k = threadIdx.x; k < t.nc; k += 256) {
+            double v = b[t.c0 + k];
+            if (scale) v *= scale[t.c0 + k];
+            const int j1 = cptr[t.pos + k + 1];
+            for (int j = cptr[t.pos + k]; j < j1; ++j) v -= upd[cidx[j]];
+            bt[k] = v;
+        }
+        if (threadIdx.x >= 256 - ROWS) {
+            const int i = threadIdx.x - (256 - ROWS), r = t.first + i;
+            double v = 0.0;
+            if (r >= t.nc && r < t.nr) {
+                const int j1 = cptr[t.pos + r + 1];
+                for (int j = cptr[t.pos + r]; j < j1; ++j) v += upd[cidx[j]];
+            }
+            off[i] = v;
+        }
     }
     __syncthreads();
     double acc = 0.0;
@@ -124,6 +145,7 @@ __global__ __launch_bounds__(256) void k_forward(const PTask* __restrict__ tasks
 template <int LPC>
 __global__ __launch_bounds__(256) void k_backward(const PTask* __restrict__ tasks,
                                                   const int32_t* __restrict__ rows,
+                                                  const int32_t* __restrict__ gsrc, int32_t slot,
                                                   const double* __restrict__ W,
                                                   const double* __restrict__ y, double* x,
                                                   const int32_t* done)
@@ -141,8 +163,20 @@ __global__ __launch_bounds__(256) void k_backward(const PTask* __restrict__ task
         const int k = col + q + p * LPC;
         a[p] = k < kend ? wc[k] : 0.0;
     }
-    for (int k = t.first + threadIdx.x; k < t.nr; k += 256)
-        g[k] = k < t.nc ? y[t.c0 + k] : -x[rows[t.aux + k - t.nc]];
+    if (gsrc) {
+        // the sources of g are known from the block index alone
+        const int32_t* gs = gsrc + int64_t(blockIdx.x) * slot;
+        for (int i = threadIdx.x; i < slot; i += 256) {
+            const int r = gs[i];
+            if (r != INT32_MIN) {
+                const double v = r >= 0 ? -x[r] : y[-1 - r];
+                g[t.first + i] = v;
+            }
+        }
+    } else {
+        for (int k = t.first + threadIdx.x; k < t.nr; k += 256)
+            g[k] = k < t.nc ? y[t.c0 + k] : -x[rows[t.aux + k - t.nc]];
+    }
     __syncthreads();
     double acc = 0.0;
     for (int k = col + q; k < kend; k += PF * LPC) {
@@ -709,15 +743,15 @@ void launch_forward(const LevelTasks& lv, const int32_t* cptr, const int32_t* ci
     const size_t lds = sizeof(double) * (size_t(lv.lds_doubles) + 256 + size_t(lv.kind));
     switch (lv.kind) {
     case 4:
-        k_forward<4><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, W, b, scale,
+        k_forward<4><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, lv.fdesc, lv.slot, W, b, scale,
                                                  y, upd, done);
         break;
     case 16:
-        k_forward<16><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, W, b, scale,
+        k_forward<16><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, lv.fdesc, lv.slot, W, b, scale,
                                                   y, upd, done);
         break;
     default:
-        k_forward<64><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, W, b, scale,
+        k_forward<64><<<lv.count, 256, lds, st>>>(lv.tasks, cptr, cidx, lv.lds_doubles, lv.fdesc, lv.slot, W, b, scale,
                                                   y, upd, done);
         break;
     }
@@ -729,10 +763,10 @@ void launch_backward(const LevelTasks& lv, const int32_t* rows, const double* W,
     const size_t lds = sizeof(double) * size_t(lv.lds_doubles);
     switch (lv.kind) {
     case 16:
-        k_backward<16><<<lv.count, 256, lds, st>>>(lv.tasks, rows, W, y, x, done);
+        k_backward<16><<<lv.count, 256, lds, st>>>(lv.tasks, rows, lv.gsrc, lv.slot, W, y, x, done);
         break;
     default:
-        k_backward<64><<<lv.count, 256, lds, st>>>(lv.tasks, rows, W, y, x, done);
+        k_backward<64><<<lv.count, 256, lds, st>>>(lv.tasks, rows, lv.gsrc, lv.slot, W, y, x, done);
         break;
     }
 }

@@ -43,7 +43,16 @@ struct LevelTasks {
     int32_t count;
     int32_t lds_doubles;   // forward: max nc of the level; backward: max nr
     int32_t kind;
-    int32_t pad_;
+    int32_t slot;          // entries per task of fdesc / gsrc
+    // Per-task tables indexed by block alone, so their loads need no task
+    // record (null: the contributor lists / row lists are used instead):
+    // forward, the update slots (up to two, -1 none) adding into btilde at
+    // column k (entry k < lds_doubles) and into the task's panel row
+    // first + i (entry lds_doubles + i);
+    const int2* fdesc;
+    // backward, the source of g at panel row first + i: x index r >= 0
+    // (an off row, negated), -1 - (y index) for an own column, INT32_MIN none.
+    const int32_t* gsrc;
 };
 
 // Subtree sweeps of the bottom levels: one block of TW wavefronts per

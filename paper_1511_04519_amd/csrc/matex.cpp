@@ -146,6 +146,7 @@ struct matex_factor_s {
     DevMem d_perm, d_iperm, d_cperm;
     DevMem d_grp, d_gci, d_gv;        // G in the permuted order (CSR), for the adjoint
     std::vector<DevMem> d_W;          // [n_shifts] M factors, then G
+    DevMem d_fdesc, d_gsrc;
     DevMem d_fwd_tasks, d_bwd_tasks, d_tree_f, d_tree_b, d_tree_fblk, d_tree_bblk, d_tree_fdesc,
         d_tree_trow;
     std::vector<LevelTasks> fwd, bwd;   // levels tree.n_levels .. n_levels - 1
@@ -160,7 +161,7 @@ struct matex_factor_s {
     int64_t held_bytes() const {
         int64_t b = 0;
         for (const DevMem* m : {&d_c0, &d_nc, &d_nr, &d_roff, &d_w, &d_u, &d_rows, &d_child_ptr, &d_child_idx,
-                                &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_grp, &d_gci, &d_gv, &d_fwd_tasks, &d_bwd_tasks, &d_tree_f, &d_tree_b,
+                                &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_grp, &d_gci, &d_gv, &d_fwd_tasks, &d_bwd_tasks, &d_fdesc, &d_gsrc, &d_tree_f, &d_tree_b,
                                 &d_tree_fblk, &d_tree_bblk, &d_tree_fdesc, &d_tree_trow, &d_b_pos,
                                 &d_b_cptr, &d_b_cidx, &d_b_ft, &d_b_fr, &d_b_bt, &d_b_br})
             b += int64_t(m->bytes);
@@ -441,9 +442,62 @@ void build_tasks(matex_factor_s& F, int32_t subtree_limit)
     for (int lv = 0; lv < S; ++lv) fo[lv + 1] = bo[lv + 1] = 0;
     F.d_fwd_tasks = upload(ft.empty() ? std::vector<PTask>(1, PTask{}) : ft);
     F.d_bwd_tasks = upload(bt.empty() ? std::vector<PTask>(1, PTask{}) : bt);
+    // block-indexed tables: forward contributor slots (levels whose panel
+    // positions have at most two contributors), backward sources of g
+    std::vector<int2> fdesc;
+    std::vector<int32_t> gsrc;
+    std::vector<int64_t> fdo(L, -1), gso(L, 0);
+    std::vector<int32_t> fslot(L, 0), gslot(L, 0);
     for (int lv = S; lv < L; ++lv) {
-        F.fwd.push_back({F.d_fwd_tasks.as<PTask>() + fo[lv], int32_t(fo[lv + 1] - fo[lv]), flds[lv], fkind[lv], 0});
-        F.bwd.push_back({F.d_bwd_tasks.as<PTask>() + bo[lv], int32_t(bo[lv + 1] - bo[lv]), blds[lv], bkind[lv], 0});
+        bool two = true;
+        for (int32_t k : s.level_sn[lv])
+            for (int32_t p = 0; p < s.sn[k].nr && two; ++p)
+                two = cptr[pos_base[k] + p + 1] - cptr[pos_base[k] + p] <= 2;
+        if (two) {
+            const int32_t nc_max = flds[lv], sl = nc_max + fkind[lv];
+            fslot[lv] = sl;
+            fdo[lv] = int64_t(fdesc.size());
+            auto entry = [&](const PTask& t, int32_t p) {
+                int2 d = make_int2(-1, -1);
+                if (p < 0 || p >= t.nr) return d;
+                const int32_t j0 = cptr[t.pos + p], j1 = cptr[t.pos + p + 1];
+                if (j1 > j0) d.x = cidx[j0];
+                if (j1 > j0 + 1) d.y = cidx[j0 + 1];
+                return d;
+            };
+            for (int64_t i = fo[lv]; i < fo[lv + 1]; ++i) {
+                const PTask& t = ft[i];
+                for (int32_t k = 0; k < nc_max; ++k) fdesc.push_back(k < t.nc ? entry(t, k) : make_int2(-1, -1));
+                for (int32_t r = 0; r < fkind[lv]; ++r) {
+                    const int32_t row = t.first + r;
+                    fdesc.push_back(row >= t.nc ? entry(t, row) : make_int2(-1, -1));
+                }
+            }
+        }
+        int32_t sl = 0;
+        for (int64_t i = bo[lv]; i < bo[lv + 1]; ++i) sl = std::max(sl, bt[i].nr - bt[i].first);
+        gslot[lv] = sl;
+        gso[lv] = int64_t(gsrc.size());
+        for (int64_t i = bo[lv]; i < bo[lv + 1]; ++i) {
+            const PTask& t = bt[i];
+            for (int32_t q = 0; q < sl; ++q) {
+                const int32_t k = t.first + q;
+                int32_t v = INT32_MIN;
+                if (k < t.nc) v = -1 - (t.c0 + k);
+                else if (k < t.nr) v = s.rows[t.aux + k - t.nc];
+                gsrc.push_back(v);
+            }
+        }
+    }
+    F.d_fdesc = upload(fdesc.empty() ? std::vector<int2>(1, make_int2(-1, -1)) : fdesc);
+    F.d_gsrc = upload(gsrc.empty() ? std::vector<int32_t>(1, INT32_MIN) : gsrc);
+    for (int lv = S; lv < L; ++lv) {
+        LevelTasks f{F.d_fwd_tasks.as<PTask>() + fo[lv], int32_t(fo[lv + 1] - fo[lv]), flds[lv], fkind[lv],
+                     fslot[lv], fdo[lv] >= 0 ? F.d_fdesc.as<int2>() + fdo[lv] : nullptr, nullptr};
+        LevelTasks b{F.d_bwd_tasks.as<PTask>() + bo[lv], int32_t(bo[lv + 1] - bo[lv]), blds[lv], bkind[lv],
+                     gslot[lv], nullptr, F.d_gsrc.as<int32_t>() + gso[lv]};
+        F.fwd.push_back(f);
+        F.bwd.push_back(b);
     }
     // batched sweeps: per level, forward blocks of 64 panel rows and
     // backward blocks of 64 panel columns, each split into tasks of at most
