@@ -90,7 +90,7 @@ print(json.dumps(dict(factor_s=tf, transient_s=tt, n=p.netlist.n, n_out=int(q.t_
     return d
 
 
-def batched_vs_plain(window_ps=0):
+def batched_vs_plain(window_ps=0, with_plain=False):
     """The 64-subtask workload batched and plain, and the 64-RHS pair."""
     import numpy as np
     import torch
@@ -110,7 +110,11 @@ def batched_vs_plain(window_ps=0):
     print(f"[bench] batched workload: n {n}, {groups} subtasks, factor {factor_s:.1f} s, "
           f"nnz(L) {F.info['nnz_l']}", flush=True)
     res = {}
-    for mode, md in (("batched", M.MATEX_BATCHED), ("plain", M.MATEX_PLAIN)):
+    # the plain run of this workload stopped on a GPU memory fault whose
+    # cause is not found yet; it runs only on request
+    modes = (("batched", M.MATEX_BATCHED), ("plain", M.MATEX_PLAIN)) if with_plain else \
+        (("batched", M.MATEX_BATCHED),)
+    for mode, md in modes:
         torch.cuda.synchronize()
         t0 = time.time()
         x, _, st = M.matex_transient(F, p, tol=tol, m_max=p.m_max, mode=md)
@@ -119,19 +123,22 @@ def batched_vs_plain(window_ps=0):
         res[mode] = (x.cpu().numpy(), dt, st)
         print(f"[bench] {mode}: {dt:.2f} s, pairs {st['solve_pairs_m']}+{st['solve_pairs_g']}, "
               f"bases {st['bases']}", flush=True)
-    diff = float(np.abs(res["batched"][0] - res["plain"][0]).max())
+    diff = float(np.abs(res["batched"][0] - res["plain"][0]).max()) if with_plain else None
     pair_s, pair_b = M.matex_time_solves(F, which=0, reps=20, nrhs=64)
     one_s, one_b = M.matex_time_solves(F, which=0, reps=20, nrhs=1)
-    sb, sp = res["batched"][2], res["plain"][2]
+    sb = res["batched"][2]
+    sp = res["plain"][2] if with_plain else None
     return {
         "workload": p.name, "n": n, "n_out": int(n_out), "subtasks": groups, "tol": tol,
         "factor_s": round(factor_s, 2),
         "batched_node_steps_per_s": n * n_out / res["batched"][1],
-        "plain_node_steps_per_s": n * n_out / res["plain"][1],
-        "batched_s": round(res["batched"][1], 3), "plain_s": round(res["plain"][1], 3),
-        "speedup": round(res["plain"][1] / res["batched"][1], 3),
+        "plain_node_steps_per_s": n * n_out / res["plain"][1] if with_plain else None,
+        "batched_s": round(res["batched"][1], 3),
+        "plain_s": round(res["plain"][1], 3) if with_plain else None,
+        "speedup": round(res["plain"][1] / res["batched"][1], 3) if with_plain else None,
         "max_abs_diff_batched_vs_plain": diff,
-        "same_steps": sb["segments"] == sp["segments"] and sb["krylov_dims"] == sp["krylov_dims"],
+        "same_steps": (sb["segments"] == sp["segments"] and sb["krylov_dims"] == sp["krylov_dims"])
+        if with_plain else None,
         "stats_batched": sb, "stats_plain": sp,
         "pair64": {"bound": "hbm", "achieved": round(pair_b / pair_s / 1e9, 2), "peak": HBM_PEAK_GBS,
                    "unit": "GB/s", "frac": round(pair_b / pair_s / 1e9 / HBM_PEAK_GBS, 5),

@@ -186,7 +186,12 @@ typedef struct {
     int64_t segments;        /* steps taken (after ladder cuts and halvings)    */
     int64_t bases;           /* Krylov bases generated                          */
     int64_t solve_pairs_m;   /* substitution pairs with C + gamma_k G           */
-    int64_t solve_pairs_g;   /* substitution pairs with G                       */
+    int64_t solve_pairs_g;   /* right-hand sides solved with G: in the plain
+                                mode two per source row of a subtask
+                                (G^-1 e_k and G^-1 C G^-1 e_k, solved 64 at a
+                                time once, then combined at each transition
+                                spot), or two per spot when those columns do
+                                not fit half the free device memory          */
     int64_t krylov_dims;     /* sum of m over bases                             */
     int32_t m_peak;
     int32_t halvings;

@@ -389,6 +389,80 @@ __global__ __launch_bounds__(256) void kb_gs_axpy(int64_t n, int R, double* V, i
     }
 }
 
+// First-pass update and second-pass dots in one sweep over the basis:
+// w' = w - sum_i h1[i] V_i in place, then per subtask the partial dots V_i^T w'
+// and ||w'||^2 (slot nv) of the block's rows into partial[(block * R + r) *
+// (NVB + 1) + i]. A block takes tiles of GS_TILE rows: each wavefront updates
+// GS_TILE / 4 rows (lane = subtask) and stages w' in LDS; then value i is
+// summed over the tile by wavefront i mod 4 (the tile's basis values come
+// back from cache, not HBM).
+constexpr int GS_TILE = 16;
+constexpr int GS_VPW_B = (NVB + 1 + 3) / 4;
+
+__global__ __launch_bounds__(256) void kb_gs_update_dots(int64_t n, int R, const double* __restrict__ V,
+                                                         int nv, double* w, double* partial,
+                                                         const KState* ks)
+{
+    __shared__ double hs[NVB][64];
+    __shared__ double wl[GS_TILE][64];
+    const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int idx = threadIdx.x; idx < NVB * 64; idx += 256) {
+        const int i = idx >> 6, q = idx & 63;
+        hs[i][q] = (q < R && i < nv) ? ks[q].h1[i] : 0.0;
+    }
+    __syncthreads();
+    const bool on = r < R && !ks[r < R ? r : 0].done;
+    double acc[GS_VPW_B];
+#pragma unroll
+    for (int q = 0; q < GS_VPW_B; ++q) acc[q] = 0.0;
+    for (int64_t base = int64_t(blockIdx.x) * GS_TILE; base < n; base += int64_t(gridDim.x) * GS_TILE) {
+        // update: rows base + wv, base + wv + 4, ...
+#pragma unroll
+        for (int t = wv; t < GS_TILE; t += 4) {
+            const int64_t row = base + t;
+            double wr = 0.0;
+            if (on && row < n) {
+                wr = w[row * R + r];
+#pragma unroll 8
+                for (int i = 0; i < nv; ++i) wr -= hs[i][r] * V[int64_t(i) * n * R + row * R + r];
+                w[row * R + r] = wr;
+            }
+            wl[t][r] = wr;
+        }
+        __syncthreads();
+        if (on) {
+            const int rows = int(min<int64_t>(GS_TILE, n - base));
+#pragma unroll
+            for (int q = 0; q < GS_VPW_B; ++q) {
+                const int i = wv + 4 * q;
+                if (i < nv) {
+                    const double* Vi = V + int64_t(i) * n * R + base * R + r;
+                    double sum = 0.0;
+#pragma unroll
+                    for (int t = 0; t < GS_TILE; ++t)
+                        if (t < rows) sum += wl[t][r] * Vi[int64_t(t) * R];
+                    acc[q] += sum;
+                } else if (i == nv) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int t = 0; t < GS_TILE; ++t)
+                        if (t < rows) sum += wl[t][r] * wl[t][r];
+                    acc[q] += sum;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (r < R) {
+        double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
+#pragma unroll
+        for (int q = 0; q < GS_VPW_B; ++q) {
+            const int i = wv + 4 * q;
+            if (i <= nv) out[i] = acc[q];
+        }
+    }
+}
+
 // One block per subtask: sums the nblk partial rows of pass `mode`.
 // mode 0: h1 (nv values). mode 1: h2 and ||w'||^2, then the new Hessenberg
 // column, m, breakdown and the normalisation scale of v_{j+1}. mode 2: the
@@ -623,8 +697,7 @@ void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial
     const dim3 gd(nb, (nv + GS_CHUNK - 1) / GS_CHUNK);
     kb_gs_dots<<<gd, 256, 0, st>>>(n, R, V, nv, w, partial, ks, 0);
     kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 0, ks, nullptr);
-    kb_gs_axpy<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks, 0);
-    kb_gs_dots<<<gd, 256, 0, st>>>(n, R, V, nv, w, partial, ks, 1);
+    kb_gs_update_dots<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
     kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 1, ks, nullptr);
     kb_gs_axpy<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks, 1);
 }

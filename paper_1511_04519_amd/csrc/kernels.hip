@@ -598,6 +598,23 @@ __global__ __launch_bounds__(256) void k_checks(KState* ks, double gamma,
     check_block(ks, m, brk, gamma, taus, c, sel, n_sel, tol, u_buf, est_buf, m_max, update_state, sm);
 }
 
+// z1 += sum_c coef[c] Z1[:, q[c]], z2 likewise (columns of n, in the order of c).
+__global__ void k_spot_update(int64_t n, int cnt, const int32_t* __restrict__ q,
+                              const double* __restrict__ coef, const double* __restrict__ Z1,
+                              const double* __restrict__ Z2, double* z1, double* z2)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        double a = z1[i], b = z2[i];
+        for (int c = 0; c < cnt; ++c) {
+            const int64_t o = int64_t(q[c]) * n + i;
+            a += coef[c] * Z1[o];
+            b += coef[c] * Z2[o];
+        }
+        z1[i] = a;
+        z2[i] = b;
+    }
+}
+
 __global__ void k_set_m(KState* ks, int m)
 {
     ks->m = m;
@@ -820,6 +837,12 @@ void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* s
 }
 
 void launch_set_m(KState* ks, int m, hipStream_t st) { k_set_m<<<1, 1, 0, st>>>(ks, m); }
+
+void launch_spot_update(int64_t n, int cnt, const int32_t* q, const double* coef, const double* Z1,
+                        const double* Z2, double* z1, double* z2, hipStream_t st)
+{
+    if (cnt > 0) k_spot_update<<<grid_for(n), 256, 0, st>>>(n, cnt, q, coef, Z1, Z2, z1, z2);
+}
 
 // ------------------------------------------------------------- adjoint
 

@@ -145,6 +145,10 @@ void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* s
 // The process's dimension after a check decided at m (iterations launched
 // ahead of that decision may have advanced it).
 void launch_set_m(KState* ks, int m, hipStream_t st);
+// z1 += sum_c coef[c] Z1[:, q[c]] and z2 += sum_c coef[c] Z2[:, q[c]]
+// (Z1, Z2: n x columns, column-major).
+void launch_spot_update(int64_t n, int cnt, const int32_t* q, const double* coef, const double* Z1,
+                        const double* Z2, double* z1, double* z2, hipStream_t st);
 // Lets a process whose check subset passed but whose full check set did not
 // continue iterating.
 void launch_resume(KState* ks, hipStream_t st);

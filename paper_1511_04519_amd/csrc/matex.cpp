@@ -16,6 +16,7 @@
 #include <cstring>
 #include <atomic>
 #include <map>
+#include <unordered_map>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -1671,6 +1672,64 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
         S.subtasks++;
         std::vector<Segment> spots = plan_spots(p, grp.second, f->sym.iperm);
         for (DevMem* b : {&y, &y0, &z1, &z2, &sl}) HIPCHK(hipMemsetAsync(b->p, 0, b->bytes, st));
+        // z1 = G^-1 s and z2 = G^-1 C z1 are linear in the slopes s, which
+        // change only at the subtask's source rows: G^-1 e_k and
+        // G^-1 C G^-1 e_k for every source row k come from the
+        // 64-right-hand-side sweeps once, and a spot then adds its changed
+        // slopes' columns instead of solving twice. Done when the columns
+        // fit half the free device memory and the spots outnumber eight
+        // per 64 columns (a 64-column pair costs about six one-vector ones).
+        std::vector<int32_t> srows;
+        for (const Segment& sg : spots) srows.insert(srows.end(), sg.node.begin(), sg.node.end());
+        std::sort(srows.begin(), srows.end());
+        srows.erase(std::unique(srows.begin(), srows.end()), srows.end());
+        const int64_t nq = int64_t(srows.size());
+        DevMem Zc;
+        std::unordered_map<int32_t, int32_t> qof;
+        {
+            size_t fr = 0, tot = 0;
+            HIPCHK(hipMemGetInfo(&fr, &tot));
+            const size_t need = sizeof(double) * size_t(n) * size_t(2 * nq + 3 * RMAX);
+            int64_t n_chg = 0;
+            for (const Segment& sg : spots) n_chg += sg.node.empty() ? 0 : 1;
+            if (nq > 0 && need <= fr / 2 && n_chg > 8 * ((nq + RMAX - 1) / RMAX)) {
+                Zc = DevMem(sizeof(double) * size_t(n) * size_t(2 * nq));
+                const int Rm = int(std::min<int64_t>(RMAX, nq));
+                BatchScratch bsc(*f, Rm);
+                DevMem E(sizeof(double) * size_t(n) * Rm), X1(sizeof(double) * size_t(n) * Rm),
+                    X2(sizeof(double) * size_t(n) * Rm), ident(sizeof(int32_t) * size_t(n)),
+                    ones(sizeof(int32_t) * RMAX + sizeof(double) * RMAX);
+                {
+                    std::vector<int32_t> id(n);
+                    for (int64_t i = 0; i < n; ++i) id[i] = int32_t(i);
+                    HIPCHK(hipMemcpyAsync(ident.p, id.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                }
+                double* Z1 = Zc.as<double>();
+                double* Z2 = Z1 + n * nq;
+                for (int64_t q0 = 0; q0 < nq; q0 += RMAX) {
+                    const int R = int(std::min<int64_t>(RMAX, nq - q0));
+                    std::vector<char> hb(sizeof(double) * RMAX + sizeof(int32_t) * RMAX);
+                    double* hv = reinterpret_cast<double*>(hb.data());
+                    int32_t* hi = reinterpret_cast<int32_t*>(hv + RMAX);
+                    for (int r = 0; r < R; ++r) {
+                        hv[r] = 1.0;
+                        hi[r] = int32_t(int64_t(srows[q0 + r]) * R + r);
+                    }
+                    ring.copy(ones.p, hb.data(), hb.size(), st);
+                    launch_b_fill(n * R, 0.0, E.as<double>(), st);
+                    launch_scatter_add(R, reinterpret_cast<int32_t*>(ones.as<double>() + RMAX), ones.as<double>(),
+                                       E.as<double>(), st);
+                    dev_solve_batched(*f, n_shifts, R, E.as<double>(), nullptr, X1.as<double>(), bsc, st);
+                    launch_b_deinterleave(n, R, ident.as<int32_t>(), X1.as<double>(), Z1 + q0 * n, st);
+                    dev_solve_batched(*f, n_shifts, R, X1.as<double>(), cperm, X2.as<double>(), bsc, st);
+                    launch_b_deinterleave(n, R, ident.as<int32_t>(), X2.as<double>(), Z2 + q0 * n, st);
+                }
+                HIPCHK(hipStreamSynchronize(st));   // the scratch is released below
+                for (int64_t q = 0; q < nq; ++q) qof[srows[q]] = int32_t(q);
+                S.solve_pairs_g += 2 * nq;
+            }
+        }
         int64_t t_a = 0;
         size_t k_spot = 0;
         while (t_a < p->t_end) {
@@ -1687,15 +1746,22 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
                     }
                     std::vector<char> buf(need);
                     std::memcpy(buf.data(), sg.dslope.data(), sizeof(double) * cnt);
-                    std::memcpy(buf.data() + sizeof(double) * cnt, sg.node.data(), sizeof(int32_t) * cnt);
+                    int32_t* bi = reinterpret_cast<int32_t*>(buf.data() + sizeof(double) * cnt);
+                    for (int32_t c = 0; c < cnt; ++c) bi[c] = Zc.p ? qof.at(sg.node[c]) : sg.node[c];
                     ring.copy(d_ev.p, buf.data(), need, st);
                     double* dv = d_ev.as<double>();
-                    launch_scatter_add(cnt, reinterpret_cast<int32_t*>(dv + cnt), dv, sl.as<double>(), st);
-                    dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
-                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
-                    dev_solve(*f, n_shifts, z1.as<double>(), cperm, z2.as<double>(),
-                              wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
-                    S.solve_pairs_g += 2;
+                    const int32_t* di = reinterpret_cast<int32_t*>(dv + cnt);
+                    if (Zc.p) {
+                        launch_spot_update(n, cnt, di, dv, Zc.as<double>(), Zc.as<double>() + n * nq,
+                                           z1.as<double>(), z2.as<double>(), st);
+                    } else {
+                        launch_scatter_add(cnt, di, dv, sl.as<double>(), st);
+                        dev_solve(*f, n_shifts, sl.as<double>(), nullptr, z1.as<double>(),
+                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
+                        dev_solve(*f, n_shifts, z1.as<double>(), cperm, z2.as<double>(),
+                                  wk.tmp.as<double>(), wk.upd.as<double>(), nullptr, st);
+                        S.solve_pairs_g += 2;
+                    }
                 }
                 k_spot++;
             }
