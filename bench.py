@@ -236,7 +236,7 @@ def main():
     roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
                 "traffic": traffic,
-                "kernel": "substitution pair: k_forward*/k_backward* level sweeps on C + gamma G",
+                "kernel": "substitution pair: k_forward_tree/k_backward_tree subtree sweeps and k_forward/k_backward level sweeps on C + gamma G",
                 "pair_us": round(pair_s * 1e6, 2), "pair_bytes": int(pair_b),
                 "kernel_sources": kernel_source_digest()}
     # calibration copy for the hardware byte counters (256 MiB read + write)
