@@ -263,6 +263,7 @@ def main():
                    "mode": "plain", "tol": args.tol, "gamma": p.gamma, "m_max": p.m_max,
                    "factor_s": round(factor_s, 2), "segments": st["segments"],
                    "bases": st["bases"], "solve_pairs": st["solve_pairs_m"] + st["solve_pairs_g"],
+                   "krylov_dims": st["krylov_dims"],
                    "max_abs_err_vs_oracle_0_500ps": err_head,
                    "max_abs_err_vs_oracle_2900_3000ps": err_mid},
         "roofline": roofline, "cpu_baseline": cpu, "batched": batched,

@@ -185,7 +185,9 @@ typedef struct {
     int64_t subtasks;
     int64_t segments;        /* steps taken (after ladder cuts and halvings)    */
     int64_t bases;           /* Krylov bases generated                          */
-    int64_t solve_pairs_m;   /* substitution pairs with C + gamma_k G           */
+    int64_t solve_pairs_m;   /* substitution pairs with C + gamma_k G, counting
+                                in the plain mode the iterations computed
+                                ahead of a stopping decision and discarded   */
     int64_t solve_pairs_g;   /* right-hand sides solved with G: in the plain
                                 mode two per source row of a subtask
                                 (G^-1 e_k and G^-1 C G^-1 e_k, solved 64 at a

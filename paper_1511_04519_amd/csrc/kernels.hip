@@ -542,12 +542,20 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(int64_t n, const doubl
 // to working precision after the first pass, so there is no cancellation);
 // v_{j+1} = w'' / ||w''||, and column j of Ht = h1 + h2 with Ht(j+1,j) = ||w''||.
 // Every block sums the pass-2 partials itself; block 0 records the column.
+__device__ inline void publish_ticket(KState* ks, int32_t ticket)
+{
+    __hip_atomic_store(&ks->ticket, ticket, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, int64_t ldv, int nv,
                                                    const double* __restrict__ w,
                                                    const double* partial_in, KState* ks,
-                                                   const int32_t* done)
+                                                   const int32_t* done, int32_t ticket)
 {
-    if (done && *done) return;
+    if (done && *done) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) publish_ticket(ks, ticket);
+        return;
+    }
     __shared__ double h[NVMAX + 1];
     __shared__ double sc;
     reduce_partials_waves<GS_WAVES>(partial_in, NVMAX + 1, gridDim.x, nv + 1, h);
@@ -568,6 +576,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, 
             ks->m = nv;
             ks->breakdown = brk ? 1 : 0;
             ks->brk[j] = brk ? 1 : 0;
+            publish_ticket(ks, ticket);
         }
     }
     __syncthreads();
@@ -578,6 +587,25 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, 
 #pragma unroll 8
         for (int i = 0; i < nv; ++i) wr -= h[i] * V[r + i * ldv];
         vout[r] = wr * inv;
+    }
+}
+
+// The waiting lane sleeps between polls of the ticket; the wait ends at the
+// ticket or at the clock limit, whichever comes first.
+__global__ __launch_bounds__(64) void k_wait_ticket(KState* ks, int32_t ticket, int64_t max_ticks)
+{
+    if (threadIdx.x != 0) return;
+    const int64_t t0 = int64_t(wall_clock64());
+    while (true) {
+        const int32_t t = __hip_atomic_load(&ks->ticket, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        if (int32_t(uint32_t(t) - uint32_t(ticket)) >= 0) return;
+        if (int64_t(wall_clock64()) - t0 > max_ticks) {
+            ks->wait_err = 1;
+            ks->converged = 0;
+            __hip_atomic_store(&ks->done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(4);
     }
 }
 
@@ -820,10 +848,16 @@ void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w
 }
 
 void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w,
-                      const double* partial, KState* ks, const int32_t* done, hipStream_t st)
+                      const double* partial, KState* ks, const int32_t* done, int32_t ticket,
+                      hipStream_t st)
 {
     const int64_t half = int64_t(RED_BLOCKS) * (MAXM + 2);
-    k_gs_finish<<<gs_grid(n), GS_THREADS, 0, st>>>(n, V, ldv, nv, w, partial + half, ks, done);
+    k_gs_finish<<<gs_grid(n), GS_THREADS, 0, st>>>(n, V, ldv, nv, w, partial + half, ks, done, ticket);
+}
+
+void launch_wait_ticket(KState* ks, int32_t ticket, int64_t max_ticks, hipStream_t st)
+{
+    k_wait_ticket<<<1, 64, 0, st>>>(ks, ticket, max_ticks);
 }
 
 size_t checks_lds_bytes() { return sizeof(double) * (7 * MAXM * LD + 2 * MAXM); }
@@ -837,6 +871,10 @@ void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* s
 }
 
 void launch_set_m(KState* ks, int m, hipStream_t st) { k_set_m<<<1, 1, 0, st>>>(ks, m); }
+
+// Diagnostics: the device wall clock (100 MHz) when the stream reaches this point.
+__global__ void k_stamp(int64_t* buf, int64_t idx) { buf[idx] = int64_t(wall_clock64()); }
+void launch_stamp(int64_t* buf, int64_t idx, hipStream_t st) { k_stamp<<<1, 1, 0, st>>>(buf, idx); }
 
 void launch_spot_update(int64_t n, int cnt, const int32_t* q, const double* coef, const double* Z1,
                         const double* Z2, double* z1, double* z2, hipStream_t st)

@@ -99,6 +99,8 @@ struct KState {
     int32_t breakdown;
     int32_t counter;       // last-block detection of the grid reductions
     int32_t mdec;          // dimension of the last iterating check (0 after set-up)
+    int32_t ticket;        // number of the last iteration whose Ht column is written
+    int32_t wait_err;      // 1 after a check gave up waiting for its iteration
     double beta;           // ||v||
     double est;            // max estimate over the check set at dimension m
     double nrm2;           // ||w'||^2 after the first Gram-Schmidt pass
@@ -130,8 +132,17 @@ void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const doubl
                     double* partial, KState* ks, const int32_t* done, hipStream_t st);
 void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w,
                       double* partial, KState* ks, const int32_t* done, hipStream_t st);
+// ticket: the iteration's number, published in ks->ticket (agent-scope
+// release) once its Ht column, m and breakdown flags are written, also when
+// the state is done and the kernel does nothing else.
 void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w,
-                      const double* partial, KState* ks, const int32_t* done, hipStream_t st);
+                      const double* partial, KState* ks, const int32_t* done, int32_t ticket,
+                      hipStream_t st);
+// One thread waits until ks->ticket has reached `ticket` (wrap-safe), so a
+// kernel queued after it on another stream sees that iteration's column
+// without a cross-stream event. After max_ticks of the 100 MHz device clock
+// it gives up: wait_err = 1, done = 1, converged = 0.
+void launch_wait_ticket(KState* ks, int32_t ticket, int64_t max_ticks, hipStream_t st);
 
 // ---- small dense part: H_m, exp(tau H_m) e1, estimates, decision ----------
 // One workgroup per checked offset: sel[0 .. n_sel) (sel null: offsets
@@ -145,6 +156,7 @@ void launch_checks(KState* ks, double gamma, const double* tau, const int32_t* s
 // The process's dimension after a check decided at m (iterations launched
 // ahead of that decision may have advanced it).
 void launch_set_m(KState* ks, int m, hipStream_t st);
+void launch_stamp(int64_t* buf, int64_t idx, hipStream_t st);
 // z1 += sum_c coef[c] Z1[:, q[c]] and z2 += sum_c coef[c] Z2[:, q[c]]
 // (Z1, Z2: n x columns, column-major).
 void launch_spot_update(int64_t n, int cnt, const int32_t* q, const double* coef, const double* Z1,

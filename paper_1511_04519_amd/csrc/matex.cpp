@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -607,19 +608,19 @@ struct Work {
     int64_t n = 0;
     DevMem V, w, tmp, upd, partial, ks, u, est, taus, sel;
     int64_t max_checks = 0;
-    hipStream_t cs = nullptr;          // checks, beside the next iteration
-    hipEvent_t ev_it = nullptr, ev_c = nullptr;
+    // checks run on their own stream beside the next iteration; a check waits
+    // for its iteration's ticket (the number gs_finish publishes), not for a
+    // cross-stream event: such an event wait slowed every iteration of the
+    // main stream by about 20 us on MI355X
+    hipStream_t cs = nullptr;
+    int32_t ticket = 0;                // number of the last iteration launched
     Work(const Work&) = delete;
     Work& operator=(const Work&) = delete;
     ~Work() {
-        if (ev_it) (void)hipEventDestroy(ev_it);
-        if (ev_c) (void)hipEventDestroy(ev_c);
         if (cs) (void)hipStreamDestroy(cs);
     }
     Work(const matex_factor_s& F, int64_t max_chk) {
         HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-        HIPCHK(hipEventCreateWithFlags(&ev_it, hipEventDisableTiming));
-        HIPCHK(hipEventCreateWithFlags(&ev_c, hipEventDisableTiming));
         n = F.sym.n;
         V = DevMem(sizeof(double) * n * (MAXM + 1));
         w = DevMem(sizeof(double) * n);
@@ -639,8 +640,16 @@ struct Work {
 };
 
 struct KsHost {
-    int32_t done, converged, m, breakdown, counter, mdec;   // KState's leading fields
+    int32_t done, converged, m, breakdown, counter, mdec, ticket, wait_err;   // KState's leading fields
+    double beta, est;
 };
+static_assert(offsetof(KsHost, wait_err) == offsetof(KState, wait_err) &&
+              offsetof(KsHost, beta) == offsetof(KState, beta) &&
+              offsetof(KsHost, est) == offsetof(KState, est), "KsHost mirrors KState's head");
+
+// A check waits at most this long (100 MHz device clock ticks, 20 s) for its
+// iteration; far beyond any one iteration, so reaching it means a fault.
+constexpr int64_t TICKET_WAIT_MAX = int64_t(2000000000);
 
 KsHost read_state(const Work& wk, KsHost* pinned, hipStream_t st)
 {
@@ -666,15 +675,39 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, hipSt
               wk.tmp.as<double>(), wk.upd.as<double>(), wk.done(), st);
     launch_gs_dots(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_update(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
-    launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
+    launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(),
+                     ++wk.ticket, st);
 }
+
+// Host-side timing of the iteration loop (diagnostics, MATEX_HOST_TIMES=1):
+// seconds spent enqueuing iterations and waiting for check results.
+// With stamps on, the device clock is also written at each iteration's
+// start (tag 0), a basis's set-up (tag 1) and its reconstruction's end (tag 2).
+struct HostTimes {
+    double enqueue_s = 0.0, wait_s = 0.0;
+    int64_t iterations = 0, waits = 0;
+    int64_t* d_stamps = nullptr;
+    int64_t cap = 0;
+    std::vector<int8_t> tags;
+    void stamp(int tag, hipStream_t st) {
+        if (!d_stamps || int64_t(tags.size()) >= cap) return;
+        launch_stamp(d_stamps, int64_t(tags.size()), st);
+        tags.push_back(int8_t(tag));
+    }
+};
+thread_local HostTimes g_host_times;
 
 // Runs Alg. 1 from the (already normalised) V_0 until a check stops it.
 // The estimate of dimension j + 1 runs on the work's check stream while
 // the main stream already computes iteration j + 1: the decision lands a
 // check later on the host, the next iteration never waits for it, and an
 // iteration computed past the decision is discarded (the dimension is set
-// back to the decided one). With more than two check offsets the
+// back to the decided one). An iteration goes ahead unless the decay of the
+// last estimates predicts that the pending check stops: the next estimate
+// is taken as the last one times the mean ratio per dimension over the last
+// two (at most 1), and a prediction below PRED_KAPPA * tol holds the
+// iteration back until the check has landed. A wrong hold costs one check's
+// latency, a wrong go-ahead one discarded iteration. With more than two check offsets the
 // iterations test only the first and the last; once those pass, one
 // evaluation of every offset confirms the decision, and if it fails the
 // process continues with every offset tested. This stops at the same
@@ -682,9 +715,13 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, hipSt
 // failing full set, and the evaluation leaves every offset's vector of the
 // current dimension for the next iteration's difference term. Returns the
 // final host view of the state (m the decided dimension).
+constexpr double PRED_KAPPA = 1.5;
+
 KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, double tol, int m_max,
-                   int m_pred, KsHost* pinned, hipStream_t st)
+                   KsHost* pinned, hipStream_t st, int* n_launched = nullptr,
+                   std::vector<double>* ests = nullptr)
 {
+    int launched = 0;
     bool full = n_tau <= 2;
     if (!full) launch_set_ends(wk.sel.as<int32_t>(), n_tau - 1, st);
     // a zero start vector has the state done already: the first check then
@@ -692,41 +729,55 @@ KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, doub
     KsHost h{};
     const double gamma = F.gammas[shift];
     auto launch_iter = [&](int i) {
+        const double t0 = now_s();
+        g_host_times.stamp(0, st);
         krylov_iteration(F, shift, wk, i, st);
-        HIPCHK(hipEventRecord(wk.ev_it, st));
+        launched++;
+        g_host_times.enqueue_s += now_s() - t0;
+        g_host_times.iterations++;
     };
-    auto launch_check = [&](int i) {   // dimension i + 1, after iteration i
-        HIPCHK(hipStreamWaitEvent(wk.cs, wk.ev_it, 0));
+    auto launch_check = [&](int i) {   // dimension i + 1, after iteration i (the last launched)
+        launch_wait_ticket(wk.kst(), wk.ticket, TICKET_WAIT_MAX, wk.cs);
         launch_checks(wk.kst(), gamma, wk.taus.as<double>(), full ? nullptr : wk.sel.as<int32_t>(),
                       full ? n_tau : 2, tol, wk.u.as<double>(), wk.est.as<double>(), m_max, 1, i + 1, wk.cs);
         HIPCHK(hipMemcpyAsync(pinned, wk.ks.p, sizeof(KsHost), hipMemcpyDeviceToHost, wk.cs));
     };
     int j = 0;   // next iteration
+    double e[3] = {0.0, 0.0, 0.0};   // the last estimates, newest first
+    int n_e = 0;
+    auto predicts_stop = [&]() {
+        if (n_e < 2 || !(e[0] > 0.0) || !(e[1] > 0.0)) return false;
+        const double r = n_e >= 3 && e[2] > 0.0 ? std::sqrt(e[0] / e[2]) : e[0] / e[1];
+        return e[0] * std::min(r, 1.0) < PRED_KAPPA * tol;
+    };
     while (true) {
         if (h.done || j >= m_max) break;
         launch_iter(j);
         launch_check(j);
         ++j;
         int mdec = 0;
-        bool past = m_pred <= 0;
         while (true) {
             // iteration j goes ahead of the decision on dimension j unless
-            // that decision is predicted to stop (an iteration launched past
-            // the stop still costs its launches)
-            const bool ahead = j < m_max && (past || j < m_pred);
+            // that decision is predicted to stop
+            const bool ahead = j < m_max && !predicts_stop();
             if (ahead) launch_iter(j);
+            const double t0 = now_s();
             HIPCHK(hipStreamSynchronize(wk.cs));
+            g_host_times.wait_s += now_s() - t0;
+            g_host_times.waits++;
             h = *pinned;
+            if (h.wait_err) throw HipError{hipErrorLaunchTimeOut, "a check timed out waiting for its iteration"};
+            if (ests) ests->push_back(h.est);
+            e[2] = e[1];
+            e[1] = e[0];
+            e[0] = h.est;
+            n_e++;
             if (h.done || j >= m_max) { mdec = h.mdec; break; }
-            if (!ahead) {
-                launch_iter(j);
-                past = true;
-            }
+            if (!ahead) launch_iter(j);
             launch_check(j);
             ++j;
         }
-        HIPCHK(hipEventRecord(wk.ev_c, wk.cs));
-        HIPCHK(hipStreamWaitEvent(st, wk.ev_c, 0));
+        // the check stream is idle: the host has seen its last copy land
         launch_set_m(wk.kst(), mdec, st);
         h.m = mdec;
         if (full || !h.converged || mdec == 0) break;
@@ -740,6 +791,7 @@ KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, doub
         h.done = 0;
         j = mdec;   // the iteration launched past the decision may have been cut short
     }
+    if (n_launched) *n_launched = launched;
     return h;
 }
 
@@ -1071,7 +1123,7 @@ matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, co
             launch_setup_v(n, acc.as<double>(), zero.as<double>(), zero.as<double>(), V,
                            wk.partial.as<double>(), wk.kst(), st);
             launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-            KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, 0, pin.as<KsHost>(), st);
+            KsHost h = run_arnoldi(*f, shift, wk, n_tau, tol, m_max, pin.as<KsHost>(), st);
             if (!h.converged) all_conv = false;
             if (m_used) m_used[r] = h.m;
             if (est) est[r] = read_est(wk, pin.as<double>() + 8, st);
@@ -1666,7 +1718,13 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
     const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
     const double* cperm = f->d_cperm.as<double>();
     double* V = wk.V.as<double>();
-    int m_last = 0;   // the previous basis's dimension predicts the next one's
+    const char* ht_env = std::getenv("MATEX_HOST_TIMES");
+    const bool host_times = ht_env && ht_env[0] == '1';
+    if (host_times) {
+        g_host_times = HostTimes{};
+        g_host_times.cap = int64_t(1) << 20;
+        HIPCHK(hipMalloc(&g_host_times.d_stamps, sizeof(int64_t) * g_host_times.cap));
+    }
 
     for (auto& grp : groups) {
         S.subtasks++;
@@ -1770,17 +1828,21 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
             int ksh = ladder_shift(f->gammas, offs[0], shift_ratio);
             ladder_cut(offs, f->gammas, ksh);
             KsHost h{};
+            int launched = 0;
+            std::vector<double> ests;
             while (true) {
                 std::vector<double> taus(offs.size());
                 for (size_t q = 0; q < offs.size(); ++q) taus[q] = double(offs[q]) * FS;
                 ring.copy(wk.taus.p, taus.data(), sizeof(double) * taus.size(), st);
+                g_host_times.stamp(1, st);
                 launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
                                wk.partial.as<double>(), wk.kst(), st);
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-                h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, m_last, hks, st);
-                if (h.m > 0) m_last = h.m;
+                ests.clear();
+                h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, hks, st, &launched,
+                                trace ? &ests : nullptr);
                 S.bases++;
-                S.solve_pairs_m += h.m;
+                S.solve_pairs_m += launched;
                 S.krylov_dims += h.m;
                 S.m_peak = std::max(S.m_peak, h.m);
                 if (trace && !h.converged)
@@ -1816,8 +1878,10 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
             const int64_t t_b = t_a + offs.back();
             if (trace) {
                 const double e = read_est(wk, hest, st);
-                fprintf(stderr, "[matex] seg t_a=%lld t_b=%lld shift=%d m=%d conv=%d est=%.3e checks=%zu\n",
-                        (long long)t_a, (long long)t_b, ksh, h.m, h.converged, e, offs.size());
+                fprintf(stderr, "[matex] seg t_a=%lld t_b=%lld shift=%d m=%d conv=%d est=%.3e checks=%zu launched=%d ests",
+                        (long long)t_a, (long long)t_b, ksh, h.m, h.converged, e, offs.size(), launched);
+                for (double v : ests) fprintf(stderr, " %.3e", v);
+                fprintf(stderr, "\n");
             }
             if (rec) rec->add(t_a, t_b, ksh, h.m, V, &wk.kst()->beta, st);
             // snapshots (Alg. 2 reuse) at the probes, then the full state at t_b
@@ -1829,10 +1893,35 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
             launch_recon_full(n, double(offs.back()) * FS,
                               wk.u.as<double>() + int64_t(offs.size() - 1) * MAXM, wk.kst(), V, n,
                               y.as<double>(), y0.as<double>(), z1.as<double>(), z2.as<double>(), st);
+            g_host_times.stamp(2, st);
             S.segments++;
             t_a = t_b;
         }
         launch_axpy_scaled(n, 1.0, y.as<double>(), ysum.as<double>(), st);
+    }
+    if (host_times) {
+        HostTimes& t = g_host_times;
+        fprintf(stderr, "[matex] host: %lld iterations enqueued in %.3f s (%.1f us each), %lld check waits %.3f s (%.1f us each)\n",
+                (long long)t.iterations, t.enqueue_s, 1e6 * t.enqueue_s / std::max<int64_t>(1, t.iterations),
+                (long long)t.waits, t.wait_s, 1e6 * t.wait_s / std::max<int64_t>(1, t.waits));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<int64_t> ts(t.tags.size());
+        if (!ts.empty())
+            HIPCHK(hipMemcpy(ts.data(), t.d_stamps, sizeof(int64_t) * ts.size(), hipMemcpyDeviceToHost));
+        // intervals (10 ns ticks) by the tags that open and close them
+        double sum[3][3] = {}, cnt[3][3] = {};
+        for (size_t i = 1; i < ts.size(); ++i) {
+            sum[t.tags[i - 1]][t.tags[i]] += double(ts[i] - ts[i - 1]) * 1e-2;
+            cnt[t.tags[i - 1]][t.tags[i]] += 1;
+        }
+        const char* nm[3] = {"iter", "setup", "recon_end"};
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                if (cnt[a][b] > 0)
+                    fprintf(stderr, "[matex] stamps %s -> %s: %.0f intervals, %.3f s, %.1f us each\n", nm[a], nm[b],
+                            cnt[a][b], 1e-6 * sum[a][b], sum[a][b] / cnt[a][b]);
+        HIPCHK(hipFree(t.d_stamps));
+        g_host_times = HostTimes{};
     }
     if (!o->output_droop) launch_vdd_minus(int64_t(n_probe) * n_out, f->vdd, d_probe_out, st);
     if (d_final) {
@@ -2087,7 +2176,6 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
         };
         const char* trace_env = std::getenv("MATEX_TRACE");
         const bool trace = trace_env && trace_env[0] == '1';
-        int m_last = 0;
         int64_t t_hi = t_last;
         jump(t_hi);
         // a jump puts weight on modes much faster than the steps; the step
@@ -2181,7 +2269,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                 launch_gs_update(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
                                  wf->done(), st);
                 launch_gs_finish(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
-                                 wf->done(), st);
+                                 wf->done(), ++wf->ticket, st);
             }
         };
         if (d_grad_c) {
@@ -2245,8 +2333,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                 launch_setup_v(n, lam.as<double>(), zero.as<double>(), zero.as<double>(), V,
                                wk.partial.as<double>(), wk.kst(), st);
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
-                h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, m_last, hks, st);
-                if (h.m > 0) m_last = h.m;
+                h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, hks, st);
                 if (h.converged || ksh + 1 == n_shifts) break;
                 ksh++;
             }
