@@ -32,6 +32,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Nested-dissection leaf size of the 180k-node grid's factor: leaves of up to
+# 32 nodes give 13 levels (4 of them in the subtree sweeps) instead of 14, one
+# level launch fewer per sweep; measured 146 us per pair and 14.1 s per
+# transient against 149 us and 14.4 s with 16-node leaves.
+CONFIG1_LEAF = 32
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_pair_config1.md")
 TRAFFIC_PROFILE64 = os.path.join(ROOT, "profiles", "solve_pair64_config2.md")
 PLAIN_SOURCES = ("kernels.hip", "kernels.hpp", "device_common.hpp", "factor.cpp", "factor.hpp")
@@ -181,8 +186,9 @@ def main():
     M.lib()   # fails loudly if libmatex.so is missing
     if args.pairs_only:
         out = {}
-        for name, prob, nrhs, reps in (("config1", I.config1(), 1, 50), ("config2", I.config2(), 64, 20)):
-            F = M.matex_factor(prob.netlist, prob.gamma)
+        for name, prob, nrhs, reps, leaf in (("config1", I.config1(), 1, 50, CONFIG1_LEAF),
+                                             ("config2", I.config2(), 64, 20, 16)):
+            F = M.matex_factor(prob.netlist, prob.gamma, leaf_max=leaf)
             sec, byt = M.matex_time_solves(F, which=0, reps=reps, nrhs=nrhs)
             out[name] = {"nrhs": nrhs, "pairs": reps + 1, "pair_ms": sec * 1e3, "pair_bytes": byt,
                          "GB_s": byt / sec / 1e9, "frac": byt / sec / 1e9 / HBM_PEAK_GBS}
@@ -200,7 +206,7 @@ def main():
                       p.t_out[p.t_out <= T], p.probe)
     n, n_out = p.netlist.n, p.t_out.size
     t0 = time.time()
-    F = M.matex_factor(p.netlist, p.gamma)
+    F = M.matex_factor(p.netlist, p.gamma, leaf_max=CONFIG1_LEAF)
     factor_s = time.time() - t0
     print(f"[bench] factor {factor_s:.2f} s (host analyse {F.info['seconds_analyse']:.2f} s, "
           f"numeric {F.info['seconds_numeric']:.2f} s), nnz(L) {F.info['nnz_l']}, "
