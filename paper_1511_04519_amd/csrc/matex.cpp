@@ -182,6 +182,11 @@ constexpr int64_t RESIDENT_BLOCKS = 2048;
 constexpr int64_t TREE_MIN_BLOCKS = 512;
 constexpr int32_t TREE_MAX_NODES = 4 * TW;
 constexpr int64_t TREE_MAX_SHARED = 4096;
+// The most subtree blocks one launch takes: all of them resident at once
+// (two per compute unit). Plain transients whose subtree sweeps ran in
+// several rounds of blocks stopped twice with a memory fault whose cause is
+// not found, so larger grids sweep those levels with the level kernels.
+constexpr int64_t TREE_MAX_BLOCKS = 512;
 
 // Subtree schedule of the bottom `limit` levels at most (limit < 0: none, 0:
 // automatic): the most levels whose supernodes all fit a wavefront item
@@ -274,6 +279,10 @@ void build_tree(matex_factor_s& F, const std::vector<int32_t>& pos_base, const s
             cur_shared += need;
             bshared.back() = cur_shared;
         }
+    if (int64_t(blocks.size()) > TREE_MAX_BLOCKS) {
+        F.tree = TreeTasks{};
+        return;
+    }
     int32_t max_nr = 64;
     for (size_t bi = 0; bi < blocks.size(); ++bi) {
         int32_t off = 0;
