@@ -1,0 +1,50 @@
+"""The one-vector iteration pipeline: checks on their own stream that wait for
+their iteration's ticket, iterations launched ahead of the pending decision
+(and cut short when it stops the process), and the device-clock diagnostics.
+Expected values come from the CPU oracle (R-MATEX written from the paper)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import rmatex as RM
+from paper_1511_04519_amd import instances as I
+from paper_1511_04519_amd import matex as M
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+GAMMA = 1e-11
+
+
+def test_pipeline_counts_and_diagnostics(capfd):
+    """Alg. 1 / Alg. 2 through the pipelined loop: the result matches the
+    oracle; every kept Krylov dimension was computed once, and iterations
+    computed past a stopping decision (counted in solve_pairs_m) are at most
+    one per decision; the device-clock stamps (MATEX_HOST_TIMES=1) change no
+    bit of the result."""
+    print("\n[case] pipeline small seed=102 2x13x11", flush=True)
+    p = I.small(102, layers=2, nx=13, ny=11, n_src=9, t_end=3 * I.NS)
+    F = M.matex_factor(p.netlist, GAMMA)
+    x, xf, st = M.matex_transient(F, p, tol=1e-12, m_max=20)
+    torch.cuda.synchronize()
+    x = x.cpu().numpy()
+    xo, _ = RM.RMatex(p.netlist, GAMMA).transient(p, tol=1e-12, m_max=20)
+    assert np.abs(x - xo).max() <= 1e-10
+    discarded = st["solve_pairs_m"] - st["krylov_dims"]
+    assert 0 <= discarded <= 2 * st["bases"], st
+    old = os.environ.get("MATEX_HOST_TIMES")
+    os.environ["MATEX_HOST_TIMES"] = "1"
+    try:
+        x2, xf2, st2 = M.matex_transient(F, p, tol=1e-12, m_max=20)
+        torch.cuda.synchronize()
+    finally:
+        if old is None:
+            del os.environ["MATEX_HOST_TIMES"]
+        else:
+            os.environ["MATEX_HOST_TIMES"] = old
+    err = capfd.readouterr().err
+    assert "[matex] stamps iter -> iter" in err
+    assert np.array_equal(x2.cpu().numpy(), x)
+    assert np.array_equal(xf2.cpu().numpy(), xf.cpu().numpy())
+    assert st2["krylov_dims"] == st["krylov_dims"] and st2["segments"] == st["segments"]
