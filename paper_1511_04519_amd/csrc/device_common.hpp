@@ -494,6 +494,100 @@ __device__ inline double* expm_mat(double* H, int m, double tau, double* buf)
     return R;
 }
 
+// e^{tau H} by the Taylor polynomial of degree 18 with scaling and squaring:
+// A = tau H / 2^s with ||A||_1 <= 1, where the remainder is below
+// e / 19! < 2.3e-17 (under the unit roundoff), then s squarings. The
+// polynomial is evaluated by Paterson and Stockmeyer's scheme in A^4
+// (A^2, A^3, A^4, then four Horner steps: seven products) and needs no
+// linear solve, which on one check's m x m system costs more than the
+// products. Buffers as for expm_mat; returns the matrix holding the result.
+static __constant__ double TAYLOR18[19] = {
+    1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0, 1.0 / 120.0, 1.0 / 720.0, 1.0 / 5040.0, 1.0 / 40320.0,
+    1.0 / 362880.0, 1.0 / 3628800.0, 1.0 / 39916800.0, 1.0 / 479001600.0, 1.0 / 6227020800.0,
+    1.0 / 87178291200.0, 1.0 / 1307674368000.0, 1.0 / 20922789888000.0, 1.0 / 355687428096000.0,
+    1.0 / 6402373705728000.0};
+
+template <int L = LD>
+__device__ inline double* expm_taylor(double* H, int m, double tau, double* buf)
+{
+    double* A = buf;
+    double* A2 = A + (L - 1) * L;
+    double* A3 = A2 + (L - 1) * L;
+    double* A4 = A3 + (L - 1) * L;
+    double* S = A4 + (L - 1) * L;
+    double* P = S + (L - 1) * L;
+    __shared__ double nrm;
+    __shared__ int sq;
+    // 1-norm of tau H: column sums by wavefront 0, then their maximum
+    if (threadIdx.x < 64) {
+        double best = 0.0;
+        for (int j = threadIdx.x; j < m; j += 64) {
+            double c = 0.0;
+            for (int i0 = 0; i0 < m; i0 += KB) {
+                double v[KB];
+#pragma unroll
+                for (int q = 0; q < KB; ++q) v[q] = H[min(i0 + q, m - 1) * L + j];
+#pragma unroll
+                for (int q = 0; q < KB; ++q)
+                    if (i0 + q < m) c += fabs(v[q]);
+            }
+            best = fmax(best, c);
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) best = fmax(best, __shfl_xor(best, o, 64));
+        nrm = best * tau;
+    }
+    if (threadIdx.x == 0) {
+        // a non-finite norm gives no squarings (the result is then NaN)
+        int s = 0;
+        if (nrm > 1.0 && nrm < 1e300) s = int(ceil(log2(nrm)));
+        sq = min(s, 1100);
+    }
+    __syncthreads();
+    const double scl = tau * ldexp(1.0, -sq);
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m;
+        A[i * L + j] = H[i * L + j] * scl;
+    }
+    __syncthreads();
+    mm<L>(A, A, A2, m);
+    mm<L>(A2, A, A3, m);
+    mm<L>(A2, A2, A4, m);
+    const double* c = TAYLOR18;
+    // S = c16 I + c17 A + c18 A^2, then S = B_j + A^4 S for j = 3 .. 0 with
+    // B_j = c_{4j} I + c_{4j+1} A + c_{4j+2} A^2 + c_{4j+3} A^3
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+        const int i = idx / m, j = idx % m, o = i * L + j;
+        S[o] = c[18] * A2[o] + c[17] * A[o] + (i == j ? c[16] : 0.0);
+    }
+    __syncthreads();
+    for (int b = 3; b >= 0; --b) {
+        mm<L>(A4, S, P, m);
+        for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+            const int i = idx / m, j = idx % m, o = i * L + j;
+            P[o] += c[4 * b + 3] * A3[o] + c[4 * b + 2] * A2[o] + c[4 * b + 1] * A[o] +
+                    (i == j ? c[4 * b] : 0.0);
+        }
+        __syncthreads();
+        double* t = S; S = P; P = t;
+    }
+    double* R = S;
+    double* T = P;
+    for (int k = 0; k < sq; ++k) {
+        mm<L>(R, R, T, m);
+        double* t = R; R = T; T = t;
+    }
+    return R;
+}
+
+// u = e^{tau H} e1 by expm_taylor.
+__device__ inline void expm_e1_taylor(double* H, int m, double tau, double* buf, double* u)
+{
+    const double* R = expm_taylor(H, m, tau, buf);
+    for (int i = threadIdx.x; i < m; i += blockDim.x) u[i] = R[i * LD];
+    __syncthreads();
+}
+
 // u = e^{tau H} e1 (m entries); buffers as for expm_mat.
 __device__ inline void expm_e1(double* H, int m, double tau, double* buf, double* u)
 {
@@ -523,7 +617,7 @@ __device__ inline void check_block(KState* ks, int m, int brk, double gamma, con
     __shared__ double red[4];
     const double tau = taus[c];
     form_h(ks, m, gamma, H, buf);
-    expm_e1(H, m, tau, buf, u);
+    expm_e1_taylor(H, m, tau, buf, u);
     // previous-dimension vector: from the buffer when iterating, recomputed
     // when only evaluating (the basis is unchanged)
     if (m == 1) {
@@ -532,7 +626,7 @@ __device__ inline void check_block(KState* ks, int m, int brk, double gamma, con
         for (int i = threadIdx.x; i < m - 1; i += blockDim.x) up[i] = u_buf[c * MAXM + i];
     } else {
         form_h(ks, m - 1, gamma, H, buf);
-        expm_e1(H, m - 1, tau, buf, up);
+        expm_e1_taylor(H, m - 1, tau, buf, up);
     }
     __syncthreads();
     if (threadIdx.x == 0) {

@@ -15,8 +15,10 @@
 //    Reductions finish in the last block to arrive, in a fixed order.
 //  * Small dense part (Eq. 9 and the estimate of Sec. 3.3.3): one workgroup
 //    per check offset tau forms H_m = (I - Ht_m^-1)/gamma, evaluates
-//    e^{tau H_m} by the [13/13] Pade approximant with scaling and squaring
-//    (Higham 2005), and the error estimate; the last workgroup decides.
+//    e^{tau H_m} by the degree-18 Taylor polynomial with scaling and
+//    squaring (no linear solve), and the error estimate; the last workgroup
+//    decides. The adjoint's augmented exponentials use the [13/13] Pade
+//    approximant with scaling and squaring (Higham 2005).
 //  * Reconstruction (Alg. 1 last line, Alg. 2 snapshot reuse):
 //    y(t_a + tau) = beta V_m e^{tau H_m} e1 + y0 + tau z1 - z2.
 #include "kernels.hpp"
