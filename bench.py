@@ -173,7 +173,7 @@ def main():
                          "the profiling run for the sweep kernels' counters")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for {args.gpus}).",
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 

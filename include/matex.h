@@ -48,7 +48,7 @@ typedef enum {
     MATEX_E_OOM = 3,         /* host or device allocation failed                  */
     MATEX_E_HIP = 4,         /* a HIP runtime call failed                         */
     MATEX_E_NOCONV = 5,      /* estimate still >= tol at m_max (and at h_min)     */
-    MATEX_E_UNSUPPORTED = 6  /* valid request outside what this build implements  */
+    MATEX_E_UNSUPPORTED = 6  /* valid request outside what the library implements */
 } matex_status;
 
 typedef struct matex_factor_s* matex_factor_t;
