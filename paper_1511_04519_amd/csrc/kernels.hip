@@ -645,6 +645,35 @@ __global__ void k_spot_update(int64_t n, int cnt, const int32_t* __restrict__ q,
     }
 }
 
+__global__ __launch_bounds__(256) void k_spot_setup(int64_t n, SpotArgs sa, const double* __restrict__ Z1,
+                                                    const double* __restrict__ Z2, double* z1, double* z2,
+                                                    const double* __restrict__ y,
+                                                    const double* __restrict__ y0, double* v,
+                                                    double* partial, double* taus, TauArgs ta)
+{
+    if (blockIdx.x == 0 && threadIdx.x < ta.n) taus[threadIdx.x] = ta.t[threadIdx.x];
+    __shared__ double red[4];
+    double acc = 0.0;
+    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < n; r += int64_t(gridDim.x) * 256) {
+        double b = z2[r];
+        if (sa.cnt > 0) {
+            double a = z1[r];
+            for (int c = 0; c < sa.cnt; ++c) {
+                const int64_t o = int64_t(sa.q[c]) * n + r;
+                a += sa.coef[c] * Z1[o];
+                b += sa.coef[c] * Z2[o];
+            }
+            z1[r] = a;
+            z2[r] = b;
+        }
+        const double t = y[r] - y0[r] + b;
+        v[r] = t;
+        acc += t * t;
+    }
+    const double s = block_sum(acc, red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
 __global__ void k_set_m(KState* ks, int m)
 {
     ks->m = m;
@@ -1270,6 +1299,13 @@ void launch_adj_jump(int n_rows, const int32_t* rows, const int32_t* ptr, const 
     if (n_rows <= 0) return;
     k_adj_jump<<<(n_rows + 255) / 256, 256, 0, st>>>(n_rows, rows, ptr, pidx, dJdx, n_out, s, cperm, inv_scale,
                                                      lam);
+}
+
+void launch_spot_setup(int64_t n, const SpotArgs& sa, const double* Z1, const double* Z2, double* z1,
+                       double* z2, const double* y, const double* y0, double* v, double* partial,
+                       double* taus, const TauArgs& ta, hipStream_t st)
+{
+    k_spot_setup<<<grid_for(n), 256, 0, st>>>(n, sa, Z1, Z2, z1, z2, y, y0, v, partial, taus, ta);
 }
 
 void launch_setup_v(int64_t n, const double* y, const double* y0, const double* z2, double* v,

@@ -161,6 +161,24 @@ void launch_stamp(int64_t* buf, int64_t idx, hipStream_t st);
 // (Z1, Z2: n x columns, column-major).
 void launch_spot_update(int64_t n, int cnt, const int32_t* q, const double* coef, const double* Z1,
                         const double* Z2, double* z1, double* z2, hipStream_t st);
+// A basis's start in one launch, its small inputs passed by value: the spot
+// update above for at most SPOT_ARGS changed columns (cnt = 0: none), then
+// launch_setup_v's v = y - y0 + z2 (with the updated z2) and its partial
+// sums, and block 0 writes the basis's check offsets to taus. The same
+// arithmetic, in the same order, as the separate launches.
+constexpr int SPOT_ARGS = 16, TAU_ARGS = 8;
+struct SpotArgs {
+    int32_t cnt;
+    int32_t q[SPOT_ARGS];
+    double coef[SPOT_ARGS];
+};
+struct TauArgs {
+    int32_t n;
+    double t[TAU_ARGS];
+};
+void launch_spot_setup(int64_t n, const SpotArgs& sa, const double* Z1, const double* Z2, double* z1,
+                       double* z2, const double* y, const double* y0, double* v, double* partial,
+                       double* taus, const TauArgs& ta, hipStream_t st);
 // Lets a process whose check subset passed but whose full check set did not
 // continue iterating.
 void launch_resume(KState* ks, hipStream_t st);

@@ -1799,12 +1799,19 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
         }
         int64_t t_a = 0;
         size_t k_spot = 0;
+        SpotArgs pend{};   // a spot update applied by the next basis's start
         while (t_a < p->t_end) {
             // new input slope at a transition spot: z1 = G^-1 s, z2 = G^-1 C z1
             if (k_spot < spots.size() && spots[k_spot].t == t_a) {
                 const Segment& sg = spots[k_spot];
                 const int32_t cnt = int32_t(sg.node.size());
-                if (cnt > 0) {
+                if (cnt > 0 && Zc.p && cnt <= SPOT_ARGS) {
+                    pend.cnt = cnt;
+                    for (int32_t c = 0; c < cnt; ++c) {
+                        pend.q[c] = qof.at(sg.node[c]);
+                        pend.coef[c] = sg.dslope[c];
+                    }
+                } else if (cnt > 0) {
                     const size_t need = cnt * (sizeof(int32_t) + sizeof(double)) + 16;
                     if (int64_t(need) > ev_cap) {
                         HIPCHK(hipStreamSynchronize(st));
@@ -1842,10 +1849,21 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
             while (true) {
                 std::vector<double> taus(offs.size());
                 for (size_t q = 0; q < offs.size(); ++q) taus[q] = double(offs[q]) * FS;
-                ring.copy(wk.taus.p, taus.data(), sizeof(double) * taus.size(), st);
+                // the spot update, the start vector and few offsets in one
+                // launch, by value; more offsets through the staging ring
+                TauArgs ta{};
+                if (taus.size() <= size_t(TAU_ARGS)) {
+                    ta.n = int32_t(taus.size());
+                    for (size_t q = 0; q < taus.size(); ++q) ta.t[q] = taus[q];
+                } else {
+                    ring.copy(wk.taus.p, taus.data(), sizeof(double) * taus.size(), st);
+                }
                 g_host_times.stamp(1, st);
-                launch_setup_v(n, y.as<double>(), y0.as<double>(), z2.as<double>(), V,
-                               wk.partial.as<double>(), wk.kst(), st);
+                launch_spot_setup(n, pend, Zc.p ? Zc.as<double>() : nullptr,
+                                  Zc.p ? Zc.as<double>() + n * nq : nullptr, z1.as<double>(), z2.as<double>(),
+                                  y.as<double>(), y0.as<double>(), V, wk.partial.as<double>(),
+                                  wk.taus.as<double>(), ta, st);
+                pend.cnt = 0;   // a retry at a lower shift only sets up again
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
                 ests.clear();
                 h = run_arnoldi(*f, ksh, wk, int(taus.size()), o->tol, o->m_max, hks, st, &launched,
