@@ -463,6 +463,72 @@ __global__ __launch_bounds__(256) void kb_gs_update_dots(int64_t n, int R, const
     }
 }
 
+// The same pass with every basis entry read once: a lane keeps the row's
+// entries of all nv vectors in registers, so the dots of w' take them from
+// there instead of reading the tile again (nv <= NVC). Wavefront wv takes
+// rows wv, wv + 4, ... of the block's share; the lanes' sums over their rows
+// are added across the four wavefronts through LDS. w' is the same as the
+// two-read pass's; the dots differ from it by rounding only (another order).
+constexpr int NVC = 24;
+
+__global__ __launch_bounds__(256) void kb_gs_update_dots_reg(int64_t n, int R, const double* __restrict__ V,
+                                                             int nv, double* w, double* partial,
+                                                             const KState* ks)
+{
+    __shared__ double hs[NVC][64];
+    __shared__ double red[2][NVC + 1][64];
+    const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int idx = threadIdx.x; idx < NVC * 64; idx += 256) {
+        const int i = idx >> 6, q = idx & 63;
+        hs[i][q] = (q < R && i < nv) ? ks[q].h1[i] : 0.0;
+    }
+    __syncthreads();
+    const bool on = r < R && !ks[r < R ? r : 0].done;
+    double acc[NVC + 1];
+#pragma unroll
+    for (int i = 0; i <= NVC; ++i) acc[i] = 0.0;
+    if (on) {
+        const int64_t nR = n * R;
+        for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
+            const double* Vr = V + row * R + r;
+            double v[NVC];
+#pragma unroll
+            for (int i = 0; i < NVC; ++i) v[i] = i < nv ? Vr[int64_t(i) * nR] : 0.0;
+            double wr = w[row * R + r];
+#pragma unroll
+            for (int i = 0; i < NVC; ++i)
+                if (i < nv) wr -= hs[i][r] * v[i];
+            w[row * R + r] = wr;
+#pragma unroll
+            for (int i = 0; i < NVC; ++i)
+                if (i < nv) acc[i] += v[i] * wr;
+            acc[NVC] += wr * wr;
+        }
+    }
+    if (wv >= 2) {
+#pragma unroll
+        for (int i = 0; i <= NVC; ++i) red[wv - 2][i][r] = acc[i];
+    }
+    __syncthreads();
+    if (wv < 2) {
+#pragma unroll
+        for (int i = 0; i <= NVC; ++i) acc[i] += red[wv][i][r];
+    }
+    __syncthreads();
+    if (wv == 1) {
+#pragma unroll
+        for (int i = 0; i <= NVC; ++i) red[0][i][r] = acc[i];
+    }
+    __syncthreads();
+    if (wv == 0 && r < R) {
+        double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
+#pragma unroll
+        for (int i = 0; i < NVC; ++i)
+            if (i < nv) out[i] = acc[i] + red[0][i][r];
+        out[nv] = acc[NVC] + red[0][NVC][r];
+    }
+}
+
 // One block per subtask: sums the nblk partial rows of pass `mode`.
 // mode 0: h1 (nv values). mode 1: h2 and ||w'||^2, then the new Hessenberg
 // column, m, breakdown and the normalisation scale of v_{j+1}. mode 2: the
@@ -697,7 +763,10 @@ void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial
     const dim3 gd(nb, (nv + GS_CHUNK - 1) / GS_CHUNK);
     kb_gs_dots<<<gd, 256, 0, st>>>(n, R, V, nv, w, partial, ks, 0);
     kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 0, ks, nullptr);
-    kb_gs_update_dots<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
+    if (nv <= NVC)
+        kb_gs_update_dots_reg<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
+    else
+        kb_gs_update_dots<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
     kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 1, ks, nullptr);
     kb_gs_axpy<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks, 1);
 }
