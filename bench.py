@@ -39,9 +39,12 @@ HBM_PEAK_GBS = 8000.0
 CONFIG1_LEAF = 32
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_pair_config1.md")
 TRAFFIC_PROFILE64 = os.path.join(ROOT, "profiles", "solve_pair64_config2.md")
-PLAIN_SOURCES = ("kernels.hip", "kernels.hpp", "device_common.hpp", "factor.cpp", "factor.hpp")
+# the sources a profile's counters depend on (matex.cpp builds the sweep
+# schedules and task tables)
+PLAIN_SOURCES = ("kernels.hip", "kernels.hpp", "device_common.hpp", "factor.cpp", "factor.hpp",
+                 "matex.cpp")
 BATCHED_SOURCES = ("batched.hip", "batched.hpp", "kernels.hpp", "device_common.hpp", "factor.cpp",
-                   "factor.hpp")
+                   "factor.hpp", "matex.cpp")
 
 
 def kernel_source_digest(files=PLAIN_SOURCES):

@@ -176,10 +176,10 @@ namespace {
 
 // Blocks the device holds at once at 256 threads each (256 compute units x 8).
 constexpr int64_t RESIDENT_BLOCKS = 2048;
-// Subtree sweeps: the fewest subtree blocks worth a launch (two per compute
+// Subtree sweeps: the fewest subtree blocks worth a launch (one per compute
 // unit), the largest panel a wavefront item takes, the most supernodes and
 // shared LDS doubles packed into one block.
-constexpr int64_t TREE_MIN_BLOCKS = 512;
+constexpr int64_t TREE_MIN_BLOCKS = 256;
 constexpr int32_t TREE_MAX_NODES = 4 * TW;
 constexpr int64_t TREE_MAX_SHARED = 4096;
 // The most subtree blocks one launch takes: all of them resident at once
