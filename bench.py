@@ -3,8 +3,8 @@
 
 One step = one full transient (every step of the hot path: segment planning,
 G solves for the F/P terms of Eq. 6, rational Arnoldi with substitution pairs
-on C + gamma_k G, Gram-Schmidt, the small Pade exponential, reconstruction at
-the output times) of the 2 x 300 x 300 grid (180,000 nodes, 400 pads, 2000
+on C + gamma_k G, Gram-Schmidt, the small matrix exponential, reconstruction
+at the output times) of the 2 x 300 x 300 grid (180,000 nodes, 400 pads, 2000
 pulse sources, 20 ns window, 2001 output times at 512 probe rows), inputs
 resident on the device. Factorisation is set-up and excluded, as the paper
 excludes LU from its transient times.
@@ -15,9 +15,10 @@ bytes per pair over the event-timed mean pair duration, against 8 TB/s.
 cpu_baseline: the CPU oracle, single-threaded, on the first part of the same
 window (a bounded sample), scaled to node-steps/s.
 batched: the 3 x 580 x 580 grid (1,009,200 nodes, 2000 sources in 64
-subtasks of shared pulse timing, 20 ns window) run batched and plain
-(subtasks one after another) at the per-subtask tolerance 1e-10 / 64, with
-the 64-right-hand-side pair's roofline (--no-batched skips it).
+subtasks of shared pulse timing, 20 ns window) run batched at the
+per-subtask tolerance 1e-10 / 64, with the 64-right-hand-side pair's
+roofline (--no-batched skips it); its plain run (subtasks one after another)
+is off by default.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
