@@ -11,7 +11,7 @@ OBJ = os.path.join(HERE, "_build")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 SOURCES = [("kernels.hip", True), ("batched.hip", True), ("matex.cpp", True),
-           ("factor.cpp", False)]
+           ("factor.cpp", False), ("schedule.cpp", False)]
 
 
 def build(verbose: bool = False) -> str:

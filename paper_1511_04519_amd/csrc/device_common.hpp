@@ -74,6 +74,27 @@ __device__ inline double block_sum(double v, double* red)
     return r;
 }
 
+// The done flag of a Krylov process, read once per block. Another stream (the
+// check that decides the process) may set the flag while a block starts, so
+// wavefronts reading it themselves can disagree: some return and the rest
+// then work on LDS that the returned ones were to fill. Thread 0 reads it,
+// the block shares it through LDS; the caller returns on a nonzero value
+// after the barrier that follows (block_done below has its own). The flag
+// word must not be written again before that barrier.
+__device__ inline void done_stage(const int32_t* done, int32_t* flag)
+{
+    if (threadIdx.x == 0)
+        *flag = done ? __hip_atomic_load(done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+}
+
+__device__ inline bool block_done(const int32_t* done)
+{
+    __shared__ int32_t flag;
+    done_stage(done, &flag);
+    __syncthreads();
+    return flag != 0;
+}
+
 // Marks this block done among `total` cooperating blocks; returns true in
 // exactly one of them (the last to arrive), which also resets the counter.
 __device__ inline bool last_of(int32_t* counter, int32_t total)

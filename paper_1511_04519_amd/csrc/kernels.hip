@@ -58,7 +58,8 @@ __global__ __launch_bounds__(256) void k_forward(const PTask* __restrict__ tasks
 {
     constexpr int KS = 256 / ROWS;
     const PTask t = tasks[blockIdx.x];
-    if (done && *done) return;
+    __shared__ int32_t quit;
+    done_stage(done, &quit);
     extern __shared__ double lds[];
     double* bt = lds;
     double* part = lds + lds_nc;
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(256) void k_forward(const PTask* __restrict__ tasks
         }
     }
     __syncthreads();
+    if (quit) return;
     double acc = 0.0;
     for (int k = ks; k < kmax; k += PF * KS) {
         double nx[PF];
@@ -153,7 +155,8 @@ __global__ __launch_bounds__(256) void k_backward(const PTask* __restrict__ task
                                                   const int32_t* done)
 {
     const PTask t = tasks[blockIdx.x];
-    if (done && *done) return;
+    __shared__ int32_t quit;
+    done_stage(done, &quit);
     extern __shared__ double g[];
     const int q = threadIdx.x % LPC;
     const int col = t.first + threadIdx.x / LPC;
@@ -180,6 +183,7 @@ __global__ __launch_bounds__(256) void k_backward(const PTask* __restrict__ task
             g[k] = k < t.nc ? y[t.c0 + k] : -x[rows[t.aux + k - t.nc]];
     }
     __syncthreads();
+    if (quit) return;
     double acc = 0.0;
     for (int k = col + q; k < kend; k += PF * LPC) {
         double nx[PF];
@@ -302,14 +306,17 @@ __global__ __launch_bounds__(64 * TW) void k_forward_tree(TreeTasks tr, const do
                                                          const int32_t* done)
 {
     const int s0 = tr.fblk[blockIdx.x], s1 = tr.fblk[blockIdx.x + 1];
-    if (done && *done) return;
+    __shared__ int32_t quit;
+    done_stage(done, &quit);
     extern __shared__ double lds[];
     TItem* items = reinterpret_cast<TItem*>(lds);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double* bt = lds + tr.item_doubles + wv * tr.ws;
     double* sh = lds + tr.item_doubles + TW * tr.ws;
+    // every wavefront copies its share of the items: none may return before
     tree_copy_items(tr.fitems + int64_t(s0) * TW, (s1 - s0) * TW, items);
     __syncthreads();
+    if (quit) return;
     auto item = [&](int s) -> const TItem& { return items[(s - s0) * TW + wv]; };
     FwdPre pa, pb;
     fwd_tree_load(item(s0), lane, tr.fdesc, int64_t(s0) * TW + wv, W, b, scale, pa);
@@ -404,14 +411,17 @@ __global__ __launch_bounds__(64 * TW) void k_backward_tree(TreeTasks tr, const d
                                                           const int32_t* done)
 {
     const int s0 = tr.bblk[blockIdx.x], s1 = tr.bblk[blockIdx.x + 1];
-    if (done && *done) return;
+    __shared__ int32_t quit;
+    done_stage(done, &quit);
     extern __shared__ double lds[];
     TItem* items = reinterpret_cast<TItem*>(lds);
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     double* g = lds + tr.item_doubles + wv * tr.ws;
     double* sh = lds + tr.item_doubles + TW * tr.ws;
+    // every wavefront copies its share of the items: none may return before
     tree_copy_items(tr.bitems + int64_t(s0) * TW, (s1 - s0) * TW, items);
     __syncthreads();
+    if (quit) return;
     auto item = [&](int s) -> const TItem& { return items[(s - s0) * TW + wv]; };
     BwdPre pa, pb;
     bwd_tree_load(item(s0), lane, tr.trow, W, y, x, pa);
@@ -491,7 +501,8 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const double*
                                                         const double* __restrict__ w,
                                                         double* partial, const int32_t* done)
 {
-    if (done && *done) return;
+    __shared__ int32_t quit;
+    done_stage(done, &quit);
     __shared__ double wl[GS_THREADS];
     double acc[GS_VPW];
 #pragma unroll
@@ -500,6 +511,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_dots(int64_t n, const double*
         const int64_t r = base + threadIdx.x;
         wl[threadIdx.x] = r < n ? w[r] : 0.0;
         __syncthreads();
+        if (quit) return;
         gs_tile_dots(V, ldv, nv, false, base, int(min<int64_t>(GS_THREADS, n - base)), wl, acc);
         __syncthreads();
     }
@@ -515,10 +527,12 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(int64_t n, const doubl
                                                           const double* partial_in, double* partial_out,
                                                           KState* ks, const int32_t* done)
 {
-    if (done && *done) return;
+    __shared__ int32_t quit;
+    done_stage(done, &quit);
     __shared__ double h[NVMAX + 1];
     __shared__ double wl[GS_THREADS];
     reduce_partials_waves<GS_WAVES>(partial_in, NVMAX + 1, gridDim.x, nv, h);
+    if (quit) return;
     if (blockIdx.x == 0 && threadIdx.x < nv) ks->h1[threadIdx.x] = h[threadIdx.x];
     double acc[GS_VPW];
 #pragma unroll
@@ -554,13 +568,15 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, 
                                                    const double* partial_in, KState* ks,
                                                    const int32_t* done, int32_t ticket)
 {
-    if (done && *done) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) publish_ticket(ks, ticket);
-        return;
-    }
+    __shared__ int32_t quit;
+    done_stage(done, &quit);
     __shared__ double h[NVMAX + 1];
     __shared__ double sc;
     reduce_partials_waves<GS_WAVES>(partial_in, NVMAX + 1, gridDim.x, nv + 1, h);
+    if (quit) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) publish_ticket(ks, ticket);
+        return;
+    }
     if (threadIdx.x == 0) {
         double s2 = 0.0, hmax = 0.0;
         for (int i = 0; i < nv; ++i) {

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "schedule.hpp"
+
 namespace matex {
 
 constexpr int MAXM = 32;          // largest Krylov dimension supported
@@ -25,17 +27,6 @@ struct DevSym {
     const int32_t* relidx;
 };
 
-// One task of a level sweep: a block (panels with more than 64 rows) or a
-// wavefront (the whole supernode, panels with at most 64 rows).
-struct PTask {
-    int64_t w;       // panel offset of the supernode
-    int64_t aux;     // forward: the supernode's update slots; backward: its off-row list
-    int32_t c0, nc, nr;
-    int32_t first;   // forward: first panel row of the task; backward: first column
-    int32_t pos;     // forward: contributor list index of the supernode's panel position 0
-    int32_t pad_;
-};
-
 // One level's task list and its kernel: the forward sweep's panel rows per
 // block (4, 16 or 64) or the backward sweep's lanes per column (16 or 64).
 struct LevelTasks {
@@ -53,22 +44,6 @@ struct LevelTasks {
     // backward, the source of g at panel row first + i: x index r >= 0
     // (an off row, negated), -1 - (y index) for an own column, INT32_MIN none.
     const int32_t* gsrc;
-};
-
-// Subtree sweeps of the bottom levels: one block of TW wavefronts per
-// subtree (or per few small subtrees), one wavefront per work item.
-constexpr int TW = 8;
-constexpr int TREE_MAX_NR = 256;   // largest panel (rows) a subtree item takes
-
-struct TItem {
-    int64_t w;        // panel offset of the supernode
-    int64_t aux;      // forward: global update slots (used by subtree roots);
-                      // backward: offset of the off-row list (trow)
-    int32_t c0, nc, nr;
-    int32_t first, last;   // forward: panel rows [first, last); backward: columns
-    int32_t pos;      // forward: contributor list index of panel position 0
-    int32_t lds_u;    // forward: LDS offset of the update slots, -1 for a subtree root
-    int32_t lds_x;    // LDS offset of the supernode's x
 };
 
 // Steps of TW items (nr = 0: idle); block b runs forward steps

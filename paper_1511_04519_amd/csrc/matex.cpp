@@ -28,6 +28,7 @@
 #include "batched.hpp"
 #include "factor.hpp"
 #include "kernels.hpp"
+#include "schedule.hpp"
 
 using namespace matex;
 
@@ -176,205 +177,21 @@ namespace {
 
 // Blocks the device holds at once at 256 threads each (256 compute units x 8).
 constexpr int64_t RESIDENT_BLOCKS = 2048;
-// Subtree sweeps: the fewest subtree blocks worth a launch (one per compute
-// unit), the largest panel a wavefront item takes, the most supernodes and
-// shared LDS doubles packed into one block.
-constexpr int64_t TREE_MIN_BLOCKS = 256;
-constexpr int32_t TREE_MAX_NODES = 4 * TW;
-constexpr int64_t TREE_MAX_SHARED = 4096;
-// The most subtree blocks one launch takes: all of them resident at once
-// (two per compute unit). Plain transients whose subtree sweeps ran in
-// several rounds of blocks stopped twice with a memory fault whose cause is
-// not found, so larger grids sweep those levels with the level kernels.
-constexpr int64_t TREE_MAX_BLOCKS = 512;
 
-// Subtree schedule of the bottom `limit` levels at most (limit < 0: none, 0:
-// automatic): the most levels whose supernodes all fit a wavefront item
-// (nc <= 64, nr <= TREE_MAX_NR, at most two children's slots adding into a
-// panel position) that still leave TREE_MIN_BLOCKS subtrees,
-// or every such level on a grid with fewer subtrees than that.
-void build_tree(matex_factor_s& F, const std::vector<int32_t>& pos_base, const std::vector<int32_t>& cptr,
-                const std::vector<int32_t>& cidx, int32_t limit)
+// Uploads the subtree schedule of the bottom levels (schedule.cpp).
+void build_tree(matex_factor_s& F, const Contrib& C, int32_t limit)
 {
-    const Symbolic& s = F.sym;
-    const int L = s.n_levels;
-    const int32_t nsn = int32_t(s.sn.size());
-    int E = 0;
-    for (; E < L && limit >= 0; ++E) {
-        bool ok = true;
-        for (int32_t k : s.level_sn[E]) {
-            const Supernode& q = s.sn[k];
-            ok = ok && q.nc <= 64 && q.nr <= TREE_MAX_NR;
-            for (int32_t p = 0; p < q.nr && ok; ++p) ok = cptr[pos_base[k] + p + 1] - cptr[pos_base[k] + p] <= 2;
-        }
-        if (!ok) break;
-    }
-    if (limit > 0) E = std::min(E, int(limit));
-    auto is_root = [&](int32_t k, int S) {
-        const int32_t par = s.sn[k].parent;
-        return s.sn[k].level < S && (par < 0 || s.sn[par].level >= S);
-    };
-    auto n_roots = [&](int S) {
-        int64_t r = 0;
-        for (int32_t k = 0; k < nsn; ++k) r += is_root(k, S) ? 1 : 0;
-        return r;
-    };
-    // subtree of each root: its supernodes and shared LDS need
-    std::vector<int32_t> stack, nodes;
-    auto subtree = [&](int32_t root) {
-        nodes.clear();
-        stack.assign(1, root);
-        while (!stack.empty()) {
-            const int32_t c = stack.back();
-            stack.pop_back();
-            nodes.push_back(c);
-            for (int32_t cp = s.child_ptr[c]; cp < s.child_ptr[c + 1]; ++cp) stack.push_back(s.child_idx[cp]);
-        }
-    };
-    auto shared_need = [&](int32_t root) {
-        subtree(root);
-        int64_t d = 0;
-        for (int32_t c : nodes) d += s.sn[c].nc + (c == root ? 0 : s.sn[c].nr - s.sn[c].nc);
-        return d;
-    };
-    int S = 0;
-    if (E > 0) {
-        const int64_t r1 = n_roots(1);
-        for (int k = 1; k <= E; ++k)
-            if (r1 < TREE_MIN_BLOCKS || n_roots(k) >= TREE_MIN_BLOCKS) S = k;
-        // every subtree must fit one block's shared LDS
-        while (S > 0) {
-            bool fits = true;
-            for (int32_t k = 0; k < nsn && fits; ++k)
-                if (is_root(k, S)) fits = shared_need(k) <= TREE_MAX_SHARED;
-            if (fits) break;
-            --S;
-        }
-    }
+    TreeHost h = build_tree_host(F.sym, C, limit);
     F.tree = TreeTasks{};
-    F.tree.n_levels = S;
-    if (S == 0) return;
-    // pack roots into blocks; LDS offsets of each block's supernodes
-    std::vector<int32_t> block_of(nsn, -1), lds_u(nsn, -1), lds_x(nsn, -1);
-    std::vector<std::vector<int32_t>> blocks;
-    std::vector<int64_t> bshared;
-    int64_t cur_nodes = 0, cur_shared = 0;
-    for (int32_t lv = S - 1; lv >= 0; --lv)
-        for (int32_t k : s.level_sn[lv]) {
-            if (!is_root(k, S)) continue;
-            const int64_t need = shared_need(k);   // fills nodes
-            if (blocks.empty() || cur_nodes + int64_t(nodes.size()) > TREE_MAX_NODES ||
-                cur_shared + need > TREE_MAX_SHARED) {
-                blocks.emplace_back();
-                bshared.push_back(0);
-                cur_nodes = cur_shared = 0;
-            }
-            const int32_t bi = int32_t(blocks.size()) - 1;
-            for (int32_t c : nodes) {
-                block_of[c] = bi;
-                blocks.back().push_back(c);
-                lds_u[c] = c == k ? -1 : 0;   // placed below
-            }
-            cur_nodes += int64_t(nodes.size());
-            cur_shared += need;
-            bshared.back() = cur_shared;
-        }
-    if (int64_t(blocks.size()) > TREE_MAX_BLOCKS) {
-        F.tree = TreeTasks{};
-        return;
-    }
-    int32_t max_nr = 64;
-    for (size_t bi = 0; bi < blocks.size(); ++bi) {
-        int32_t off = 0;
-        for (int32_t c : blocks[bi])
-            if (lds_u[c] >= 0) { lds_u[c] = off; off += s.sn[c].nr - s.sn[c].nc; }
-        for (int32_t c : blocks[bi]) { lds_x[c] = off; off += s.sn[c].nc; }
-        for (int32_t c : blocks[bi]) max_nr = std::max(max_nr, s.sn[c].nr);
-    }
-    // LDS offsets of contributions and off rows
-    std::vector<int32_t> trow(s.rows.size() + 1, 0);   // one spare: clamped reads stay inside
-    std::vector<int32_t> owner(s.n);
-    for (int32_t k = 0; k < nsn; ++k)
-        for (int32_t c = 0; c < s.sn[k].nc; ++c) owner[s.sn[k].c0 + c] = k;
-    std::vector<int32_t> slot_lds(std::max<int64_t>(1, s.n_upd), -1);
-    for (int32_t k = 0; k < nsn; ++k)
-        if (block_of[k] >= 0 && lds_u[k] >= 0)
-            for (int32_t t = 0; t < s.sn[k].nr - s.sn[k].nc; ++t) slot_lds[s.sn[k].u + t] = lds_u[k] + t;
-    for (int32_t k = 0; k < nsn; ++k) {
-        if (block_of[k] < 0) continue;
-        const Supernode& q = s.sn[k];
-        for (int32_t t = 0; t < q.nr - q.nc; ++t) {
-            const int32_t r = s.rows[q.roff + t], a = owner[r];
-            trow[q.roff + t] = block_of[a] == block_of[k] ? -1 - (lds_x[a] + r - s.sn[a].c0) : r;
-        }
-    }
-    // steps: forward items are 64-row slabs, children's levels first;
-    // backward items column groups with at most 16 rows per lane, root first
-    std::vector<TItem> fi, bi_;
-    std::vector<int32_t> fblk{0}, bblk{0};
-    std::vector<TItem> lvl;
-    auto flush = [&](std::vector<TItem>& out) {
-        for (size_t i = 0; i < lvl.size(); i += TW)
-            for (size_t w = i; w < i + TW; ++w) out.push_back(w < lvl.size() ? lvl[w] : TItem{});
-        lvl.clear();
-    };
-    for (const auto& blk : blocks) {
-        for (int32_t lv = 0; lv < S; ++lv) {
-            for (int32_t c : blk) {
-                const Supernode& q = s.sn[c];
-                if (q.level != lv) continue;
-                for (int32_t r = 0; r < q.nr; r += 64)
-                    lvl.push_back({q.w, q.u, q.c0, q.nc, q.nr, r, std::min(q.nr, r + 64), pos_base[c],
-                                   lds_u[c], lds_x[c]});
-            }
-            flush(fi);
-        }
-        fblk.push_back(int32_t(fi.size() / TW));
-        for (int32_t lv = S - 1; lv >= 0; --lv) {
-            for (int32_t c : blk) {
-                const Supernode& q = s.sn[c];
-                if (q.level != lv) continue;
-                int32_t lpc = 1;
-                while (lpc < 64 && int64_t(lpc) * 16 < q.nr) lpc *= 2;
-                const int32_t cpi = 64 / lpc;
-                for (int32_t c1 = 0; c1 < q.nc; c1 += cpi)
-                    lvl.push_back({q.w, q.roff, q.c0, q.nc, q.nr, c1, std::min(q.nc, c1 + cpi), 0,
-                                   lds_u[c], lds_x[c]});
-            }
-            flush(bi_);
-        }
-        bblk.push_back(int32_t(bi_.size() / TW));
-    }
-    // per forward item and lane: the LDS slots adding into its btilde column
-    // and its panel row
-    auto desc = [&](const TItem& t, int32_t p) {
-        int32_t d = 0, sh = 0;
-        if (p >= t.nr) return 0;
-        const int64_t base = t.pos + p;
-        for (int32_t j = cptr[base]; j < cptr[base + 1]; ++j, sh += 16) d |= (slot_lds[cidx[j]] + 1) << sh;
-        return d;
-    };
-    std::vector<int2> fd(fi.size() * 64, make_int2(0, 0));
-    for (size_t i = 0; i < fi.size(); ++i) {
-        const TItem& t = fi[i];
-        if (t.nr == 0) continue;
-        for (int32_t lane = 0; lane < 64; ++lane) {
-            const int32_t row = t.first + lane;
-            fd[i * 64 + lane] = make_int2(lane < t.nc ? desc(t, lane) : 0,
-                                          row >= t.nc && row < t.last ? desc(t, row) : 0);
-        }
-    }
-    int64_t shared = 0, steps = 0;
-    for (int64_t v : bshared) shared = std::max(shared, v);
-    for (size_t b = 0; b + 1 < fblk.size(); ++b)
-        steps = std::max<int64_t>(steps, std::max(fblk[b + 1] - fblk[b], bblk[b + 1] - bblk[b]));
-    F.d_tree_fdesc = upload(fd);
-    F.d_tree_f = upload(fi);
-    F.d_tree_b = upload(bi_);
-    F.d_tree_fblk = upload(fblk);
-    F.d_tree_bblk = upload(bblk);
-
-    F.d_tree_trow = upload(trow);
+    F.tree.n_levels = h.n_levels;
+    if (h.n_levels == 0) return;
+    static_assert(sizeof(I2) == sizeof(int2), "I2 is read as int2");
+    F.d_tree_fdesc = upload(h.fdesc);
+    F.d_tree_f = upload(h.fitems);
+    F.d_tree_b = upload(h.bitems);
+    F.d_tree_fblk = upload(h.fblk);
+    F.d_tree_bblk = upload(h.bblk);
+    F.d_tree_trow = upload(h.trow);
     TreeTasks& T = F.tree;
     T.fitems = F.d_tree_f.as<TItem>();
     T.bitems = F.d_tree_b.as<TItem>();
@@ -382,10 +199,10 @@ void build_tree(matex_factor_s& F, const std::vector<int32_t>& pos_base, const s
     T.bblk = F.d_tree_bblk.as<int32_t>();
     T.fdesc = F.d_tree_fdesc.as<int2>();
     T.trow = F.d_tree_trow.as<int32_t>();
-    T.n_blocks = int32_t(blocks.size());
-    T.ws = (max_nr + 15) / 16 * 16;
-    T.item_doubles = int32_t(steps * TW * int64_t(sizeof(TItem)) / 8);
-    T.lds_doubles = int32_t(T.item_doubles + TW * T.ws + shared);
+    T.n_blocks = h.n_blocks;
+    T.ws = h.ws;
+    T.item_doubles = h.item_doubles;
+    T.lds_doubles = h.lds_doubles;
 }
 
 void build_tasks(matex_factor_s& F, int32_t subtree_limit)
@@ -394,28 +211,11 @@ void build_tasks(matex_factor_s& F, int32_t subtree_limit)
     const int L = s.n_levels;
     // every panel position's contributing child update slots, in child order
     // (the inverse of relidx), shared by the one-vector and batched sweeps
-    std::vector<int32_t> pos_base(s.sn.size()), cptr{0}, cidx;
-    {
-        std::vector<std::vector<int32_t>> contrib;
-        for (size_t k = 0; k < s.sn.size(); ++k) {
-            const Supernode& q = s.sn[k];
-            contrib.assign(q.nr, {});
-            for (int32_t cp = s.child_ptr[k]; cp < s.child_ptr[k + 1]; ++cp) {
-                const Supernode& c = s.sn[s.child_idx[cp]];
-                for (int32_t t = 0; t < c.nr - c.nc; ++t)
-                    contrib[s.relidx[c.u + t]].push_back(int32_t(c.u + t));
-            }
-            pos_base[k] = int32_t(cptr.size()) - 1;
-            for (int32_t p = 0; p < q.nr; ++p) {
-                cidx.insert(cidx.end(), contrib[p].begin(), contrib[p].end());
-                cptr.push_back(int32_t(cidx.size()));
-            }
-        }
-        if (cidx.empty()) cidx.push_back(0);
-        F.d_b_pos = upload(pos_base); F.d_b_cptr = upload(cptr); F.d_b_cidx = upload(cidx);
-        F.bas = BatchAssembly{F.d_b_pos.as<int32_t>(), F.d_b_cptr.as<int32_t>(), F.d_b_cidx.as<int32_t>()};
-    }
-    build_tree(F, pos_base, cptr, cidx, subtree_limit);
+    const Contrib C = contributions(s);
+    const std::vector<int32_t>&pos_base = C.pos_base, &cptr = C.cptr, &cidx = C.cidx;
+    F.d_b_pos = upload(pos_base); F.d_b_cptr = upload(cptr); F.d_b_cidx = upload(cidx);
+    F.bas = BatchAssembly{F.d_b_pos.as<int32_t>(), F.d_b_cptr.as<int32_t>(), F.d_b_cidx.as<int32_t>()};
+    build_tree(F, C, subtree_limit);
     const int32_t S = F.tree.n_levels;
     // levels above: the forward sweep takes 16 panel rows per block, 64 when
     // that many blocks would not all be resident at once, 4 on levels with
