@@ -1,26 +1,39 @@
 #!/usr/bin/env python
-"""Benchmark of the R-MATEX transient on one MI355X.
+"""Benchmark of the R-MATEX transient on one MI355X: batched vs plain.
 
-One step = one full transient (every step of the hot path: segment planning,
-G solves for the F/P terms of Eq. 6, rational Arnoldi with substitution pairs
+Workload (one step): the 3 x 580 x 580 grid (1,009,200 nodes, 1521 pads,
+2000 pulse sources in 64 subtasks of shared pulse timing, 20 ns window, 2001
+output times at 512 probe rows), every step of the hot path (segment
+planning, the F/P terms of Eq. 6, rational Arnoldi with substitution pairs
 on C + gamma_k G, Gram-Schmidt, the small matrix exponential, reconstruction
-at the output times) of the 2 x 300 x 300 grid (180,000 nodes, 400 pads, 2000
-pulse sources, 20 ns window, 2001 output times at 512 probe rows), inputs
-resident on the device. Factorisation is set-up and excluded, as the paper
-excludes LU from its transient times.
+at the output times, superposition of the subtasks), inputs resident on the
+device. Tolerance 1e-10 V per basis and subtask count (1e-10 / 64).
+Factorisation is set-up and excluded, as the paper excludes LU from its
+transient times.
 
-metric value: node-steps/s = n * N_out / transient seconds.
-roofline: the substitution-pair sweeps (the dominant kernels), algorithmic
-bytes per pair over the event-timed mean pair duration, against 8 TB/s.
-cpu_baseline: the CPU oracle, single-threaded, on the first part of the same
-window (a bounded sample), scaled to node-steps/s.
-batched: the 3 x 580 x 580 grid (1,009,200 nodes, 2000 sources in 64
-subtasks of shared pulse timing, 20 ns window) run batched at the
-per-subtask tolerance 1e-10 / 64, with the 64-right-hand-side pair's
-roofline (--no-batched skips it); its plain run (subtasks one after another)
-is off by default.
+value: node-steps/s of the batched mode (all 64 subtasks through
+64-right-hand-side substitution pairs) = n * N_out / transient seconds.
+plain: the same workload with the subtasks one after another (one-vector
+pairs), run once; speedup = plain seconds / batched seconds (same steps).
+parity: both modes against the oracle's stored windows of this workload
+([0, 300] ps from t = 0; [0.9, 1.0] ns from a quasi-static start).
+roofline: the 64-right-hand-side substitution pair (the batched transient's
+dominant kernels), algorithmic bytes per pair (each nonzero of L once per
+sweep, 8 B, plus 4 x 8 B per row and right-hand side) over the event-timed
+mean pair duration, against 8 TB/s; traffic from the committed rocprofv3
+counter summary when it was taken on the current kernel sources.
+cpu_baseline: the CPU oracle on a bounded sample of the same workload (all
+64 subtasks over its first 50 ps), one core and all cores (subtasks in
+threads), and the oracle's trapezoidal rule at a fixed 10 ps step (the
+paper's comparator) on the same window; the oracle's factors (those of the
+trapezoidal rule too) are built in threads while the GPU runs and are
+excluded, as on the GPU.
+config1: context, the 2 x 300 x 300 grid (180k nodes) in plain mode, run
+once, with its oracle windows and its one-vector pair (a cache-resident
+factor: 130 MB against the 256 MB Infinity Cache).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --pairs-only   (the profiling run of the sweep kernels)
 """
 import argparse
 import json
@@ -33,22 +46,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Nested-dissection leaf size of the 180k-node grid's factor: leaves of up to
-# 32 nodes give 13 levels (4 of them in the subtree sweeps) instead of 14, one
-# level launch fewer per sweep; measured 146 us per pair and 14.1 s per
-# transient against 149 us and 14.4 s with 16-node leaves.
+METRIC = "SpTRSV HBM GB/s + transient node·steps/s, batched vs plain, at 1e-9 rel err"
+# Nested-dissection leaf size of the 180k-node grid's factor (13 levels
+# instead of 14 with 16-node leaves; 145 against 149 us per pair).
 CONFIG1_LEAF = 32
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "solve_pair_config1.md")
+CPU_WINDOW_PS = 50
 TRAFFIC_PROFILE64 = os.path.join(ROOT, "profiles", "solve_pair64_config2.md")
-# the sources a profile's counters depend on (matex.cpp builds the sweep
-# schedules and task tables)
+TRAFFIC_PROFILE1 = os.path.join(ROOT, "profiles", "solve_pair_config1.md")
+# the sources a profile's counters depend on (matex.cpp and schedule.cpp
+# build the sweep schedules and task tables)
 PLAIN_SOURCES = ("kernels.hip", "kernels.hpp", "device_common.hpp", "factor.cpp", "factor.hpp",
-                 "matex.cpp")
+                 "schedule.cpp", "schedule.hpp", "matex.cpp")
 BATCHED_SOURCES = ("batched.hip", "batched.hpp", "kernels.hpp", "device_common.hpp", "factor.cpp",
-                   "factor.hpp", "matex.cpp")
+                   "factor.hpp", "schedule.cpp", "schedule.hpp", "matex.cpp")
 
 
-def kernel_source_digest(files=PLAIN_SOURCES):
+def kernel_source_digest(files):
     import hashlib
     h = hashlib.sha256()
     for f in files:
@@ -56,9 +69,11 @@ def kernel_source_digest(files=PLAIN_SOURCES):
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path=TRAFFIC_PROFILE, files=PLAIN_SOURCES):
+def measured_traffic(path, files):
     """HBM bytes per substitution pair from a committed rocprofv3 counter
     summary, if it was taken on the current kernel sources (else None)."""
+    if path is None:
+        return None
     try:
         txt = open(path).read()
     except OSError:
@@ -68,116 +83,227 @@ def measured_traffic(path=TRAFFIC_PROFILE, files=PLAIN_SOURCES):
     if fields.get("kernel-sources", "").strip() != kernel_source_digest(files):
         return None
     return float(fields["traffic-bytes-per-pair"])
-METRIC = "SpTRSV HBM GB/s + transient node·steps/s, batched vs plain, at 1e-9 rel err"
 
 
-def cpu_baseline(prob, tol, window_fs, threads=1):
-    """Oracle R-MATEX on [0, window_fs] of the same workload, in a child
-    process pinned to `threads` BLAS threads; returns a dict."""
-    code = f"""
-import os, sys, time, json
-sys.path.insert(0, {ROOT!r})
-import numpy as np
-from paper_1511_04519_amd import instances as I
-from oracle import rmatex as RM
-p = I.config1()
-T = {int(window_fs)}
-q = I.Problem('head', p.netlist, p.sources, T, p.t_out[p.t_out <= T], p.probe)
-t0 = time.time(); s = RM.RMatex(p.netlist, p.gamma); tf = time.time() - t0
-t0 = time.time(); s.transient(q, tol={tol!r}, m_max=p.m_max); tt = time.time() - t0
-print(json.dumps(dict(factor_s=tf, transient_s=tt, n=p.netlist.n, n_out=int(q.t_out.size),
-                      bases=s.stats.bases, pairs=s.stats.solve_pairs_M + s.stats.solve_pairs_G)))
-"""
-    env = dict(os.environ, OPENBLAS_NUM_THREADS=str(threads), OMP_NUM_THREADS=str(threads),
-               MKL_NUM_THREADS=str(threads))
-    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env,
-                         timeout=900)
-    if out.returncode != 0:
-        raise RuntimeError(out.stderr[-2000:])
-    d = json.loads(out.stdout.strip().splitlines()[-1])
-    d["value"] = d["n"] * d["n_out"] / d["transient_s"]
-    return d
+def host_cpu():
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
-def batched_vs_plain(window_ps=0, with_plain=False):
-    """The 64-subtask workload batched and plain, and the 64-RHS pair."""
+# ------------------------------------------------------------ CPU baseline
+
+def cpu_child(window_ps, cores):
+    """Runs in a child process: the oracle on the first window_ps of the
+    1M-node workload. Prints one JSON line after each phase; waits for a line
+    on stdin before the all-core and trapezoidal phases (the GPU's timed
+    region is over by then)."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    from oracle import circuit as OC
+    from oracle import reference as OR
+    from oracle import rmatex as RM
+    from paper_1511_04519_amd import instances as I
+
+    p = I.config2()
+    T = window_ps * I.PS
+    q = I.Problem("sample", p.netlist, p.sources, T, p.t_out[p.t_out <= T], p.probe)
+    groups = OC.subtasks(p.sources)
+    tol = 1e-10 / len(groups)
+    # the oracle's factors (5 shifts and G), built side by side: the C
+    # factorisation runs outside the interpreter lock
+    t0 = time.time()
+    s = RM.RMatex.__new__(RM.RMatex)
+    s.nl, s.n = p.netlist, p.netlist.n
+    s.gammas = [p.gamma * 10.0 ** (-k) for k in range(5)]
+    s.c = np.asarray(p.netlist.c_node, dtype=np.float64)
+    rp, ci, gv = OC.assemble_G(p.netlist)
+    s.G = (rp, ci, gv)
+    h_tr = 10 * I.PS
+    with ThreadPoolExecutor(7) as ex:
+        fg = ex.submit(OC.Cholesky, rp, ci, gv)
+        fm = [ex.submit(OC.Cholesky, rp, ci, OC.csr_add_diag(rp, ci, gv, s.c, alpha=g)) for g in s.gammas]
+        ft = ex.submit(OC.Cholesky, rp, ci, OC.csr_add_diag(rp, ci, gv, s.c / (h_tr * OC.FS), alpha=0.5))
+        s.Gf = fg.result()
+        s.Mfs = [f.result() for f in fm]
+        tr_facs = {"G": s.Gf, h_tr: ft.result()}
+    s.stats = RM.Stats()
+    s.trace = False
+    factor_s = time.time() - t0
+    n_out = int(q.t_out.size)
+
+    def run(idx_list):
+        for idx in idx_list:
+            s.subtask(p.sources, idx, T, q.t_out, q.probe, tol, p.m_max, 1.0, 1, 1.0, 0)
+
+    t0 = time.time()
+    run(groups)
+    one = time.time() - t0
+    st = s.stats
+    print(json.dumps({"phase": "one", "factor_s": factor_s, "transient_s": one, "n": s.n, "n_out": n_out,
+                      "bases": st.bases, "pairs": st.solve_pairs_M + st.solve_pairs_G,
+                      "subtasks": len(groups)}), flush=True)
+    sys.stdin.readline()
+    # all cores: the subtasks dealt to `cores` threads (the sparse solves and
+    # the vector operations release the interpreter lock); time = the slowest
+    shares = [groups[k::cores] for k in range(cores)]
+    t0 = time.time()
+    with ThreadPoolExecutor(cores) as ex:
+        list(ex.map(run, shares))
+    allc = time.time() - t0
+    print(json.dumps({"phase": "all", "transient_s": allc, "cores": cores}), flush=True)
+    t0 = time.time()
+    _, _, pairs_tr = OR.trapezoidal(q, h_tr, align=False, factors=tr_facs)
+    tr = time.time() - t0
+    print(json.dumps({"phase": "tr", "seconds": tr, "pairs": pairs_tr}), flush=True)
+
+
+class CpuBaseline:
+    def __init__(self, window_ps, cores):
+        self.window_ps, self.cores = window_ps, cores
+        self.p = subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-child",
+                                   str(window_ps), str(cores)], stdin=subprocess.PIPE,
+                                  stdout=subprocess.PIPE, text=True,
+                                  env=dict(os.environ, OPENBLAS_NUM_THREADS="1", OMP_NUM_THREADS="1",
+                                           MKL_NUM_THREADS="1"))
+
+    def _line(self):
+        line = self.p.stdout.readline()
+        if not line:
+            raise RuntimeError("CPU baseline child ended early")
+        return json.loads(line)
+
+    def finish(self):
+        one = self._line()
+        self.p.stdin.write("go\n")
+        self.p.stdin.flush()
+        allc = self._line()
+        tr = self._line()
+        self.p.wait(timeout=60)
+        model, ncpu = host_cpu()
+        work = one["n"] * one["n_out"]
+        return {
+            "value": work / one["transient_s"], "unit": "node*steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle R-MATEX on the same 1M-node workload and tolerance, all {one['subtasks']} "
+                       f"subtasks over [0, {self.window_ps} ps] ({one['n_out']} output times, "
+                       f"{one['bases']} bases, {one['pairs']} solve pairs), {one['transient_s']:.1f} s on "
+                       f"one core; its factors ({one['factor_s']:.0f} s, built in threads) excluded"),
+            "all_cores": {"value": work / allc["transient_s"], "cores": allc["cores"],
+                          "seconds": allc["transient_s"],
+                          "how": "subtasks dealt to threads, time of the slowest (the paper's max over nodes)"},
+            "oracle_tr_10ps": {"value": work / tr["seconds"], "seconds": tr["seconds"],
+                               "pairs": tr["pairs"], "cores": 1,
+                               "how": "Eq. 2 at a fixed 10 ps step (the paper's comparator), same window"},
+            "host": {"nproc": ncpu, "model": model},
+        }
+
+
+# ------------------------------------------------------------------- GPU
+
+def pair_roofline(F, nrhs, reps, profile, sources):
+    from paper_1511_04519_amd import matex as M
+    sec, byt = M.matex_time_solves(F, which=0, reps=reps, nrhs=nrhs)
+    info = F.info
+    fmt = 2 * 8 * info["nnz_l"] + 32 * info["n"] * nrhs
+    slots = 16 * info["n_upd"] * nrhs
+    achieved = byt / sec / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5),
+            "traffic": measured_traffic(profile, sources),
+            "kernel": (f"substitution pair on C + gamma G, {nrhs} right-hand side(s): all level launches "
+                       f"of one forward and one backward sweep"),
+            "pair_ms": round(sec * 1e3, 4), "algorithmic_bytes": int(byt),
+            "algorithmic_bytes_def": "2*8*nnz(L) + 4*8*n*nrhs, nnz(L) the factor's structural nonzeros",
+            "nnz_l_exact": info["nnz_l_exact"], "nnz_l_stored": info["nnz_l"],
+            "format_bytes": int(fmt), "update_slot_bytes": int(slots),
+            "kernel_sources": kernel_source_digest(sources)}
+
+
+def windows_error(x, gold_dir, names, t_out):
+    import numpy as np
+    out = {}
+    for nm in names:
+        g = np.load(os.path.join(gold_dir, nm))
+        sel = np.isin(t_out, g["t_out"])
+        out[nm] = float(np.abs(x[:, sel] - g["x"]).max())
+    return out
+
+
+def config1_context(tol):
     import numpy as np
     import torch
     from paper_1511_04519_amd import instances as I
     from paper_1511_04519_amd import matex as M
-    p = I.config2()
-    if window_ps:
-        T = window_ps * I.PS
-        p = I.Problem(p.name + f" (first {window_ps} ps)", p.netlist, p.sources, T,
-                      p.t_out[p.t_out <= T], p.probe)
-    groups = len(np.unique(p.sources.group))
-    tol = 1e-10 / groups
-    n, n_out = p.netlist.n, p.t_out.size
+    p = I.config1()
+    F = M.matex_factor(p.netlist, p.gamma, leaf_max=CONFIG1_LEAF)
+    torch.cuda.synchronize()
     t0 = time.time()
-    F = M.matex_factor(p.netlist, p.gamma)
-    factor_s = time.time() - t0
-    print(f"[bench] batched workload: n {n}, {groups} subtasks, factor {factor_s:.1f} s, "
-          f"nnz(L) {F.info['nnz_l']}", flush=True)
-    res = {}
-    # the plain run of this workload stopped on a GPU memory fault whose
-    # cause is not found yet; it runs only on request
-    modes = (("batched", M.MATEX_BATCHED), ("plain", M.MATEX_PLAIN)) if with_plain else \
-        (("batched", M.MATEX_BATCHED),)
-    for mode, md in modes:
-        torch.cuda.synchronize()
-        t0 = time.time()
-        x, _, st = M.matex_transient(F, p, tol=tol, m_max=p.m_max, mode=md)
-        torch.cuda.synchronize()
-        dt = time.time() - t0
-        res[mode] = (x.cpu().numpy(), dt, st)
-        print(f"[bench] {mode}: {dt:.2f} s, pairs {st['solve_pairs_m']}+{st['solve_pairs_g']}, "
-              f"bases {st['bases']}", flush=True)
-    diff = float(np.abs(res["batched"][0] - res["plain"][0]).max()) if with_plain else None
-    pair_s, pair_b = M.matex_time_solves(F, which=0, reps=20, nrhs=64)
-    one_s, one_b = M.matex_time_solves(F, which=0, reps=20, nrhs=1)
-    sb = res["batched"][2]
-    sp = res["plain"][2] if with_plain else None
-    return {
-        "workload": p.name, "n": n, "n_out": int(n_out), "subtasks": groups, "tol": tol,
-        "factor_s": round(factor_s, 2),
-        "batched_node_steps_per_s": n * n_out / res["batched"][1],
-        "plain_node_steps_per_s": n * n_out / res["plain"][1] if with_plain else None,
-        "batched_s": round(res["batched"][1], 3),
-        "plain_s": round(res["plain"][1], 3) if with_plain else None,
-        "speedup": round(res["plain"][1] / res["batched"][1], 3) if with_plain else None,
-        "max_abs_diff_batched_vs_plain": diff,
-        "same_steps": (sb["segments"] == sp["segments"] and sb["krylov_dims"] == sp["krylov_dims"])
-        if with_plain else None,
-        "stats_batched": sb, "stats_plain": sp,
-        "pair64": {"bound": "hbm", "achieved": round(pair_b / pair_s / 1e9, 2), "peak": HBM_PEAK_GBS,
-                   "unit": "GB/s", "frac": round(pair_b / pair_s / 1e9 / HBM_PEAK_GBS, 5),
-                   "traffic": measured_traffic(TRAFFIC_PROFILE64, BATCHED_SOURCES),
-                   "pair_ms": round(pair_s * 1e3, 3), "pair_bytes": int(pair_b),
-                   "ms_per_subtask": round(pair_s * 1e3 / 64, 4),
-                   "kernel_sources": kernel_source_digest(BATCHED_SOURCES)},
-        "pair1": {"achieved": round(one_b / one_s / 1e9, 2), "unit": "GB/s",
-                  "frac": round(one_b / one_s / 1e9 / HBM_PEAK_GBS, 5), "pair_ms": round(one_s * 1e3, 3)},
-    }
+    x, _, st = M.matex_transient(F, p, tol=tol, m_max=p.m_max)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    xs = x.cpu().numpy()
+    gold = np.load(os.path.join(ROOT, "tests/golden/config1_head.npz"))
+    k = int((p.t_out <= int(gold["t_end"])).sum())
+    mid = np.load(os.path.join(ROOT, "tests/golden/config1_mid.npz"))
+    sel = np.isin(p.t_out, mid["t_out"])
+    roof = pair_roofline(F, 1, 50, TRAFFIC_PROFILE1, PLAIN_SOURCES)
+    roof["bound"] = "hbm (cache-resident: the factor fits the 256 MB Infinity Cache)"
+    return {"workload": p.name, "n": p.netlist.n, "n_out": int(p.t_out.size), "mode": "plain",
+            "leaf": CONFIG1_LEAF, "tol": tol, "seconds": round(dt, 3),
+            "node_steps_per_s": p.netlist.n * p.t_out.size / dt, "segments": st["segments"],
+            "bases": st["bases"], "solve_pairs": st["solve_pairs_m"] + st["solve_pairs_g"],
+            "max_abs_err_vs_oracle_0_500ps": float(np.abs(xs[:, :k] - gold["x"][:, :k]).max()),
+            "max_abs_err_vs_oracle_2900_3000ps": float(np.abs(xs[:, sel] - mid["x"]).max()),
+            "pair1": roof}
+
+
+def pairs_only():
+    """The profiling run for the sweep kernels' counters: 1 + 50 one-vector
+    pairs on the 180k-node grid, 1 + 20 pairs with 64 right-hand sides on the
+    1M-node grid, then a 256 MiB device copy for calibration."""
+    import torch
+    from paper_1511_04519_amd import instances as I
+    from paper_1511_04519_amd import matex as M
+    out = {}
+    for name, prob, nrhs, reps, leaf in (("config1", I.config1(), 1, 50, CONFIG1_LEAF),
+                                         ("config2", I.config2(), 64, 20, 16)):
+        F = M.matex_factor(prob.netlist, prob.gamma, leaf_max=leaf)
+        sec, byt = M.matex_time_solves(F, which=0, reps=reps, nrhs=nrhs)
+        out[name] = {"nrhs": nrhs, "pairs": reps + 1, "pair_ms": sec * 1e3, "pair_bytes": byt,
+                     "GB_s": byt / sec / 1e9, "frac": byt / sec / 1e9 / HBM_PEAK_GBS}
+        print(f"[bench] {name}: pair {sec * 1e3:.3f} ms, {byt / sec / 1e9:.0f} GB/s", flush=True)
+        del F
+    a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
+    torch.empty_like(a).copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps(out), flush=True)
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--cpu-child":
+        cpu_child(int(sys.argv[2]), int(sys.argv[3]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--window-ps", type=int, default=0, help="shorten the window (0 = full)")
-    ap.add_argument("--cpu-window-ps", type=int, default=30)
+    ap.add_argument("--cpu-window-ps", type=int, default=CPU_WINDOW_PS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-window-ps", type=int, default=0, help="shorten the batched window")
-    ap.add_argument("--pairs-only", action="store_true",
-                    help="only time the substitution pairs (one-vector on the 180k-node grid, "
-                         "1 + 50 pairs; 64 right-hand sides on the 1M-node grid, 1 + 20 pairs): "
-                         "the profiling run for the sweep kernels' counters")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-config1", action="store_true")
+    ap.add_argument("--pairs-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for {args.gpus}).",
+        print(f"bench.py runs on one GPU: nothing in this build uses a second one (asked for {args.gpus}).",
               file=sys.stderr)
         sys.exit(2)
 
@@ -189,94 +315,88 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     M.lib()   # fails loudly if libmatex.so is missing
     if args.pairs_only:
-        out = {}
-        for name, prob, nrhs, reps, leaf in (("config1", I.config1(), 1, 50, CONFIG1_LEAF),
-                                             ("config2", I.config2(), 64, 20, 16)):
-            F = M.matex_factor(prob.netlist, prob.gamma, leaf_max=leaf)
-            sec, byt = M.matex_time_solves(F, which=0, reps=reps, nrhs=nrhs)
-            out[name] = {"nrhs": nrhs, "pairs": reps + 1, "pair_ms": sec * 1e3, "pair_bytes": byt,
-                         "GB_s": byt / sec / 1e9, "frac": byt / sec / 1e9 / HBM_PEAK_GBS}
-            print(f"[bench] {name}: pair {sec * 1e3:.3f} ms, {byt / sec / 1e9:.0f} GB/s", flush=True)
-            del F
-        a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
-        torch.empty_like(a).copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps(out), flush=True)
+        pairs_only()
         return
-    p = I.config1()
+    cores = max(1, min(16, os.cpu_count() or 1))
+    cpu = None if args.no_cpu_baseline else CpuBaseline(args.cpu_window_ps, cores)
+
+    p = I.config2()
     if args.window_ps:
         T = args.window_ps * I.PS
         p = I.Problem(p.name + f" (first {args.window_ps} ps)", p.netlist, p.sources, T,
                       p.t_out[p.t_out <= T], p.probe)
+    groups = len(np.unique(p.sources.group))
+    tol = 1e-10 / groups
     n, n_out = p.netlist.n, p.t_out.size
     t0 = time.time()
-    F = M.matex_factor(p.netlist, p.gamma, leaf_max=CONFIG1_LEAF)
+    F = M.matex_factor(p.netlist, p.gamma)
     factor_s = time.time() - t0
-    print(f"[bench] factor {factor_s:.2f} s (host analyse {F.info['seconds_analyse']:.2f} s, "
-          f"numeric {F.info['seconds_numeric']:.2f} s), nnz(L) {F.info['nnz_l']}, "
-          f"levels {F.info['n_levels']}", flush=True)
+    print(f"[bench] factor {factor_s:.1f} s (host analyse {F.info['seconds_analyse']:.2f} s, numeric "
+          f"{F.info['seconds_numeric']:.1f} s), nnz(L) {F.info['nnz_l_exact']} (stored "
+          f"{F.info['nnz_l']}), levels {F.info['n_levels']}, subtree blocks {F.info['subtree_blocks']}",
+          flush=True)
 
     for w in range(args.warmup):
-        M.matex_transient(F, p, tol=args.tol, m_max=p.m_max)
+        M.matex_transient(F, p, tol=tol, m_max=p.m_max, mode=M.MATEX_BATCHED)
         print(f"[bench] warmup {w + 1}/{args.warmup} done", flush=True)
     torch.cuda.synchronize()
     t0 = time.time()
     for k in range(args.steps):
-        x, xf, st = M.matex_transient(F, p, tol=args.tol, m_max=p.m_max)
-        print(f"[bench] step {k + 1}/{args.steps}: {st['seconds']:.2f} s, segments {st['segments']}, "
-              f"bases {st['bases']}, pairs {st['solve_pairs_m']}+{st['solve_pairs_g']}", flush=True)
+        x, _, st = M.matex_transient(F, p, tol=tol, m_max=p.m_max, mode=M.MATEX_BATCHED)
+        print(f"[bench] step {k + 1}/{args.steps}: {st['seconds']:.3f} s, segments {st['segments']}, "
+              f"bases {st['bases']}, 64-column pairs {st['solve_pairs_m']}+{st['solve_pairs_g']}", flush=True)
     torch.cuda.synchronize()
     dt = (time.time() - t0) / args.steps
     value = n * n_out / dt
+    xb = x.cpu().numpy()
 
-    # parity spot checks against the oracle's stored windows of this run
-    xs = x.cpu().numpy()
-    gold = np.load(os.path.join(ROOT, "tests/golden/config1_head.npz"))
-    k_head = int((p.t_out <= int(gold["t_end"])).sum())
-    err_head = float(np.abs(xs[:, :k_head] - gold["x"][:, :k_head]).max())
-    mid = np.load(os.path.join(ROOT, "tests/golden/config1_mid.npz"))
-    sel = np.isin(p.t_out, mid["t_out"])
-    err_mid = float(np.abs(xs[:, sel] - mid["x"][:, : int(sel.sum())]).max()) if sel.any() else None
+    plain = None
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        t0 = time.time()
+        xp_t, _, sp = M.matex_transient(F, p, tol=tol, m_max=p.m_max, mode=M.MATEX_PLAIN)
+        torch.cuda.synchronize()
+        tp = time.time() - t0
+        xp = xp_t.cpu().numpy()
+        print(f"[bench] plain: {tp:.2f} s, pairs {sp['solve_pairs_m']}+{sp['solve_pairs_g']}", flush=True)
+        plain = {"seconds": round(tp, 3), "node_steps_per_s": n * n_out / tp,
+                 "speedup_batched_vs_plain": round(tp / dt, 3),
+                 "same_steps": sp["segments"] == st["segments"] and sp["krylov_dims"] == st["krylov_dims"]
+                 and sp["bases"] == st["bases"],
+                 "max_abs_diff_batched_vs_plain": float(np.abs(xb - xp).max()),
+                 "stats": sp}
 
-    # live roofline of the substitution-pair sweeps (event-timed on the
-    # library's stream): one pair = the forward and backward level sweeps
-    pair_s, pair_b = M.matex_time_solves(F, which=0, reps=50)
-    achieved = pair_b / pair_s / 1e9
-    traffic = measured_traffic()
-    roofline = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                "traffic": traffic,
-                "kernel": "substitution pair: k_forward_tree/k_backward_tree subtree sweeps and k_forward/k_backward level sweeps on C + gamma G",
-                "pair_us": round(pair_s * 1e6, 2), "pair_bytes": int(pair_b),
-                "kernel_sources": kernel_source_digest()}
+    gold_dir = os.path.join(ROOT, "tests/golden")
+    parity = {"batched": windows_error(xb, gold_dir, ("config2_head.npz", "config2_mid.npz"), p.t_out)}
+    if plain is not None:
+        parity["plain"] = windows_error(xp, gold_dir, ("config2_head.npz", "config2_mid.npz"), p.t_out)
+    parity["criterion"] = "max |x_gpu - x_oracle| / max |x_oracle| <= 1e-9 (x ~ Vdd = 1 V)"
+
+    roof = pair_roofline(F, 64, 20, TRAFFIC_PROFILE64, BATCHED_SOURCES)
+    pair1 = pair_roofline(F, 1, 20, None, PLAIN_SOURCES)
+    pair1.pop("traffic")
     # calibration copy for the hardware byte counters (256 MiB read + write)
     a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
     torch.empty_like(a).copy_(a)
     torch.cuda.synchronize()
+    del F
 
-    batched = None if args.no_batched else batched_vs_plain(args.batched_window_ps)
-
-    cpu = None
-    if not args.no_cpu_baseline:
-        d = cpu_baseline(p, args.tol, args.cpu_window_ps * I.PS)
-        cpu = {"value": d["value"], "unit": "node*steps/s", "cores": 1, "kind": "oracle",
-               "sample": f"oracle R-MATEX, same grid and tol, window [0, {args.cpu_window_ps} ps] "
-                         f"({d['n_out']} outputs, {d['bases']} bases, {d['pairs']} solve pairs, "
-                         f"{d['transient_s']:.1f} s; factor {d['factor_s']:.1f} s excluded)"}
+    c1 = None if args.no_config1 else config1_context(1e-10)
+    cpu_line = cpu.finish() if cpu is not None else None
 
     line = {
         "metric": METRIC, "value": value, "unit": "node*steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic (seeded 2x300x300 RC grid, 2000 pulse sources)",
-        "config": {"workload": p.name, "n": n, "n_out": int(n_out), "n_probe": int(p.probe.size),
-                   "mode": "plain", "tol": args.tol, "gamma": p.gamma, "m_max": p.m_max,
-                   "factor_s": round(factor_s, 2), "segments": st["segments"],
-                   "bases": st["bases"], "solve_pairs": st["solve_pairs_m"] + st["solve_pairs_g"],
-                   "krylov_dims": st["krylov_dims"],
-                   "max_abs_err_vs_oracle_0_500ps": err_head,
-                   "max_abs_err_vs_oracle_2900_3000ps": err_mid},
-        "roofline": roofline, "cpu_baseline": cpu, "batched": batched,
+        "data": "synthetic (seeded 3x580x580 RC grid, 2000 pulse sources in 64 timing groups)",
+        "config": {"workload": p.name + ", batched (64 subtasks per substitution pair)", "n": n,
+                   "n_out": int(n_out), "n_probe": int(p.probe.size), "subtasks": groups, "mode": "batched",
+                   "tol": tol, "gamma": p.gamma, "m_max": p.m_max, "factor_s": round(factor_s, 2),
+                   "segments": st["segments"], "bases": st["bases"],
+                   "pairs_64rhs": st["solve_pairs_m"] + st["solve_pairs_g"],
+                   "krylov_dims": st["krylov_dims"]},
+        "plain": plain, "parity": parity, "roofline": roof, "pair1": pair1, "config1": c1,
+        "cpu_baseline": cpu_line,
     }
     print(json.dumps(line), flush=True)
 

@@ -100,6 +100,12 @@ typedef struct {
     int64_t device_bytes;    /* device memory held by the handle                 */
     int32_t subtree_levels;  /* bottom levels swept as whole subtrees          */
     int32_t subtree_blocks;  /* workgroups of those subtree sweeps             */
+    int64_t nnz_l_exact;     /* structural nonzeros of one factor L in this
+                                ordering, diagonal included (what a solve
+                                must read; nnz_l adds the explicit zeros of
+                                the supernodal panels)                         */
+    int64_t n_upd;           /* forward update slots per right-hand side (the
+                                off-diagonal rows of all supernodes)           */
 } matex_factor_info;
 
 /*
@@ -130,6 +136,24 @@ matex_status matex_factor_get_info(matex_factor_t f, matex_factor_info* info);
  */
 matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const double* d_b,
                          const double* d_scale, double* d_x, void* stream);
+
+/*
+ * matex_solve_noalloc - matex_solve for one right-hand side (nrhs = 1) that
+ * allocates nothing: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Same arguments and result as matex_solve with nrhs = 1 (the
+ * same kernels in the same order, so the same bits). Its scratch (the
+ * permuted b, x and scale, the forward result and the update slots:
+ * 3 n + n_upd doubles, see matex_factor_info) lives in a library-owned
+ * device array of 64 MiB (8 Mi doubles) per GPU, held until the process
+ * ends; a factor that needs more is refused with MATEX_E_INVALID before any
+ * device work. Every call on one GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams, other host threads) race and must be
+ * serialised by the caller. Asynchronous: nothing is synchronised.
+ * Errors: MATEX_E_INVALID, MATEX_E_HIP.
+ */
+matex_status matex_solve_noalloc(matex_factor_t f, int32_t which, const double* d_b,
+                                 const double* d_scale, double* d_x, void* stream);
 
 /*
  * matex_krylov_step - e^{tau_k A} v_r (Eq. 9) for every tau_k and every
@@ -289,11 +313,21 @@ matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex
  * stream around the batch. nrhs = 1 times the one-vector sweeps of the plain
  * mode; nrhs in 2..64 the multi-right-hand-side sweeps of the batched mode
  * (nrhs subtasks per pair). Writes the mean seconds per pair to *seconds and
- * the algorithmic bytes of one pair (panel values and indices read once per
- * sweep, plus nrhs times the vectors) to *bytes. For measurement only.
+ * the algorithmic bytes of one pair to *bytes: each nonzero of L read once
+ * per sweep (8 B, nnz_l_exact) and, per right-hand side, the right-hand
+ * side and result of both sweeps (4 x 8 B per row). For measurement only.
  */
 matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t nrhs, int32_t reps,
                                double* seconds, double* bytes, void* stream);
+
+/*
+ * matex_sync - waits for the work the library enqueued on `stream` (NULL =
+ * default stream) and reports what HIP reports: an asynchronous device fault
+ * of an earlier call surfaces here (or at the next call) as MATEX_E_HIP,
+ * with HIP's text in matex_last_error(). MATEX_OK when the stream is idle
+ * and no error is pending.
+ */
+matex_status matex_sync(void* stream);
 
 /* Copies the calling thread's last error text (NUL-terminated) into buf. */
 size_t matex_last_error(char* buf, size_t len);

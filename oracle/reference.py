@@ -121,11 +121,13 @@ def dense_eq5(prob):
     return y_out, x
 
 
-def trapezoidal(prob, h_fs: int, align: bool = True):
+def trapezoidal(prob, h_fs: int, align: bool = True, factors=None):
     """Eq. 2 with fixed step h (fs): (C/h + G/2) y+ = (C/h - G/2) y + (i + i+)/2.
     With align, steps are cut at every transition spot and output time so the
     piecewise-linear input is sampled exactly; returns (y at probe x t_out,
-    y(t_end), number of substitution pairs)."""
+    y(t_end), number of substitution pairs). `factors` may hold factors made
+    beforehand: "G" (for the initial state) and, per step h in fs, the
+    Cholesky of C/h + G/2; the missing ones are made here."""
     nl, src = prob.netlist, prob.sources
     n = nl.n
     idx = np.arange(src.n_src)
@@ -141,8 +143,9 @@ def trapezoidal(prob, h_fs: int, align: bool = True):
         grid = np.array(grid, dtype=np.int64)
     else:
         grid = np.arange(0, prob.t_end + 1, h_fs, dtype=np.int64)
-    facs = {}
-    y = Cholesky(rp, ci, gv).solve(current(src, idx, n, 0))
+    facs = dict(factors or {})
+    Gf = facs.pop("G", None) or Cholesky(rp, ci, gv)
+    y = Gf.solve(current(src, idx, n, 0))
     y_out = np.zeros((prob.probe.size, prob.t_out.size))
     k_out = 0
     pairs = 0

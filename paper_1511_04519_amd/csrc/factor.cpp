@@ -159,6 +159,44 @@ std::vector<int32_t> bfs_coords(const Csr& g)
 
 }  // namespace
 
+// Structural nonzeros of the Cholesky factor of P G P^T (diagonal included):
+// the elimination tree (Liu's algorithm, with path compression on a
+// separate ancestor array), then for every row i the row subtree, the
+// nodes on the paths from each k < i with G(i, k) != 0 up to i. The
+// supernodal panels store more (the explicit zeros of each supernode's
+// shared row list and of relaxed leaves); this is what a solve must read.
+static int64_t exact_lower_nnz(const Csr& g, const Symbolic& s)
+{
+    const int64_t n = s.n;
+    std::vector<int32_t> parent(n, -1), anc(n, -1), mark(n, -1);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t o = s.perm[i];
+        for (int64_t p = g.rp[o]; p < g.rp[o + 1]; ++p) {
+            int32_t j = s.iperm[g.ci[p]];
+            while (j != -1 && j < i) {
+                const int32_t nx = anc[j];
+                anc[j] = int32_t(i);
+                if (nx == -1) parent[j] = int32_t(i);
+                j = nx;
+            }
+        }
+    }
+    int64_t nnz = n;
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t o = s.perm[i];
+        mark[i] = int32_t(i);
+        for (int64_t p = g.rp[o]; p < g.rp[o + 1]; ++p) {
+            const int32_t k = s.iperm[g.ci[p]];
+            if (k >= i) continue;
+            for (int32_t j = k; j != -1 && mark[j] != i; j = parent[j]) {
+                mark[j] = int32_t(i);
+                nnz++;
+            }
+        }
+    }
+    return nnz;
+}
+
 Symbolic analyse(const Csr& g, const int32_t* coord, int32_t leaf_max)
 {
     Symbolic s;
@@ -230,6 +268,7 @@ Symbolic analyse(const Csr& g, const int32_t* coord, int32_t leaf_max)
     s.n_w = w;
     s.n_upd = u;
     s.nnz_l = nnz;
+    s.nnz_exact = exact_lower_nnz(g, s);
     // children lists and each off-diagonal row's place among the parent's rows
     s.child_ptr.assign(nsn + 1, 0);
     for (int32_t k = 0; k < nsn; ++k)

@@ -55,6 +55,7 @@ struct Symbolic {
     int64_t n_upd = 0;            // sum of off-diagonal row counts
     int64_t n_w = 0;              // total panel storage (sum panel_ld(nr) * nc)
     int64_t nnz_l = 0;            // entries of L in the stored panels (lower part)
+    int64_t nnz_exact = 0;        // structural nonzeros of L in this ordering (diagonal included)
     int32_t n_levels = 0;
     std::vector<std::vector<int32_t>> level_sn;   // supernodes per level
     int32_t max_nr = 0, max_nc = 0;

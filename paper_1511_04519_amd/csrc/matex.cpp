@@ -604,27 +604,50 @@ KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, doub
     return h;
 }
 
-// Algorithmic bytes of one substitution pair on the stored structure: every
-// panel entry of the lower triangle is read once per sweep (8 B value; the
-// panel layout needs no per-entry index), each sweep reads its right-hand
-// side and writes its result once (8 B per row), the forward sweep also
-// reads the diagonal scale when there is one, each update slot is written
-// once and read once by the parent with its 4 B relative index, and the
-// backward sweep reads the 4 B off-diagonal row list once.
-int64_t solve_pair_bytes(const Symbolic& s, bool scaled)
+// Algorithmic bytes of one substitution pair on nrhs right-hand sides: every
+// nonzero of L read once per sweep (8 B; the exact structural count, not the
+// stored panel entries with their explicit zeros) and, per right-hand side,
+// each sweep's right-hand side and result (4 x 8 B per row). The panel
+// format's own overheads (explicit zeros, update slots, indices) are not
+// algorithmic.
+int64_t solve_pair_bytes(const Symbolic& s, int nrhs)
 {
-    const int64_t vec = 8 * s.n;
-    return 2 * 8 * s.nnz_l + 4 * vec + (scaled ? vec : 0) + s.n_upd * (8 + 8 + 4) +
-           int64_t(s.rows.size()) * 4;
+    return 2 * 8 * s.nnz_exact + int64_t(nrhs) * 4 * 8 * s.n;
 }
 
-// The same for a pair on R row-interleaved right-hand sides: the panels, the
-// scale and the index lists once, every vector term R times.
-int64_t solve_pair_bytes_batched(const Symbolic& s, bool scaled, int R)
+}  // namespace
+
+// ------------------------------------------------ allocation-free solves
+
+// Scratch of matex_solve_noalloc: a file-scope device array, one per GPU the
+// library runs on, held until the process ends. Host code never passes the
+// array's name to a kernel (on the host it is a stand-in, not a device
+// address): each device's address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and is used instead.
+constexpr int64_t NOALLOC_DOUBLES = int64_t(8) << 20;   // 64 MiB
+static __device__ __align__(256) double g_noalloc_scratch[NOALLOC_DOUBLES];
+
+namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[MAX_DEVICES] = {};
+
+// The scratch's address on the current device (nullptr and the error text
+// set when HIP cannot resolve it).
+double* noalloc_scratch(int dev)
 {
-    const int64_t vec = 8 * s.n;
-    return 2 * 8 * s.nnz_l + int64_t(R) * (4 * vec + s.n_upd * (8 + 8)) + (scaled ? vec : 0) +
-           s.n_upd * 4 + int64_t(s.rows.size()) * 4;
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(g_noalloc_scratch));
+        if (e != hipSuccess || !ptr) {
+            g_err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+    }
+    return g_noalloc_ptr[dev];
 }
 
 }  // namespace
@@ -633,7 +656,15 @@ int64_t solve_pair_bytes_batched(const Symbolic& s, bool scaled, int R)
 
 extern "C" {
 
-const char* matex_version(void) { return "matex-mi355x 0.1 (gfx950, fp64)"; }
+const char* matex_version(void) { return "matex-mi355x 0.2 (gfx950, fp64)"; }
+
+matex_status matex_sync(void* stream)
+{
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) return fail(MATEX_E_HIP, std::string("matex_sync: ") + hipGetErrorString(e));
+    return MATEX_OK;
+}
 
 size_t matex_last_error(char* buf, size_t len)
 {
@@ -765,6 +796,8 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
         I.device_bytes = F->held_bytes();
         I.subtree_levels = F->tree.n_levels;
         I.subtree_blocks = F->tree.n_blocks;
+        I.nnz_l_exact = s.nnz_exact;
+        I.n_upd = s.n_upd;
         *out = F.release();
         return MATEX_OK;
     } catch (const HipError& e) {
@@ -785,6 +818,51 @@ matex_status matex_factor_get_info(matex_factor_t f, matex_factor_info* info)
     if (!f || !info) return fail(MATEX_E_INVALID, "null argument");
     *info = f->info;
     return MATEX_OK;
+}
+
+matex_status matex_solve_noalloc(matex_factor_t f, int32_t which, const double* d_b, const double* d_scale,
+                                 double* d_x, void* stream)
+{
+    if (!f || !d_b || !d_x) return fail(MATEX_E_INVALID, "bad argument");
+    const int n_shifts = int(f->gammas.size());
+    if (which < -1 || which >= n_shifts) return fail(MATEX_E_INVALID, "factor index out of range");
+    if (d_b == d_x) return fail(MATEX_E_INVALID, "d_b and d_x may not alias");
+    const int64_t n = f->sym.n, n_upd = std::max<int64_t>(1, f->sym.n_upd);
+    // b, x (also the scale until the backward sweep), the forward result and
+    // the update slots
+    const int64_t need = 3 * n + n_upd;
+    if (need > NOALLOC_DOUBLES)
+        return fail(MATEX_E_INVALID, "matex_solve_noalloc: the factor needs " + std::to_string(need) +
+                                         " doubles of scratch (3 n + update slots), more than its " +
+                                         std::to_string(NOALLOC_DOUBLES) + " (64 MiB)");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES)
+        return fail(MATEX_E_HIP, "matex_solve_noalloc: no usable current device");
+    double* sp = noalloc_scratch(dev);
+    if (!sp) return MATEX_E_HIP;
+    const int idx = which < 0 ? n_shifts : which;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    double* bp = sp;
+    double* xp = sp + n;
+    double* tmp = sp + 2 * n;
+    double* upd = sp + 3 * n;
+    const int32_t* perm = f->d_perm.as<int32_t>();
+    try {
+        launch_gather_perm(n, perm, d_b, bp, n, n, 1, st);
+        const double* scale_p = nullptr;
+        if (d_scale) {
+            // the scale is read by the forward sweep only; the backward sweep
+            // then writes x over it
+            launch_gather_perm(n, perm, d_scale, xp, n, n, 1, st);
+            scale_p = xp;
+        }
+        dev_solve(*f, idx, bp, scale_p, xp, tmp, upd, nullptr, st);
+        launch_scatter_perm(n, perm, xp, d_x, n, n, 1, st);
+        HIPCHK(hipGetLastError());
+        return MATEX_OK;
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
 }
 
 matex_status matex_solve(matex_factor_t f, int32_t which, int32_t nrhs, const double* d_b,
@@ -869,7 +947,7 @@ matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t nrhs, in
             (void)hipEventDestroy(e0);
             (void)hipEventDestroy(e1);
             *seconds = 1e-3 * double(ms) / reps;
-            *bytes = double(solve_pair_bytes_batched(f->sym, idx < n_shifts, nrhs));
+            *bytes = double(solve_pair_bytes(f->sym, nrhs));
             return MATEX_OK;
         } catch (const HipError& e) {
             return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
@@ -897,7 +975,7 @@ matex_status matex_time_solves(matex_factor_t f, int32_t which, int32_t nrhs, in
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         *seconds = 1e-3 * double(ms) / reps;
-        *bytes = double(solve_pair_bytes(f->sym, idx < n_shifts));
+        *bytes = double(solve_pair_bytes(f->sym, 1));
         return MATEX_OK;
     } catch (const HipError& e) {
         return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));

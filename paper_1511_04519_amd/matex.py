@@ -44,7 +44,8 @@ class FactorInfo(ctypes.Structure):
     _fields_ = [("n", _i64), ("nnz_l", _i64), ("panel_doubles", _i64), ("n_supernodes", _i32),
                 ("n_levels", _i32), ("n_shifts", _i32), ("max_nr", _i32), ("gamma", _f64),
                 ("seconds_analyse", _f64), ("seconds_numeric", _f64), ("device_bytes", _i64),
-                ("subtree_levels", _i32), ("subtree_blocks", _i32)]
+                ("subtree_levels", _i32), ("subtree_blocks", _i32), ("nnz_l_exact", _i64),
+                ("n_upd", _i64)]
 
 
 class Problem(ctypes.Structure):
@@ -70,8 +71,9 @@ class Stats(ctypes.Structure):
 
 
 EXPORTS = ["matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
+           "matex_solve_noalloc",
            "matex_krylov_step", "matex_transient", "matex_transient_many", "matex_adjoint",
-           "matex_time_solves", "matex_last_error", "matex_version"]
+           "matex_time_solves", "matex_sync", "matex_last_error", "matex_version"]
 
 _lib = None
 
@@ -91,6 +93,7 @@ def lib():
         L.matex_factor_free.argtypes = [_vp]
         L.matex_factor_get_info.argtypes = [_vp, ctypes.POINTER(FactorInfo)]
         L.matex_solve.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp]
+        L.matex_solve_noalloc.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
         L.matex_krylov_step.argtypes = [_vp, _i32, _i32, _vp, _i32, _pf64, _i32, _f64, _vp, _pi32,
                                         _pf64, _vp]
         L.matex_transient.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(RunOpts), _vp,
@@ -101,12 +104,14 @@ def lib():
         L.matex_adjoint.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(RunOpts), _vp,
                                     _vp, _vp, _vp]
         L.matex_time_solves.argtypes = [_vp, _i32, _i32, _i32, _pf64, _pf64, _vp]
+        L.matex_sync.argtypes = [_vp]
         L.matex_last_error.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.matex_last_error.restype = ctypes.c_size_t
         L.matex_version.restype = ctypes.c_char_p
         for name in ("matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
+                     "matex_solve_noalloc",
                      "matex_krylov_step", "matex_transient", "matex_transient_many",
-                     "matex_adjoint", "matex_time_solves"):
+                     "matex_adjoint", "matex_time_solves", "matex_sync"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -196,6 +201,14 @@ def matex_solve(f: FactorHandle, which: int, b, scale=None):
     return x.reshape(b.shape)
 
 
+def matex_solve_noalloc(f: FactorHandle, which: int, b, x, scale=None):
+    """x = A_which^-1 (scale * b) for one (n,) float64 device vector into the
+    caller's x, through the library's allocation-free entry point (nothing
+    allocated by the library; asynchronous on torch's current stream)."""
+    _check(lib().matex_solve_noalloc(f.handle, which, _ptr(b), _ptr(scale), _ptr(x), _stream()))
+    return x
+
+
 def matex_krylov_step(f: FactorHandle, v, taus, shift: int = 0, m_max: int = 20,
                       tol: float = 1e-12):
     """e^{tau A} v for every tau (seconds). v: (n,) or (nrhs, n) device tensor.
@@ -279,6 +292,12 @@ def matex_time_solves(f: FactorHandle, which: int = 0, reps: int = 50, nrhs: int
     _check(lib().matex_time_solves(f.handle, which, nrhs, reps, ctypes.byref(sec),
                                    ctypes.byref(byt), _stream()))
     return sec.value, byt.value
+
+
+def matex_sync():
+    """Waits for the library's work on torch's current stream; raises
+    MatexError (MATEX_E_HIP) if HIP reports a pending error."""
+    _check(lib().matex_sync(_stream()))
 
 
 def matex_adjoint(f: FactorHandle, prob, dJdx, tol: float = 1e-10, m_max: int = 30,

@@ -14,7 +14,15 @@ stored so a test can tell that it rebuilt the same instance.
                     the grid forgets that start within tens of ps (its slowest
                     time constant is a few ps), which check_warm_start()
                     confirms on the head window against the run from 0.
-Run:  OPENBLAS_NUM_THREADS=1 python tests/golden/make_golden.py [head|mid|check]
+  config2_head.npz  the 3x580x580 workload (1,009,200 nodes, 2000 sources in
+                    64 timing groups) over its first 300 ps: x at the 512
+                    probe rows every 10 ps. The oracle runs all sources as one
+                    subtask (Sec. 3.1: the subtasks' responses add up to it),
+                    tol 1e-12 per basis.
+  config2_mid.npz   the same workload over [0.9, 1.0] ns (11 transition
+                    spots), started at 0.6 ns from G^-1 i(0.6 ns).
+Run:  OPENBLAS_NUM_THREADS=1 python tests/golden/make_golden.py
+          [head|mid|check|c2head|c2mid]
 """
 import os
 import sys
@@ -72,6 +80,24 @@ def config1_mid():
                         t_start=2600 * I.PS, tol=1e-12)
 
 
+def config2_window(name, t0, t1, t2, tol=1e-12):
+    """Oracle x at the probes of the 1M-node workload for t_out in [t1, t2],
+    started at t0 (from G^-1 i(t0); exact at t0 = 0), all sources in one
+    subtask."""
+    p = I.config2()
+    sel = (p.t_out >= t1) & (p.t_out <= t2)
+    q = I.Problem(p.name + " (window)", p.netlist, p.sources, t2, p.t_out[p.t_out <= t2], p.probe)
+    t = time.time()
+    s = RM.RMatex(p.netlist, p.gamma)
+    print(f"config2 factors: {time.time() - t:.1f} s", flush=True)
+    t = time.time()
+    x, _ = s.transient(q, tol=tol, m_max=p.m_max, decompose=False, t_start=t0)
+    print(f"config2 window [{t0}, {t2}] fs: {time.time() - t:.1f} s, bases {s.stats.bases}, "
+          f"pairs {s.stats.solve_pairs_M}+{s.stats.solve_pairs_G}", flush=True)
+    np.savez_compressed(os.path.join(HERE, name), x=x[:, sel[p.t_out <= t2]], t_out=p.t_out[sel],
+                        digest=p.digest(), t_start=t0, tol=tol)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     if what in ("head", "all"):
@@ -80,3 +106,7 @@ if __name__ == "__main__":
         check_warm_start()
     if what in ("mid", "all"):
         config1_mid()
+    if what in ("c2head", "all"):
+        config2_window("config2_head.npz", 0, 0, 300 * I.PS)
+    if what in ("c2mid", "all"):
+        config2_window("config2_mid.npz", 600 * I.PS, 900 * I.PS, 1000 * I.PS)

@@ -235,10 +235,12 @@ def test_transient_edge_cases():
 
 # ------------------------------------------------- full-size config 1 grid
 
-@pytest.fixture(scope="module")
-def config1_factor():
+@pytest.fixture(scope="module", params=[16, 32], ids=["leaf16", "leaf32"])
+def config1_factor(request):
+    """The 180k-node grid factored with 16-node leaves (the library's
+    default) and with the 32-node leaves the benchmark's context run uses."""
     p = I.config1()
-    return p, M.matex_factor(p.netlist, p.gamma)
+    return p, M.matex_factor(p.netlist, p.gamma, leaf_max=request.param)
 
 
 def test_config1_instance_is_the_stored_one(config1_factor):
@@ -268,4 +270,26 @@ def test_config1_matches_oracle_windows(config1_factor, which):
         sel = np.isin(q.t_out, g["t_out"])
         err = np.abs(x[:, sel] - g["x"]).max()
     print(f"config1 {which}: max |x_gpu - x_oracle| = {err:.3e} V, stats {st}", flush=True)
+    assert err <= 1e-9
+
+
+def test_config1_regrouped_batched_matches_oracle_head(config1_factor):
+    """The 2000 sources regrouped into 64 subtasks (seeded), run batched: by
+    superposition (Sec. 3.1) their sum is the full response the oracle's
+    head window holds. A 64-right-hand-side pair on a factor with 13-14
+    levels and supernodes of up to 900 rows."""
+    import os
+    p, F = config1_factor
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "config1_head.npz"))
+    t_end = int(g["t_end"])
+    rng = np.random.default_rng(64)
+    src = p.sources
+    regrouped = I.Sources(node=src.node, amp=src.amp, delay=src.delay, rise=src.rise, width=src.width,
+                          fall=src.fall, group=rng.integers(0, 64, src.n_src).astype(np.int32))
+    q = I.Problem(p.name, p.netlist, regrouped, t_end, p.t_out[p.t_out <= t_end], p.probe)
+    _note("config1 regrouped into 64 subtasks, batched")
+    x, _, st = M.matex_transient(F, q, tol=1e-10 / 64, m_max=p.m_max, mode=M.MATEX_BATCHED)
+    err = np.abs(x.cpu().numpy() - g["x"]).max()
+    print(f"config1 regrouped batched: max |x_gpu - x_oracle| = {err:.3e} V, stats {st}", flush=True)
+    assert st["subtasks"] == 64
     assert err <= 1e-9
