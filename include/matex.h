@@ -48,7 +48,9 @@ typedef enum {
     MATEX_E_OOM = 3,         /* host or device allocation failed                  */
     MATEX_E_HIP = 4,         /* a HIP runtime call failed                         */
     MATEX_E_NOCONV = 5,      /* estimate still >= tol at m_max (and at h_min)     */
-    MATEX_E_UNSUPPORTED = 6  /* valid request outside what the library implements */
+    MATEX_E_UNSUPPORTED = 6, /* valid request outside what the library implements */
+    MATEX_E_NONFINITE = 7    /* a result came out NaN or infinite (outputs are
+                                written; the text names which ones)            */
 } matex_status;
 
 typedef struct matex_factor_s* matex_factor_t;
@@ -249,7 +251,7 @@ typedef struct {
  * solve_pairs_g then count multi-right-hand-side pairs; bases, segments and
  * krylov_dims count per subtask.
  * Errors: MATEX_E_INVALID (also for an unknown mode), MATEX_E_NOCONV,
- * MATEX_E_OOM, MATEX_E_HIP.
+ * MATEX_E_OOM, MATEX_E_HIP, MATEX_E_NONFINITE (an output is NaN or Inf).
  */
 matex_status matex_transient(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
                              double* d_probe_out, double* d_final, matex_stats* stats,
@@ -300,7 +302,9 @@ matex_status matex_transient_many(int32_t n_inst, const matex_factor_t* f, const
  * step's estimate relative to the largest jump norm ||C^-1 dJ/dy(t_s)||_2
  * (about 1e-11 is the practical floor), o->m_max must be <= 30, o->mode and
  * o->output_droop are ignored. Synchronises `stream`.
- * Errors: MATEX_E_INVALID, MATEX_E_NOCONV, MATEX_E_OOM, MATEX_E_HIP.
+ * Errors: MATEX_E_INVALID, MATEX_E_NOCONV, MATEX_E_OOM, MATEX_E_HIP,
+ * MATEX_E_NONFINITE (a gradient is NaN or Inf, e.g. from a non-finite
+ * d_dJdx; the gradients are still written).
  */
 matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
                            const double* d_dJdx, double* d_grad_amp, double* d_grad_c,

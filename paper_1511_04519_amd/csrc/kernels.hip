@@ -817,6 +817,14 @@ __global__ void k_scatter_perm(int64_t n, const int32_t* perm, const double* src
         dst[perm[k] + c * ldd] = src[k + c * lds_];
 }
 
+__global__ void k_flag_nonfinite(int64_t count, const double* __restrict__ a, int32_t* flag)
+{
+    bool bad = false;
+    for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < count; r += int64_t(gridDim.x) * 256)
+        bad |= !isfinite(a[r]);
+    if (bad) *flag = 1;
+}
+
 __global__ void k_vdd_minus(int64_t count, double vdd, double* buf)
 {
     for (int64_t r = int64_t(blockIdx.x) * 256 + threadIdx.x; r < count; r += int64_t(gridDim.x) * 256)
@@ -1376,6 +1384,11 @@ void launch_scatter_perm(int64_t n, const int32_t* perm, const double* src, doub
                          int64_t ld_src, int64_t ld_dst, int ncols, hipStream_t st)
 {
     k_scatter_perm<<<dim3(grid_for(n), ncols), 256, 0, st>>>(n, perm, src, dst, ld_src, ld_dst, ncols);
+}
+
+void launch_flag_nonfinite(int64_t count, const double* a, int32_t* flag, hipStream_t st)
+{
+    if (count > 0) k_flag_nonfinite<<<grid_for(count), 256, 0, st>>>(count, a, flag);
 }
 
 void launch_vdd_minus(int64_t count, double vdd, double* buf, hipStream_t st)

@@ -212,5 +212,7 @@ void launch_gather_perm(int64_t n, const int32_t* perm, const double* src, doubl
 void launch_scatter_perm(int64_t n, const int32_t* perm, const double* src, double* dst,
                          int64_t ld_src, int64_t ld_dst, int ncols, hipStream_t st);
 void launch_vdd_minus(int64_t count, double vdd, double* buf, hipStream_t st);
+// *flag = 1 if some a[i], i < count, is NaN or infinite (flag untouched otherwise).
+void launch_flag_nonfinite(int64_t count, const double* a, int32_t* flag, hipStream_t st);
 
 }  // namespace matex

@@ -22,6 +22,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "../../include/matex.h"
@@ -133,6 +134,24 @@ struct StageRing {
 double now_s()
 {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// Names of the arrays (count, device pointer) holding a NaN or an infinite
+// value; empty when all are finite. Synchronises st.
+std::string nonfinite_arrays(const std::vector<std::tuple<const char*, int64_t, const double*>>& arrs,
+                             hipStream_t st)
+{
+    DevMem flags(sizeof(int32_t) * std::max<size_t>(1, arrs.size()));
+    HIPCHK(hipMemsetAsync(flags.p, 0, flags.bytes, st));
+    for (size_t k = 0; k < arrs.size(); ++k)
+        if (std::get<2>(arrs[k])) launch_flag_nonfinite(std::get<1>(arrs[k]), std::get<2>(arrs[k]), flags.as<int32_t>() + k, st);
+    std::vector<int32_t> h(arrs.size(), 0);
+    if (!h.empty()) HIPCHK(hipMemcpyAsync(h.data(), flags.p, sizeof(int32_t) * h.size(), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::string bad;
+    for (size_t k = 0; k < arrs.size(); ++k)
+        if (h[k]) bad += std::string(bad.empty() ? "" : ", ") + std::get<0>(arrs[k]);
+    return bad;
 }
 
 }  // namespace
@@ -1865,6 +1884,20 @@ static matex_status check_problem(matex_factor_t f, const matex_problem* p, cons
     return MATEX_OK;
 }
 
+// MATEX_E_NONFINITE if a probe output or the final state is NaN or infinite.
+static matex_status check_outputs(const matex_problem* p, int64_t n, const double* d_probe_out,
+                                  const double* d_final, hipStream_t st)
+{
+    try {
+        const std::string bad = nonfinite_arrays(
+            {{"probe outputs", int64_t(p->n_probe) * p->n_out, d_probe_out}, {"final state", n, d_final}}, st);
+        if (!bad.empty()) return fail(MATEX_E_NONFINITE, "non-finite values in the " + bad);
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    }
+    return MATEX_OK;
+}
+
 extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p,
                                         const matex_run_opts* o, double* d_probe_out,
                                         double* d_final, matex_stats* stats, void* stream)
@@ -1901,7 +1934,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
         }
         S.seconds = now_s() - t_start;
         if (stats) *stats = S;
-        return MATEX_OK;
+        return check_outputs(p, n, d_probe_out, d_final, st);
     }
     try {
         transient_plain(f, p, o, groups, h_min, shift_ratio, trace, d_probe_out, d_final, S, st, nullptr);
@@ -1914,7 +1947,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     }
     S.seconds = now_s() - t_start;
     if (stats) *stats = S;
-    return MATEX_OK;
+    return check_outputs(p, n, d_probe_out, d_final, st);
 }
 
 extern "C" matex_status matex_transient_many(int32_t n_inst, const matex_factor_t* f,
@@ -2311,7 +2344,9 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
         if (d_grad_c) launch_scatter_perm(n, f->d_perm.as<int32_t>(), gcp.as<double>(), d_grad_c, n, n, 1, st);
         HIPCHK(hipGetLastError());
         HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipStreamSynchronize(st));
+        const std::string bad = nonfinite_arrays(
+            {{"amplitude gradients", n_src, d_grad_amp}, {"capacitance gradients", n, d_grad_c}}, st);
+        if (!bad.empty()) return fail(MATEX_E_NONFINITE, "non-finite values in the " + bad);
     } catch (const NoConv& e) {
         return fail(MATEX_E_NOCONV, "forward run for the capacitance gradients: " + e.msg);
     } catch (const HipError& e) {

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmatex.so")
 
 MATEX_OK, MATEX_E_INVALID, MATEX_E_NOT_SPD, MATEX_E_OOM, MATEX_E_HIP, MATEX_E_NOCONV, \
-    MATEX_E_UNSUPPORTED = range(7)
+    MATEX_E_UNSUPPORTED, MATEX_E_NONFINITE = range(8)
 MATEX_PLAIN, MATEX_BATCHED = 0, 1
 
 _i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p

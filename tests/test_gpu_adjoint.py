@@ -167,3 +167,17 @@ def test_adjoint_capacitances_full_grid_against_forward_differences():
         fd = -float(np.sum(w * (ys[0] - ys[1]))) / (2e-4 * c[i])
         print(f"node {i}: adjoint {gc[i]:.9e} differences {fd:.9e}", flush=True)
         assert abs(fd - gc[i]) <= 1e-5 * np.abs(gc).max()
+
+
+def test_adjoint_nonfinite_input_is_reported():
+    """A NaN in dJ/dx makes gradients NaN: the call says so
+    (MATEX_E_NONFINITE) instead of returning MATEX_OK with NaN."""
+    _note("adjoint with a NaN in dJ/dx")
+    p = I.small(606, nx=6, ny=5, n_src=3, t_end=1 * I.NS)
+    F = M.matex_factor(p.netlist, GAMMA)
+    w = _weights(p, 5, 606)
+    w[0, 10] = np.nan
+    with pytest.raises(M.MatexError) as e:
+        M.matex_adjoint(F, p, _dev(w), tol=1e-10, m_max=30, grad_c=True)
+    assert e.value.status == M.MATEX_E_NONFINITE
+    assert "amplitude gradients" in str(e.value)

@@ -41,18 +41,20 @@ def test_noalloc_solve_matches_matex_solve_twice_second_smaller():
 
 
 def test_noalloc_solve_refuses_a_factor_beyond_its_scratch():
-    # 3 n + n_upd > 8 Mi doubles on the 1M-node grid with large leaves
+    """The 1M-node grid with one-node leaves needs 3 n + n_upd = 8.52 Mi
+    doubles, beyond the 8 Mi of the scratch: refused before device work."""
     p = I.small(33, layers=1, nx=8, ny=8, n_src=1)
     F = M.matex_factor(p.netlist, 1e-11)
     assert 3 * F.info["n"] + F.info["n_upd"] <= (8 << 20)
     q = I.config2()
-    F2 = M.matex_factor(q.netlist, q.gamma, leaf_max=64)
+    F2 = M.matex_factor(q.netlist, q.gamma, leaf_max=1, n_shifts=1)
     need = 3 * F2.info["n"] + F2.info["n_upd"]
+    assert need > (8 << 20), need
     b = torch.zeros(q.netlist.n, dtype=torch.float64, device="cuda")
-    x = torch.zeros_like(b)
-    if need <= (8 << 20):
-        pytest.skip(f"this factor fits the scratch ({need} doubles)")
+    x = torch.full_like(b, 7.0)
     with pytest.raises(M.MatexError) as e:
         M.matex_solve_noalloc(F2, 0, b, x)
     assert e.value.status == M.MATEX_E_INVALID
     assert "64 MiB" in str(e.value)
+    torch.cuda.synchronize()
+    assert bool((x == 7.0).all())   # nothing written
