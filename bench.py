@@ -28,9 +28,13 @@ threads), and the oracle's trapezoidal rule at a fixed 10 ps step (the
 paper's comparator) on the same window; the oracle's factors (those of the
 trapezoidal rule too) are built in threads while the GPU runs and are
 excluded, as on the GPU.
+trapezoidal: the trapezoidal rule at a fixed 10 ps step (the paper's
+comparator) on the same workload, its time and its error.
 config1: context, the 2 x 300 x 300 grid (180k nodes) in plain mode, run
 once, with its oracle windows and its one-vector pair (a cache-resident
 factor: 130 MB against the 256 MB Infinity Cache).
+config3_uneven: the 128 uneven meshes (10k to 300k nodes, own factor each)
+over their first nanosecond, concurrently and one at a time.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --pairs-only   (the profiling run of the sweep kernels)
@@ -265,6 +269,67 @@ def config1_context(tol):
             "pair1": roof}
 
 
+def tr_comparator(p, batched_s, gold_dir):
+    """The trapezoidal rule at a fixed 10 ps step (Eq. 2; the comparator of
+    the paper's Tab. 3) on the same workload, all sources together: time,
+    node-steps/s and its distance from the oracle's windows."""
+    import torch
+    from paper_1511_04519_amd import instances as I
+    from paper_1511_04519_amd import matex as M
+    h = 10 * I.PS
+    t0 = time.time()
+    F = M.matex_factor(p.netlist, 0.5 * h * 1e-15, n_shifts=1)
+    fs = time.time() - t0
+    M.matex_trapezoidal(F, p, h, final=False)   # warm
+    torch.cuda.synchronize()
+    t0 = time.time()
+    x, _, st = M.matex_trapezoidal(F, p, h, final=False)
+    torch.cuda.synchronize()
+    dt = time.time() - t0
+    err = windows_error(x.cpu().numpy(), gold_dir, ("config2_head.npz", "config2_mid.npz"), p.t_out)
+    return {"h_ps": 10, "steps": st["segments"], "seconds": round(dt, 3), "factor_s": round(fs, 2),
+            "node_steps_per_s": p.netlist.n * p.t_out.size / dt,
+            "max_abs_err_vs_oracle": err,
+            "batched_matex_speedup_vs_tr": round(dt / batched_s, 3)}
+
+
+def config3_uneven(window_ps, tol):
+    """The 128 uneven meshes (own factor each) over their first window_ps:
+    advanced concurrently (matex_transient_many, 16 streams) and one at a
+    time; node-steps/s = sum of n * N_out over the instances / seconds."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import torch
+    from paper_1511_04519_amd import instances as I
+    from paper_1511_04519_amd import matex as M
+    T = window_ps * I.PS
+    probs = []
+    for k in range(128):
+        p = I.config3(k)
+        probs.append(I.Problem(p.name, p.netlist, p.sources, T, p.t_out[p.t_out <= T], p.probe))
+    t0 = time.time()
+    with ThreadPoolExecutor(4) as ex:
+        factors = list(ex.map(lambda q: M.matex_factor(q.netlist, q.gamma), probs))
+    fs = time.time() - t0
+    work = sum(q.netlist.n * q.t_out.size for q in probs)
+    torch.cuda.synchronize()
+    t0 = time.time()
+    res = M.matex_transient_many(factors, probs, tol=tol, m_max=20, n_streams=16, final=False)
+    torch.cuda.synchronize()
+    tc = time.time() - t0
+    t0 = time.time()
+    one = [M.matex_transient(F, q, tol=tol, m_max=20, final=False) for F, q in zip(factors, probs)]
+    torch.cuda.synchronize()
+    ts = time.time() - t0
+    same = all(torch.equal(a[0], b[0]) for a, b in zip(res, one))
+    return {"instances": 128, "window_ps": window_ps, "nodes": int(sum(q.netlist.n for q in probs)),
+            "sources": int(sum(q.sources.n_src for q in probs)), "factor_s": round(fs, 1), "tol": tol,
+            "concurrent_s": round(tc, 3), "one_at_a_time_s": round(ts, 3),
+            "concurrent_node_steps_per_s": work / tc, "one_at_a_time_node_steps_per_s": work / ts,
+            "speedup": round(ts / tc, 3), "identical_results": bool(same),
+            "bases": int(sum(r[2]["bases"] for r in res))}
+
+
 def pairs_only():
     """The profiling run for the sweep kernels' counters: 1 + 50 one-vector
     pairs on the 180k-node grid, 1 + 20 pairs with 64 right-hand sides on the
@@ -300,6 +365,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-config1", action="store_true")
+    ap.add_argument("--no-tr", action="store_true")
+    ap.add_argument("--config3-window-ps", type=int, default=1000,
+                    help="window of the 128-mesh uneven batch (0 = skip it)")
     ap.add_argument("--pairs-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -379,9 +447,18 @@ def main():
     a = torch.ones(2 ** 25, dtype=torch.float64, device="cuda")
     torch.empty_like(a).copy_(a)
     torch.cuda.synchronize()
+    F_info = F.info
+    schedule = M.matex_factor_describe(F).splitlines()
     del F
 
+    tr = None if args.no_tr else tr_comparator(p, dt, gold_dir)
+    if tr is not None:
+        print(f"[bench] trapezoidal 10 ps: {tr['seconds']:.2f} s", flush=True)
     c1 = None if args.no_config1 else config1_context(1e-10)
+    c3 = config3_uneven(args.config3_window_ps, 1e-10) if args.config3_window_ps > 0 else None
+    if c3 is not None:
+        print(f"[bench] uneven batch: concurrent {c3['concurrent_s']:.2f} s, one at a time "
+              f"{c3['one_at_a_time_s']:.2f} s", flush=True)
     cpu_line = cpu.finish() if cpu is not None else None
 
     line = {
@@ -394,8 +471,10 @@ def main():
                    "tol": tol, "gamma": p.gamma, "m_max": p.m_max, "factor_s": round(factor_s, 2),
                    "segments": st["segments"], "bases": st["bases"],
                    "pairs_64rhs": st["solve_pairs_m"] + st["solve_pairs_g"],
-                   "krylov_dims": st["krylov_dims"]},
-        "plain": plain, "parity": parity, "roofline": roof, "pair1": pair1, "config1": c1,
+                   "krylov_dims": st["krylov_dims"], "seconds_tune": round(F_info["seconds_tune"], 3),
+                   "batched_schedule": schedule},
+        "plain": plain, "parity": parity, "roofline": roof, "pair1": pair1, "trapezoidal": tr,
+        "config1": c1, "config3_uneven": c3,
         "cpu_baseline": cpu_line,
     }
     print(json.dumps(line), flush=True)

@@ -86,6 +86,16 @@ typedef struct {
                                 k > 0 = at most k (levels whose supernodes
                                 have more than 64 columns or 256 rows are
                                 never taken)                                   */
+    int32_t batched_schedule; /* schedule of the multi-right-hand-side sweeps:
+                                0 = autotuned at factor time (per level, the
+                                fastest of split tasks over 64, 128 or 256
+                                panel columns/rows and, on levels of
+                                supernodes of at most 32 columns, one
+                                wavefront per supernode, timed on the factor
+                                of C + gamma G); 1 = fixed (256-column split
+                                tasks on every level); 2 = fixed (one
+                                wavefront per supernode where allowed, else
+                                64-column split tasks)                        */
 } matex_factor_opts;
 
 typedef struct {
@@ -108,6 +118,7 @@ typedef struct {
                                 the supernodal panels)                         */
     int64_t n_upd;           /* forward update slots per right-hand side (the
                                 off-diagonal rows of all supernodes)           */
+    double seconds_tune;     /* device time spent choosing the batched schedule */
 } matex_factor_info;
 
 /*
@@ -125,6 +136,10 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
                           void* stream, matex_factor_t* out);
 matex_status matex_factor_free(matex_factor_t f);
 matex_status matex_factor_get_info(matex_factor_t f, matex_factor_info* info);
+/* Text description of the factor's sweep schedules (one line per level: its
+ * supernodes and the multi-right-hand-side schedule kept) into buf
+ * (NUL-terminated, truncated to len); returns the full length. */
+size_t matex_factor_describe(matex_factor_t f, char* buf, size_t len);
 
 /*
  * matex_solve - one forward/backward substitution pair (Alg. 1, the step
@@ -256,6 +271,24 @@ typedef struct {
 matex_status matex_transient(matex_factor_t f, const matex_problem* p, const matex_run_opts* o,
                              double* d_probe_out, double* d_final, matex_stats* stats,
                              void* stream);
+
+/*
+ * matex_trapezoidal - the trapezoidal rule (Eq. 2) at a fixed step h, the
+ * comparator of the paper's runtime tables (Sec. 4.3, Tab. 3: TR at 10 ps):
+ * (C/h + G/2) y_{k+1} = (C/h - G/2) y_k + (i(t_k) + i(t_{k+1})) / 2 in the
+ * droop form, y(0) = G^-1 i(0), steps at t_k = k h up to p->t_end, the
+ * pulses sampled at the step ends only (no cut at transition spots, as a
+ * fixed-step run does). f must be a factor made with gamma = h / 2 (any
+ * n_shifts): C + (h/2) G = h (C/h + G/2) is then its first shift, G its last.
+ * h_fs > 0 must divide t_end and every output time. o: only o->output_droop
+ * is read (o->tol, o->m_max, o->mode are ignored). Outputs as
+ * matex_transient (all sources together; groups ignored). stats: segments =
+ * solve_pairs_m = steps. Synchronises `stream`.
+ * Errors: MATEX_E_INVALID (also for a factor of another gamma), MATEX_E_OOM,
+ * MATEX_E_HIP, MATEX_E_NONFINITE.
+ */
+matex_status matex_trapezoidal(matex_factor_t f, const matex_problem* p, int64_t h_fs, const matex_run_opts* o,
+                               double* d_probe_out, double* d_final, matex_stats* stats, void* stream);
 
 /*
  * matex_transient_many - matex_transient for n_inst independent problems,

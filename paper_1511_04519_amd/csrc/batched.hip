@@ -269,6 +269,142 @@ __global__ __launch_bounds__(256) void kb_bwd_reduce(DevSym s, const BRed* __res
     }
 }
 
+// ------------------------------------------------ wavefront-per-supernode
+
+// Levels whose supernodes have at most WNC columns: one wavefront per
+// supernode, lane r owning right-hand side r, so every vector row moves as
+// one 512-byte line. btilde (forward) and the column sums (backward) stay in
+// registers; the panel goes through wavefront-private LDS 64 rows at a time
+// and is read as broadcasts. No block barrier: four independent wavefronts
+// per block. The sums run over k (forward) and the panel rows (backward) in
+// increasing order, as the block kernels' unsplit tasks do, so both give the
+// same bits.
+constexpr int WPF = 8;   // rows whose right-hand-side loads are issued together
+
+// Panel rows i0 .. i0 + 63 (zeros past nr) of columns 0 .. nc - 1 into
+// Ws[k * 64 + i - i0]; column k's rows are contiguous, one load per lane.
+__device__ inline void stage_panel_rows(const double* __restrict__ Wp, int64_t ld, int i0, int nr, int nc, int lane,
+                                        double* Ws)
+{
+    const int i = i0 + lane;
+    const double* src = Wp + (i < nr ? i : 0);
+#pragma unroll 4
+    for (int k = 0; k < nc; ++k) {
+        const double v = src[int64_t(k) * ld];
+        Ws[k * 64 + lane] = i < nr ? v : 0.0;
+    }
+}
+
+template <int WNC>
+__global__ __launch_bounds__(256) void kb_fwd_wave(DevSym s, BatchAssembly as, const int32_t* __restrict__ sns,
+                                                   int count, int R, const double* __restrict__ W,
+                                                   const double* __restrict__ B,
+                                                   const double* __restrict__ scale, double* y, double* U)
+{
+    __shared__ double Wsh[4][WNC * 64];
+    const int wv = threadIdx.x >> 6, r = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wv;
+    if (idx >= count) return;
+    const int sn = sns[idx];
+    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    const int pb = as.pos_base[sn];
+    const int64_t ld = dpanel_ld(nr), u = s.u[sn];
+    const double* Wp = W + s.w[sn];
+    double* Ws = Wsh[wv];
+    const bool on = r < R;
+    double bt[WNC];
+#pragma unroll
+    for (int k = 0; k < WNC; ++k) {
+        double v = 0.0;
+        if (k < nc && on) {
+            const int64_t o = int64_t(c0 + k) * R + r;
+            v = (scale ? B[o] * scale[c0 + k] : B[o]) - pull(as, pb + k, R, r, U);
+        }
+        bt[k] = v;
+    }
+    for (int i0 = 0; i0 < nr; i0 += 64) {
+        wave_sync();
+        stage_panel_rows(Wp, ld, i0, nr, nc, r, Ws);
+        wave_sync();
+        const int i1 = min(nr, i0 + 64);
+        for (int ib = i0; ib < i1; ib += WPF) {
+            // the children's updates on the off rows of these rows, loaded together
+            double pu[WPF];
+#pragma unroll
+            for (int q = 0; q < WPF; ++q) {
+                const int i = ib + q;
+                pu[q] = (i < i1 && i >= nc && on) ? pull(as, pb + i, R, r, U) : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < WPF; ++q) {
+                const int i = ib + q;
+                if (i >= i1) break;
+                const int kmax = i < nc ? i + 1 : nc;
+                const double* wr = Ws + (i - i0);
+                double acc = 0.0;
+#pragma unroll
+                for (int k = 0; k < WNC; ++k)
+                    if (k < kmax) acc += wr[k * 64] * bt[k];
+                if (on) {
+                    if (i < nc) y[int64_t(c0 + i) * R + r] = acc;
+                    else U[(u + i - nc) * R + r] = pu[q] + acc;
+                }
+            }
+        }
+    }
+}
+
+template <int WNC>
+__global__ __launch_bounds__(256) void kb_bwd_wave(DevSym s, const int32_t* __restrict__ sns, int count, int R,
+                                                   const double* __restrict__ W, const double* y, double* x)
+{
+    __shared__ double Wsh[4][WNC * 64];
+    const int wv = threadIdx.x >> 6, r = threadIdx.x & 63;
+    const int idx = blockIdx.x * 4 + wv;
+    if (idx >= count) return;
+    const int sn = sns[idx];
+    const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
+    const int64_t ld = dpanel_ld(nr);
+    const int32_t* roff = s.rows + s.roff[sn];
+    const double* Wp = W + s.w[sn];
+    double* Ws = Wsh[wv];
+    const bool on = r < R;
+    double acc[WNC];
+#pragma unroll
+    for (int c = 0; c < WNC; ++c) acc[c] = 0.0;
+    for (int i0 = 0; i0 < nr; i0 += 64) {
+        wave_sync();
+        stage_panel_rows(Wp, ld, i0, nr, nc, r, Ws);
+        wave_sync();
+        const int i1 = min(nr, i0 + 64);
+        for (int ib = i0; ib < i1; ib += WPF) {
+            // g = [y_s ; -x(off rows)] for these rows, loaded together
+            double g[WPF];
+#pragma unroll
+            for (int q = 0; q < WPF; ++q) {
+                const int i = ib + q;
+                double v = 0.0;
+                if (i < i1 && on) v = i < nc ? y[int64_t(c0 + i) * R + r] : -x[int64_t(roff[i - nc]) * R + r];
+                g[q] = v;
+            }
+#pragma unroll
+            for (int q = 0; q < WPF; ++q) {
+                const int i = ib + q;
+                if (i >= i1) break;
+                const double* wr = Ws + (i - i0);
+#pragma unroll
+                for (int c = 0; c < WNC; ++c)
+                    if (c < nc && c <= i) acc[c] += wr[c * 64] * g[q];
+            }
+        }
+    }
+    if (on) {
+#pragma unroll
+        for (int c = 0; c < WNC; ++c)
+            if (c < nc) x[int64_t(c0 + c) * R + r] = acc[c];
+    }
+}
+
 // Column-major natural-order right-hand sides (ld n) to row-interleaved
 // permuted order and back: dst[k * R + r] = src[perm[k] + r * n] and
 // dst[perm[k] + r * n] = src[k * R + r].
@@ -744,6 +880,14 @@ void launch_b_forward(const DevSym& s, const BatchAssembly& as, const BatchLevel
                       const double* W, const double* B, const double* scale, double* y,
                       double* U, double* P, hipStream_t st)
 {
+    if (lv.fwave) {
+        if (lv.wave_nc <= 16)
+            kb_fwd_wave<16><<<(lv.n_fwave + 3) / 4, 256, 0, st>>>(s, as, lv.fwave, lv.n_fwave, R, W, B, scale, y, U);
+        else
+            kb_fwd_wave<WAVE_MAX_NC><<<(lv.n_fwave + 3) / 4, 256, 0, st>>>(s, as, lv.fwave, lv.n_fwave, R, W, B, scale,
+                                                                           y, U);
+        return;
+    }
     kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, as, lv.fwd, R, W, B, scale, y, U, P);
     if (lv.n_fred) kb_fwd_reduce<<<lv.n_fred, 256, 0, st>>>(s, as, lv.fred, R, P, y, U);
 }
@@ -751,6 +895,13 @@ void launch_b_forward(const DevSym& s, const BatchAssembly& as, const BatchLevel
 void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
                        const double* y, double* x, double* P, hipStream_t st)
 {
+    if (lv.bwave) {
+        if (lv.wave_nc <= 16)
+            kb_bwd_wave<16><<<(lv.n_bwave + 3) / 4, 256, 0, st>>>(s, lv.bwave, lv.n_bwave, R, W, y, x);
+        else
+            kb_bwd_wave<WAVE_MAX_NC><<<(lv.n_bwave + 3) / 4, 256, 0, st>>>(s, lv.bwave, lv.n_bwave, R, W, y, x);
+        return;
+    }
     kb_bwd<<<lv.n_bwd, 256, 0, st>>>(s, lv.bwd, R, W, y, x, P);
     if (lv.n_bred) kb_bwd_reduce<<<lv.n_bred, 256, 0, st>>>(s, lv.bred, R, P, x);
 }

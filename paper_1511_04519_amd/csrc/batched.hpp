@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cstdint>
 
 #include "kernels.hpp"
@@ -13,7 +14,9 @@ constexpr int RMAX = 64;           // subtasks per batch (one wavefront lane eac
 constexpr int BR = 64;             // panel rows / columns per batched sweep task
 constexpr int B_RED_BLOCKS = 4096; // blocks of the batched reductions
 
-constexpr int KCHUNK = 256;        // panel columns (forward) / rows (backward) per task
+// panel columns (forward) / rows (backward) per task of the split schedules
+constexpr std::array<int32_t, 3> BATCH_CHUNKS = {64, 128, 256};
+constexpr int WAVE_MAX_NC = 32;    // widest supernode a wavefront sweeps alone
 constexpr int PSLOT = 64 * RMAX;   // doubles of one partial-result slot (64 x RMAX)
 
 // One block of a batched sweep: panel rows (forward) or columns (backward)
@@ -49,6 +52,13 @@ struct BatchLevel {
     int32_t n_bwd;
     const BRed* bred;
     int32_t n_bred;
+    // levels of narrow supernodes (at most WAVE_MAX_NC columns): the
+    // supernodes, swept one wavefront each (null: the block tasks above)
+    const int32_t* fwave = nullptr;
+    int32_t n_fwave = 0;
+    const int32_t* bwave = nullptr;
+    int32_t n_bwave = 0;
+    int32_t wave_nc = 0;   // the level's widest supernode (selects the kernel's register tile)
 };
 
 // Multi-right-hand-side pair, all n x R arrays row-interleaved (x[i * R + r]).

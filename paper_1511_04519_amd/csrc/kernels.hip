@@ -817,6 +817,46 @@ __global__ void k_scatter_perm(int64_t n, const int32_t* perm, const double* src
         dst[perm[k] + c * ldd] = src[k + c * lds_];
 }
 
+// ---------------------------------------------------- trapezoidal rule
+
+// Unit trapezoidal pulse at t (fs): 0 up to the delay, a linear rise, the
+// flat top, a linear fall, 0 afterwards (one period).
+__device__ inline double unit_pulse(int64_t t, int64_t d, int64_t r, int64_t w, int64_t f)
+{
+    if (t > d && t <= d + r) return double(t - d) / double(r);
+    if (t > d + r && t <= d + r + w) return 1.0;
+    if (t > d + r + w && t < d + r + w + f) return 1.0 - double(t - d - r - w) / double(f);
+    return 0.0;
+}
+
+// Right-hand side of one trapezoidal step (Eq. 2 times h): rhs = C y - (h/2) G y
+// + (h/2) (i(t0) + i(t1)), every row in the factor's order; the sources of
+// row r are sptr[r] .. sptr[r + 1] (in a fixed order).
+__global__ void k_tr_rhs(int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                         const double* __restrict__ gv, const double* __restrict__ cperm,
+                         const double* __restrict__ y, double hh, int64_t t0, int64_t t1,
+                         const int32_t* __restrict__ sptr, const double* __restrict__ amp,
+                         const int64_t* __restrict__ sd, const int64_t* __restrict__ sr,
+                         const int64_t* __restrict__ sw, const int64_t* __restrict__ sf, double* rhs)
+{
+    for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+        double gy = 0.0;
+        for (int q = rp[i]; q < rp[i + 1]; ++q) gy += gv[q] * y[ci[q]];
+        double src = 0.0;
+        for (int k = sptr[i]; k < sptr[i + 1]; ++k)
+            src += amp[k] * (unit_pulse(t0, sd[k], sr[k], sw[k], sf[k]) + unit_pulse(t1, sd[k], sr[k], sw[k], sf[k]));
+        rhs[i] = (cperm[i] * y[i] - hh * gy) + hh * src;
+    }
+}
+
+// out[p * n_out + col] = y[probe_perm[p]]
+__global__ void k_gather_probes(int n_probe, const int32_t* __restrict__ probe_perm, const double* __restrict__ y,
+                                double* out, int32_t n_out, int32_t col)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < n_probe) out[int64_t(p) * n_out + col] = y[probe_perm[p]];
+}
+
 __global__ void k_flag_nonfinite(int64_t count, const double* __restrict__ a, int32_t* flag)
 {
     bool bad = false;
@@ -1384,6 +1424,21 @@ void launch_scatter_perm(int64_t n, const int32_t* perm, const double* src, doub
                          int64_t ld_src, int64_t ld_dst, int ncols, hipStream_t st)
 {
     k_scatter_perm<<<dim3(grid_for(n), ncols), 256, 0, st>>>(n, perm, src, dst, ld_src, ld_dst, ncols);
+}
+
+void launch_tr_rhs(int64_t n, const int32_t* rp, const int32_t* ci, const double* gv, const double* cperm,
+                   const double* y, double hh, int64_t t0, int64_t t1, const int32_t* sptr, const double* amp,
+                   const int64_t* sd, const int64_t* sr, const int64_t* sw, const int64_t* sf, double* rhs,
+                   hipStream_t st)
+{
+    k_tr_rhs<<<grid_for(n), 256, 0, st>>>(n, rp, ci, gv, cperm, y, hh, t0, t1, sptr, amp, sd, sr, sw, sf, rhs);
+}
+
+void launch_gather_probes(int n_probe, const int32_t* probe_perm, const double* y, double* out, int32_t n_out,
+                          int32_t col, hipStream_t st)
+{
+    if (n_probe > 0)
+        k_gather_probes<<<(n_probe + 255) / 256, 256, 0, st>>>(n_probe, probe_perm, y, out, n_out, col);
 }
 
 void launch_flag_nonfinite(int64_t count, const double* a, int32_t* flag, hipStream_t st)

@@ -212,6 +212,15 @@ void launch_gather_perm(int64_t n, const int32_t* perm, const double* src, doubl
 void launch_scatter_perm(int64_t n, const int32_t* perm, const double* src, double* dst,
                          int64_t ld_src, int64_t ld_dst, int ncols, hipStream_t st);
 void launch_vdd_minus(int64_t count, double vdd, double* buf, hipStream_t st);
+// Trapezoidal rule: rhs = C y - hh G y + hh (i(t0) + i(t1)) (hh = h / 2; G in
+// CSR in the factor's order; the pulses of row r are sptr[r] .. sptr[r + 1]).
+void launch_tr_rhs(int64_t n, const int32_t* rp, const int32_t* ci, const double* gv, const double* cperm,
+                   const double* y, double hh, int64_t t0, int64_t t1, const int32_t* sptr, const double* amp,
+                   const int64_t* sd, const int64_t* sr, const int64_t* sw, const int64_t* sf, double* rhs,
+                   hipStream_t st);
+// out[p * n_out + col] = y[probe_perm[p]], p < n_probe.
+void launch_gather_probes(int n_probe, const int32_t* probe_perm, const double* y, double* out, int32_t n_out,
+                          int32_t col, hipStream_t st);
 // *flag = 1 if some a[i], i < count, is NaN or infinite (flag untouched otherwise).
 void launch_flag_nonfinite(int64_t count, const double* a, int32_t* flag, hipStream_t st);
 

@@ -174,9 +174,15 @@ struct matex_factor_s {
     std::vector<LevelTasks> fwd, bwd;   // levels tree.n_levels .. n_levels - 1
     TreeTasks tree{};
     // batched (multi-subtask) sweeps
-    DevMem d_b_pos, d_b_cptr, d_b_cidx, d_b_ft, d_b_fr, d_b_bt, d_b_br;
+    DevMem d_b_pos, d_b_cptr, d_b_cidx, d_b_ft, d_b_fr, d_b_bt, d_b_br, d_b_wave;
     BatchAssembly bas{};
-    std::vector<BatchLevel> blevels;
+    std::vector<BatchLevel> blevels;               // the schedule in use, per level
+    struct BatchCand {
+        BatchLevel lv;
+        std::string name;
+    };
+    std::vector<std::vector<BatchCand>> bcand;     // candidates per level
+    std::vector<std::pair<int, int>> bchoice;      // forward, backward candidate kept
     int64_t b_slots = 0;   // partial-result slots one batched sweep needs
     DevSym dsym{};
     matex_factor_info info{};
@@ -185,7 +191,7 @@ struct matex_factor_s {
         for (const DevMem* m : {&d_c0, &d_nc, &d_nr, &d_roff, &d_w, &d_u, &d_rows, &d_child_ptr, &d_child_idx,
                                 &d_relidx, &d_perm, &d_iperm, &d_cperm, &d_grp, &d_gci, &d_gv, &d_fwd_tasks, &d_bwd_tasks, &d_fdesc, &d_gsrc, &d_tree_f, &d_tree_b,
                                 &d_tree_fblk, &d_tree_bblk, &d_tree_fdesc, &d_tree_trow, &d_b_pos,
-                                &d_b_cptr, &d_b_cidx, &d_b_ft, &d_b_fr, &d_b_bt, &d_b_br})
+                                &d_b_cptr, &d_b_cidx, &d_b_ft, &d_b_fr, &d_b_bt, &d_b_br, &d_b_wave})
             b += int64_t(m->bytes);
         for (const DevMem& m : d_W) b += int64_t(m.bytes);
         return b;
@@ -329,62 +335,176 @@ void build_tasks(matex_factor_s& F, int32_t subtree_limit)
         F.fwd.push_back(f);
         F.bwd.push_back(b);
     }
-    // batched sweeps: per level, forward blocks of 64 panel rows and
+    // batched sweeps: per level, candidate schedules of the 64-right-hand-side
+    // pair, picked by tune_batched: forward blocks of 64 panel rows and
     // backward blocks of 64 panel columns, each split into tasks of at most
-    // KCHUNK panel columns / rows whose partial results are summed
+    // `chunk` panel columns / rows whose partial results are summed (chunk
+    // 64, 128 or 256), and on levels of narrow supernodes one wavefront per
+    // supernode
     {
         std::vector<BTask> ft, bt;
         std::vector<BRed> fr, br;
-        std::vector<int64_t> fo(L + 1), fro(L + 1), bo(L + 1), bro(L + 1);
+        std::vector<int32_t> wv;
+        struct Off { int64_t f, fr, b, br; };
+        std::vector<std::vector<Off>> off(L);
+        std::vector<int64_t> wo(L, -1);
         for (int lv = 0; lv < L; ++lv) {
-            fo[lv] = int64_t(ft.size()); fro[lv] = int64_t(fr.size());
-            bo[lv] = int64_t(bt.size()); bro[lv] = int64_t(br.size());
-            int32_t fslots = 0, bslots = 0;
-            for (int32_t k : s.level_sn[lv]) {
-                const Supernode& q = s.sn[k];
-                for (int32_t r0 = 0; r0 < q.nr; r0 += BR) {
-                    const int32_t K = std::min(q.nc, r0 + BR);
-                    const int32_t nch = (K + KCHUNK - 1) / KCHUNK;
-                    if (nch == 1) {
-                        ft.push_back({k, r0, 0, K, -1});
-                    } else {
-                        fr.push_back({k, r0, fslots, nch});
-                        for (int32_t c = 0; c < nch; ++c)
-                            ft.push_back({k, r0, c * KCHUNK, std::min(K, (c + 1) * KCHUNK), fslots++});
+            for (int32_t chunk : BATCH_CHUNKS) {
+                Off o{int64_t(ft.size()), int64_t(fr.size()), int64_t(bt.size()), int64_t(br.size())};
+                int32_t fslots = 0, bslots = 0;
+                for (int32_t k : s.level_sn[lv]) {
+                    const Supernode& q = s.sn[k];
+                    for (int32_t r0 = 0; r0 < q.nr; r0 += BR) {
+                        const int32_t K = std::min(q.nc, r0 + BR);
+                        const int32_t nch = (K + chunk - 1) / chunk;
+                        if (nch == 1) {
+                            ft.push_back({k, r0, 0, K, -1});
+                        } else {
+                            fr.push_back({k, r0, fslots, nch});
+                            for (int32_t c = 0; c < nch; ++c)
+                                ft.push_back({k, r0, c * chunk, std::min(K, (c + 1) * chunk), fslots++});
+                        }
+                    }
+                    for (int32_t c0 = 0; c0 < q.nc; c0 += BR) {
+                        const int32_t nch = (q.nr - c0 + chunk - 1) / chunk;
+                        if (nch == 1) {
+                            bt.push_back({k, c0, c0, q.nr, -1});
+                        } else {
+                            br.push_back({k, c0, bslots, nch});
+                            for (int32_t c = 0; c < nch; ++c)
+                                bt.push_back({k, c0, c0 + c * chunk, std::min(q.nr, c0 + (c + 1) * chunk),
+                                              bslots++});
+                        }
                     }
                 }
-                for (int32_t c0 = 0; c0 < q.nc; c0 += BR) {
-                    const int32_t nch = (q.nr - c0 + KCHUNK - 1) / KCHUNK;
-                    if (nch == 1) {
-                        bt.push_back({k, c0, c0, q.nr, -1});
-                    } else {
-                        br.push_back({k, c0, bslots, nch});
-                        for (int32_t c = 0; c < nch; ++c)
-                            bt.push_back({k, c0, c0 + c * KCHUNK, std::min(q.nr, c0 + (c + 1) * KCHUNK),
-                                          bslots++});
-                    }
-                }
+                F.b_slots = std::max<int64_t>(F.b_slots, std::max(fslots, bslots));
+                off[lv].push_back(o);
             }
-            F.b_slots = std::max<int64_t>(F.b_slots, std::max(fslots, bslots));
+            off[lv].push_back({int64_t(ft.size()), int64_t(fr.size()), int64_t(bt.size()), int64_t(br.size())});
+            bool narrow = true;
+            for (int32_t k : s.level_sn[lv]) narrow = narrow && s.sn[k].nc <= WAVE_MAX_NC;
+            if (narrow && !s.level_sn[lv].empty()) {
+                wo[lv] = int64_t(wv.size());
+                wv.insert(wv.end(), s.level_sn[lv].begin(), s.level_sn[lv].end());
+            }
         }
-        fo[L] = int64_t(ft.size()); fro[L] = int64_t(fr.size());
-        bo[L] = int64_t(bt.size()); bro[L] = int64_t(br.size());
         if (fr.empty()) fr.push_back({0, 0, 0, 0});
         if (br.empty()) br.push_back({0, 0, 0, 0});
+        if (wv.empty()) wv.push_back(0);
         F.d_b_ft = upload(ft); F.d_b_fr = upload(fr); F.d_b_bt = upload(bt); F.d_b_br = upload(br);
+        F.d_b_wave = upload(wv);
+        F.bcand.assign(L, {});
         for (int lv = 0; lv < L; ++lv) {
-            BatchLevel b;
-            b.fwd = F.d_b_ft.as<BTask>() + fo[lv];
-            b.n_fwd = int32_t(fo[lv + 1] - fo[lv]);
-            b.fred = F.d_b_fr.as<BRed>() + fro[lv];
-            b.n_fred = int32_t(fro[lv + 1] - fro[lv]);
-            b.bwd = F.d_b_bt.as<BTask>() + bo[lv];
-            b.n_bwd = int32_t(bo[lv + 1] - bo[lv]);
-            b.bred = F.d_b_br.as<BRed>() + bro[lv];
-            b.n_bred = int32_t(bro[lv + 1] - bro[lv]);
-            F.blevels.push_back(b);
+            for (size_t v = 0; v + 1 < off[lv].size(); ++v) {
+                const Off& o = off[lv][v];
+                const Off& e = off[lv][v + 1];
+                BatchLevel b;
+                b.fwd = F.d_b_ft.as<BTask>() + o.f;
+                b.n_fwd = int32_t(e.f - o.f);
+                b.fred = F.d_b_fr.as<BRed>() + o.fr;
+                b.n_fred = int32_t(e.fr - o.fr);
+                b.bwd = F.d_b_bt.as<BTask>() + o.b;
+                b.n_bwd = int32_t(e.b - o.b);
+                b.bred = F.d_b_br.as<BRed>() + o.br;
+                b.n_bred = int32_t(e.br - o.br);
+                F.bcand[lv].push_back({b, "split" + std::to_string(BATCH_CHUNKS[v])});
+            }
+            if (wo[lv] >= 0) {
+                BatchLevel b = F.bcand[lv].back().lv;
+                b.fwave = b.bwave = F.d_b_wave.as<int32_t>() + wo[lv];
+                b.n_fwave = b.n_bwave = int32_t(s.level_sn[lv].size());
+                for (int32_t k : s.level_sn[lv]) b.wave_nc = std::max(b.wave_nc, s.sn[k].nc);
+                F.bcand[lv].push_back({b, "wave"});
+            }
+            // until tuned: the largest chunk (the candidate of fewest tasks)
+            F.blevels.push_back(F.bcand[lv][BATCH_CHUNKS.size() - 1].lv);
+            F.bchoice.push_back({int(BATCH_CHUNKS.size()) - 1, int(BATCH_CHUNKS.size()) - 1});
         }
     }
+}
+
+// The autotuner of the 64-right-hand-side pair: for every level, each
+// candidate schedule's forward and backward launches are timed on the
+// factor of C + gamma_0 G (HIP events on `st`, the best of a few repeats,
+// after one untimed launch), and the fastest forward and the fastest
+// backward are kept. The choice depends on the structure and the device
+// only; values do not change the timing (zero right-hand sides).
+void tune_batched(matex_factor_s& F, hipStream_t st)
+{
+    const int L = F.sym.n_levels;
+    const int R = RMAX;
+    const int64_t n = F.sym.n;
+    const double t0 = now_s();
+    DevMem B(sizeof(double) * size_t(n) * R), Y(sizeof(double) * size_t(n) * R), X(sizeof(double) * size_t(n) * R),
+        U(sizeof(double) * std::max<int64_t>(1, F.sym.n_upd) * R),
+        P(sizeof(double) * std::max<int64_t>(1, F.b_slots) * PSLOT);
+    for (DevMem* m : {&B, &Y, &X, &U}) HIPCHK(hipMemsetAsync(m->p, 0, m->bytes, st));
+    const double* W = F.d_W[0].as<double>();
+    const double* sc = F.d_cperm.as<double>();
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    constexpr int REPS = 3;
+    auto time_it = [&](auto&& launch) {
+        launch();
+        float best = 1e30f;
+        for (int r = 0; r < REPS; ++r) {
+            HIPCHK(hipEventRecord(e0, st));
+            launch();
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            best = std::min(best, ms);
+        }
+        return best;
+    };
+    for (int lv = 0; lv < L; ++lv) {
+        const auto& cand = F.bcand[lv];
+        int bf = 0, bb = 0;
+        float tf = 1e30f, tb = 1e30f;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            const BatchLevel& b = cand[c].lv;
+            const float f = time_it([&]() {
+                launch_b_forward(F.dsym, F.bas, b, R, W, B.as<double>(), sc, Y.as<double>(), U.as<double>(),
+                                 P.as<double>(), st);
+            });
+            const float g = time_it([&]() {
+                launch_b_backward(F.dsym, b, R, W, Y.as<double>(), X.as<double>(), P.as<double>(), st);
+            });
+            if (f < tf) { tf = f; bf = int(c); }
+            if (g < tb) { tb = g; bb = int(c); }
+        }
+        BatchLevel m = cand[size_t(bf)].lv;
+        const BatchLevel& mb = cand[size_t(bb)].lv;
+        m.bwd = mb.bwd; m.n_bwd = mb.n_bwd; m.bred = mb.bred; m.n_bred = mb.n_bred;
+        m.bwave = mb.bwave; m.n_bwave = mb.n_bwave;
+        m.fwave = cand[size_t(bf)].lv.fwave;
+        m.n_fwave = cand[size_t(bf)].lv.n_fwave;
+        m.wave_nc = std::max(cand[size_t(bf)].lv.wave_nc, mb.wave_nc);
+        F.blevels[size_t(lv)] = m;
+        F.bchoice[size_t(lv)] = {bf, bb};
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(hipStreamSynchronize(st));
+    F.info.seconds_tune = now_s() - t0;
+}
+
+// One line per level: the supernodes' widths and the schedules kept.
+std::string describe_batched(const matex_factor_s& F)
+{
+    std::string out;
+    for (int lv = 0; lv < F.sym.n_levels; ++lv) {
+        int mx = 0;
+        for (int32_t k : F.sym.level_sn[size_t(lv)]) mx = std::max(mx, F.sym.sn[size_t(k)].nc);
+        const auto& c = F.bcand[size_t(lv)];
+        out += "level " + std::to_string(lv) + ": " + std::to_string(F.sym.level_sn[size_t(lv)].size()) +
+               " supernodes (nc <= " + std::to_string(mx) + "), forward " +
+               c[size_t(F.bchoice[size_t(lv)].first)].name + ", backward " +
+               c[size_t(F.bchoice[size_t(lv)].second)].name + "\n";
+    }
+    return out;
 }
 
 // x = A_which^-1 (scale .* b), all in the permuted ordering. tmp: [n], upd: [n_upd].
@@ -722,6 +842,8 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
     int n_shifts = (opts && opts->n_shifts > 0) ? opts->n_shifts : 6;
     int leaf = (opts && opts->leaf_max > 0) ? opts->leaf_max : 16;
     const int32_t subtree = opts ? opts->subtree_levels : 0;
+    const int32_t bsched = opts ? opts->batched_schedule : 0;
+    if (bsched < 0 || bsched > 2) return fail(MATEX_E_INVALID, "batched_schedule must be 0, 1 or 2");
     if (n_shifts > 12) return fail(MATEX_E_INVALID, "n_shifts must be <= 12");
     try {
         auto F = std::make_unique<matex_factor_s>();
@@ -801,6 +923,14 @@ matex_status matex_factor(const matex_netlist* nl, double gamma, const matex_fac
                          F->d_rows.as<int32_t>(), F->d_child_ptr.as<int32_t>(),
                          F->d_child_idx.as<int32_t>(), F->d_relidx.as<int32_t>()};
         build_tasks(*F, subtree);
+        if (bsched == 0) tune_batched(*F, static_cast<hipStream_t>(stream));
+        if (bsched == 2)
+            for (int lv = 0; lv < F->sym.n_levels; ++lv) {
+                const int c = int(F->bcand[size_t(lv)].size()) - 1;
+                const int k = F->bcand[size_t(lv)][size_t(c)].name == "wave" ? c : 0;
+                F->blevels[size_t(lv)] = F->bcand[size_t(lv)][size_t(k)].lv;
+                F->bchoice[size_t(lv)] = {k, k};
+            }
         matex_factor_info& I = F->info;
         I.n = n;
         I.nnz_l = s.nnz_l;
@@ -830,6 +960,18 @@ matex_status matex_factor_free(matex_factor_t f)
 {
     delete f;
     return MATEX_OK;
+}
+
+size_t matex_factor_describe(matex_factor_t f, char* buf, size_t len)
+{
+    if (!f) return 0;
+    const std::string d = describe_batched(*f);
+    if (buf && len) {
+        const size_t k = std::min(len - 1, d.size());
+        std::memcpy(buf, d.data(), k);
+        buf[k] = 0;
+    }
+    return d.size();
 }
 
 matex_status matex_factor_get_info(matex_factor_t f, matex_factor_info* info)
@@ -1945,6 +2087,113 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
     } catch (const std::bad_alloc&) {
         return fail(MATEX_E_OOM, "host allocation failed");
     }
+    S.seconds = now_s() - t_start;
+    if (stats) *stats = S;
+    return check_outputs(p, n, d_probe_out, d_final, st);
+}
+
+// The trapezoidal rule at a fixed step (Eq. 2), the paper's comparator: every
+// step forms its right-hand side on the device (one fused kernel), then one
+// substitution pair with the factor of C + (h/2) G, then gathers the probes
+// when the step ends at an output time.
+extern "C" matex_status matex_trapezoidal(matex_factor_t f, const matex_problem* p, int64_t h_fs,
+                                          const matex_run_opts* o, double* d_probe_out, double* d_final,
+                                          matex_stats* stats, void* stream)
+{
+    const double t_start = now_s();
+    if (!d_probe_out || !o) return fail(MATEX_E_INVALID, "null argument");
+    matex_run_opts oo = *o;
+    oo.mode = MATEX_PLAIN;
+    if (!(oo.tol > 0.0)) oo.tol = 1.0;
+    if (oo.m_max < 1) oo.m_max = 1;
+    if (matex_status cs = check_problem(f, p, &oo)) return cs;
+    if (h_fs <= 0 || p->t_end % h_fs != 0) return fail(MATEX_E_INVALID, "h must be > 0 and divide t_end");
+    for (int32_t k = 0; k < p->n_out; ++k)
+        if (p->t_out[k] % h_fs != 0) return fail(MATEX_E_INVALID, "every output time must be a multiple of h");
+    const double hs = double(h_fs) * FS;
+    if (!(std::fabs(f->gammas[0] - 0.5 * hs) <= 1e-12 * hs))
+        return fail(MATEX_E_INVALID, "the factor's first shift must be h / 2 (factor C + (h/2) G)");
+    const int64_t n = f->sym.n;
+    const int32_t n_out = p->n_out, n_probe = p->n_probe, n_src = p->n_src;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    matex_stats S{};
+    try {
+        // sources grouped by row (factor order), each row's in source order
+        std::vector<int32_t> order(n_src);
+        for (int32_t k = 0; k < n_src; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            return f->sym.iperm[p->node[a]] < f->sym.iperm[p->node[b]];
+        });
+        std::vector<int32_t> sptr(n + 1, 0);
+        std::vector<double> amp;
+        std::vector<int64_t> sd, sr, sw, sf;
+        for (int32_t q : order) {
+            sptr[f->sym.iperm[p->node[q]] + 1]++;
+            amp.push_back(p->amp[q]);
+            sd.push_back(p->delay[q]); sr.push_back(p->rise[q]); sw.push_back(p->width[q]); sf.push_back(p->fall[q]);
+        }
+        for (int64_t i = 0; i < n; ++i) sptr[i + 1] += sptr[i];
+        if (amp.empty()) { amp.push_back(0.0); sd.push_back(0); sr.push_back(1); sw.push_back(0); sf.push_back(1); }
+        DevMem d_sptr = upload(sptr), d_amp = upload(amp), d_sd = upload(sd), d_sr = upload(sr), d_sw = upload(sw),
+               d_sf = upload(sf);
+        std::vector<int32_t> pp(std::max(1, n_probe), 0);
+        for (int32_t k = 0; k < n_probe; ++k) pp[k] = f->sym.iperm[p->probe[k]];
+        DevMem d_pp = upload(pp);
+        DevMem y(sizeof(double) * n), rhs(sizeof(double) * n), tmp(sizeof(double) * n),
+            upd(sizeof(double) * std::max<int64_t>(1, f->sym.n_upd));
+        HIPCHK(hipMemsetAsync(d_probe_out, 0, sizeof(double) * int64_t(n_probe) * n_out, st));
+        // initial state: y(0) = G^-1 i(0) (0 when no pulse is on at t = 0)
+        {
+            std::vector<double> i0(n, 0.0);
+            bool any = false;
+            for (int32_t k = 0; k < n_src; ++k) {
+                const int64_t d = p->delay[k], r = p->rise[k], w = p->width[k], fl = p->fall[k];
+                double u = 0.0;
+                if (0 > d && 0 <= d + r) u = double(0 - d) / double(r);
+                else if (0 > d + r && 0 <= d + r + w) u = 1.0;
+                else if (0 > d + r + w && 0 < d + r + w + fl) u = 1.0 - double(0 - d - r - w) / double(fl);
+                if (u != 0.0) { i0[f->sym.iperm[p->node[k]]] += p->amp[k] * u; any = true; }
+            }
+            if (any) {
+                DevMem d_i0 = upload(i0);
+                dev_solve(*f, int(f->gammas.size()), d_i0.as<double>(), nullptr, y.as<double>(), tmp.as<double>(),
+                          upd.as<double>(), nullptr, st);
+                S.solve_pairs_g++;
+                HIPCHK(hipStreamSynchronize(st));
+            } else {
+                HIPCHK(hipMemsetAsync(y.p, 0, y.bytes, st));
+            }
+        }
+        int32_t k_out = 0;
+        while (k_out < n_out && p->t_out[k_out] == 0)
+            launch_gather_probes(n_probe, d_pp.as<int32_t>(), y.as<double>(), d_probe_out, n_out, k_out++, st);
+        const int64_t steps = p->t_end / h_fs;
+        for (int64_t k = 1; k <= steps; ++k) {
+            const int64_t t0 = (k - 1) * h_fs, t1 = k * h_fs;
+            launch_tr_rhs(n, f->d_grp.as<int32_t>(), f->d_gci.as<int32_t>(), f->d_gv.as<double>(),
+                          f->d_cperm.as<double>(), y.as<double>(), 0.5 * hs, t0, t1, d_sptr.as<int32_t>(),
+                          d_amp.as<double>(), d_sd.as<int64_t>(), d_sr.as<int64_t>(), d_sw.as<int64_t>(),
+                          d_sf.as<int64_t>(), rhs.as<double>(), st);
+            dev_solve(*f, 0, rhs.as<double>(), nullptr, y.as<double>(), tmp.as<double>(), upd.as<double>(), nullptr,
+                      st);
+            while (k_out < n_out && p->t_out[k_out] == t1)
+                launch_gather_probes(n_probe, d_pp.as<int32_t>(), y.as<double>(), d_probe_out, n_out, k_out++, st);
+            S.solve_pairs_m++;
+            S.segments++;
+        }
+        if (!o->output_droop) launch_vdd_minus(int64_t(n_probe) * n_out, f->vdd, d_probe_out, st);
+        if (d_final) {
+            launch_scatter_perm(n, f->d_perm.as<int32_t>(), y.as<double>(), d_final, n, n, 1, st);
+            if (!o->output_droop) launch_vdd_minus(n, f->vdd, d_final, st);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(st));
+    } catch (const HipError& e) {
+        return fail(MATEX_E_HIP, std::string(e.what) + ": " + hipGetErrorString(e.e));
+    } catch (const std::bad_alloc&) {
+        return fail(MATEX_E_OOM, "host allocation failed");
+    }
+    S.subtasks = 1;
     S.seconds = now_s() - t_start;
     if (stats) *stats = S;
     return check_outputs(p, n, d_probe_out, d_final, st);

@@ -37,7 +37,8 @@ class Netlist(ctypes.Structure):
 
 
 class FactorOpts(ctypes.Structure):
-    _fields_ = [("n_shifts", _i32), ("leaf_max", _i32), ("subtree_levels", _i32)]
+    _fields_ = [("n_shifts", _i32), ("leaf_max", _i32), ("subtree_levels", _i32),
+                ("batched_schedule", _i32)]
 
 
 class FactorInfo(ctypes.Structure):
@@ -45,7 +46,7 @@ class FactorInfo(ctypes.Structure):
                 ("n_levels", _i32), ("n_shifts", _i32), ("max_nr", _i32), ("gamma", _f64),
                 ("seconds_analyse", _f64), ("seconds_numeric", _f64), ("device_bytes", _i64),
                 ("subtree_levels", _i32), ("subtree_blocks", _i32), ("nnz_l_exact", _i64),
-                ("n_upd", _i64)]
+                ("n_upd", _i64), ("seconds_tune", _f64)]
 
 
 class Problem(ctypes.Structure):
@@ -70,9 +71,11 @@ class Stats(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad_"}
 
 
-EXPORTS = ["matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
+EXPORTS = ["matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_factor_describe",
+           "matex_solve",
            "matex_solve_noalloc",
-           "matex_krylov_step", "matex_transient", "matex_transient_many", "matex_adjoint",
+           "matex_krylov_step", "matex_transient", "matex_trapezoidal", "matex_transient_many",
+           "matex_adjoint",
            "matex_time_solves", "matex_sync", "matex_last_error", "matex_version"]
 
 _lib = None
@@ -92,12 +95,16 @@ def lib():
                                    ctypes.POINTER(_vp)]
         L.matex_factor_free.argtypes = [_vp]
         L.matex_factor_get_info.argtypes = [_vp, ctypes.POINTER(FactorInfo)]
+        L.matex_factor_describe.argtypes = [_vp, ctypes.c_char_p, ctypes.c_size_t]
+        L.matex_factor_describe.restype = ctypes.c_size_t
         L.matex_solve.argtypes = [_vp, _i32, _i32, _vp, _vp, _vp, _vp]
         L.matex_solve_noalloc.argtypes = [_vp, _i32, _vp, _vp, _vp, _vp]
         L.matex_krylov_step.argtypes = [_vp, _i32, _i32, _vp, _i32, _pf64, _i32, _f64, _vp, _pi32,
                                         _pf64, _vp]
         L.matex_transient.argtypes = [_vp, ctypes.POINTER(Problem), ctypes.POINTER(RunOpts), _vp,
                                       _vp, ctypes.POINTER(Stats), _vp]
+        L.matex_trapezoidal.argtypes = [_vp, ctypes.POINTER(Problem), _i64, ctypes.POINTER(RunOpts), _vp, _vp,
+                                        ctypes.POINTER(Stats), _vp]
         L.matex_transient_many.argtypes = [_i32, ctypes.POINTER(_vp), ctypes.POINTER(Problem),
                                            ctypes.POINTER(RunOpts), ctypes.POINTER(_vp),
                                            ctypes.POINTER(_vp), ctypes.POINTER(Stats), _i32, _vp]
@@ -110,7 +117,7 @@ def lib():
         L.matex_version.restype = ctypes.c_char_p
         for name in ("matex_factor", "matex_factor_free", "matex_factor_get_info", "matex_solve",
                      "matex_solve_noalloc",
-                     "matex_krylov_step", "matex_transient", "matex_transient_many",
+                     "matex_krylov_step", "matex_transient", "matex_trapezoidal", "matex_transient_many",
                      "matex_adjoint", "matex_time_solves", "matex_sync"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
@@ -169,7 +176,8 @@ class FactorHandle:
 
 
 def matex_factor(netlist, gamma: float, n_shifts: int = 6, leaf_max: int = 16,
-                 use_coords: bool = True, subtree_levels: int = 0) -> FactorHandle:
+                 use_coords: bool = True, subtree_levels: int = 0,
+                 batched_schedule: int = 0) -> FactorHandle:
     """Factor C + gamma_k G for the shift ladder and G (see matex.h)."""
     a = np.ascontiguousarray(netlist.br_a, np.int32)
     b = np.ascontiguousarray(netlist.br_b, np.int32)
@@ -182,13 +190,21 @@ def matex_factor(netlist, gamma: float, n_shifts: int = 6, leaf_max: int = 16,
                  _p(g, ctypes.c_double), _p(c, ctypes.c_double), pn.size, _p(pn, ctypes.c_int32),
                  _p(pg, ctypes.c_double), float(netlist.vdd),
                  _p(crd, ctypes.c_int32) if crd is not None else None)
-    opts = FactorOpts(n_shifts, leaf_max, subtree_levels)
+    opts = FactorOpts(n_shifts, leaf_max, subtree_levels, batched_schedule)
     h = ctypes.c_void_p()
     _check(lib().matex_factor(ctypes.byref(nl), float(gamma), ctypes.byref(opts), _stream(),
                               ctypes.byref(h)))
     info = FactorInfo()
     _check(lib().matex_factor_get_info(h, ctypes.byref(info)))
     return FactorHandle(h, {k: getattr(info, k) for k, _ in FactorInfo._fields_})
+
+
+def matex_factor_describe(f: FactorHandle) -> str:
+    """The factor's sweep schedules, one line per level."""
+    n = lib().matex_factor_describe(f.handle, None, 0)
+    buf = ctypes.create_string_buffer(n + 1)
+    lib().matex_factor_describe(f.handle, buf, n + 1)
+    return buf.value.decode()
 
 
 def matex_solve(f: FactorHandle, which: int, b, scale=None):
@@ -259,6 +275,23 @@ def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
     opts = RunOpts(float(tol), int(m_max), int(mode), int(h_min), float(shift_ratio), int(droop), 0)
     _check(lib().matex_transient(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(out), _ptr(fin),
                                  ctypes.byref(st), _stream()))
+    return out, fin, st.as_dict()
+
+
+def matex_trapezoidal(f: FactorHandle, prob, h_fs: int, device="cuda", final: bool = True,
+                      droop: bool = False):
+    """The trapezoidal rule at the fixed step h_fs (fs); f must be factored
+    with gamma = h / 2. Returns (x at probes (n_probe, n_out), x(t_end) or
+    None, stats dict), or the droop with droop=True."""
+    import torch
+    keep = []
+    pr = _problem_struct(prob, keep)
+    out = torch.empty((prob.probe.size, prob.t_out.size), dtype=torch.float64, device=device)
+    fin = torch.empty(f.info["n"], dtype=torch.float64, device=device) if final else None
+    st = Stats()
+    opts = RunOpts(1.0, 1, MATEX_PLAIN, 1, 1.0, int(droop), 0)
+    _check(lib().matex_trapezoidal(f.handle, ctypes.byref(pr), int(h_fs), ctypes.byref(opts), _ptr(out),
+                                   _ptr(fin), ctypes.byref(st), _stream()))
     return out, fin, st.as_dict()
 
 

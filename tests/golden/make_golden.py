@@ -21,8 +21,11 @@ stored so a test can tell that it rebuilt the same instance.
                     tol 1e-12 per basis.
   config2_mid.npz   the same workload over [0.9, 1.0] ns (11 transition
                     spots), started at 0.6 ns from G^-1 i(0.6 ns).
+  config3_head.npz  8 of the 128 uneven 2-layer meshes (the smallest, the
+                    largest and 6 drawn with seed 3) over their first 100 ps:
+                    x at their probes every 10 ps, oracle R-MATEX tol 1e-12.
 Run:  OPENBLAS_NUM_THREADS=1 python tests/golden/make_golden.py
-          [head|mid|check|c2head|c2mid]
+          [head|mid|check|c2head|c2mid|c3]
 """
 import os
 import sys
@@ -98,6 +101,31 @@ def config2_window(name, t0, t1, t2, tol=1e-12):
                         digest=p.digest(), t_start=t0, tol=tol)
 
 
+def config3_subset():
+    """The smallest and the largest of the 128 meshes and 6 others (seed 3)."""
+    ns = np.array([I.config3(k).netlist.n for k in range(128)])
+    lo, hi = int(np.argmin(ns)), int(np.argmax(ns))
+    rest = [k for k in range(128) if k not in (lo, hi)]
+    pick = np.random.default_rng(3).choice(rest, 6, replace=False)
+    return [lo, hi] + sorted(int(k) for k in pick)
+
+
+def config3_head(t_end=100 * I.PS, tol=1e-12):
+    out = {}
+    sub = config3_subset()
+    for k in sub:
+        p = I.config3(k)
+        q = I.Problem(p.name, p.netlist, p.sources, t_end, p.t_out[p.t_out <= t_end], p.probe)
+        t = time.time()
+        s = RM.RMatex(p.netlist, p.gamma)
+        x, _ = s.transient(q, tol=tol, m_max=p.m_max)
+        print(f"config3[{k}] n {p.netlist.n}: {time.time() - t:.1f} s, bases {s.stats.bases}", flush=True)
+        out[f"x_{k}"] = x
+        out[f"digest_{k}"] = p.digest()
+    np.savez_compressed(os.path.join(HERE, "config3_head.npz"), instances=np.array(sub), t_end=t_end, tol=tol,
+                        **out)
+
+
 if __name__ == "__main__":
     what = sys.argv[1] if len(sys.argv) > 1 else "all"
     if what in ("head", "all"):
@@ -110,3 +138,5 @@ if __name__ == "__main__":
         config2_window("config2_head.npz", 0, 0, 300 * I.PS)
     if what in ("c2mid", "all"):
         config2_window("config2_mid.npz", 600 * I.PS, 900 * I.PS, 1000 * I.PS)
+    if what in ("c3", "all"):
+        config3_head()
