@@ -219,7 +219,16 @@ typedef struct {
                                 tau_1 >= shift_ratio * gamma_k (0 = default 1.0)  */
     int32_t output_droop;    /* 0: outputs are x = Vdd - y; 1: the droop y itself
                                 (no supply offset, full relative precision)     */
-    int32_t reserved_;       /* 0                                                */
+    int32_t batched_independent; /* MATEX_BATCHED only. 0: lockstep generations
+                                (every subtask takes one step per generation;
+                                slope changes by G solves of the whole
+                                batch). 1: each subtask advances on its own
+                                (a converged subtask starts its next step
+                                while the others iterate; slope changes from
+                                solved columns of the sources' pulse timings;
+                                lockstep when those do not fit half the free
+                                memory); the same steps and results to
+                                rounding, more pairs on the 1M-node workload  */
 } matex_run_opts;
 
 typedef struct {
@@ -258,11 +267,11 @@ typedef struct {
  * step is retried one shift lower, and with the smallest shift it is halved
  * down to h_min. Stats may be NULL.
  * Modes: MATEX_PLAIN runs the subtasks one after another. MATEX_BATCHED runs
- * up to 64 subtasks together: in lockstep generations every unfinished
- * subtask takes one step; subtasks that need the same shift share one
- * multi-right-hand-side substitution pair per Krylov iteration, and each
- * keeps its own Gram-Schmidt, checks and step decisions (those of the plain
- * mode, so both modes take the same steps). In stats, solve_pairs_m and
+ * up to 64 subtasks together: subtasks that use the same shift share one
+ * multi-right-hand-side substitution pair per Krylov iteration, each at its
+ * own dimension, and each keeps its own Gram-Schmidt, checks and step
+ * decisions (those of the plain mode, so both modes take the same steps);
+ * see o->batched_lockstep for how their steps are scheduled. In stats, solve_pairs_m and
  * solve_pairs_g then count multi-right-hand-side pairs; bases, segments and
  * krylov_dims count per subtask.
  * Errors: MATEX_E_INVALID (also for an unknown mode), MATEX_E_NOCONV,

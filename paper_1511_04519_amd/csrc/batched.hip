@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void kb_fwd(DevSym s, BatchAssembly as,
                                               const double* __restrict__ W,
                                               const double* __restrict__ B,
                                               const double* __restrict__ scale, double* y,
-                                              double* U, double* P)
+                                              double* U, double* P, const KState* rks)
 {
     __shared__ double Ws[BK][LROW];
     __shared__ double Ts[BK][LROW];
@@ -82,6 +82,9 @@ __global__ __launch_bounds__(256) void kb_fwd(DevSym s, BatchAssembly as,
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
     double wr[4], tr[4];
+    // ragged inputs: right-hand side e is block m of its own basis
+    const int e_own = tid & 63;
+    const int64_t boff = rks && e_own < R ? int64_t(rks[e_own].m) * s.n * R : 0;
     auto load = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(256) void kb_fwd(DevSym s, BatchAssembly as,
             wr[q] = (k < ke && row < nr) ? Wp[int64_t(k) * ld + row] : 0.0;
             double b = 0.0;
             if (k < ke && e < R) {
-                const int64_t o = int64_t(c0 + k) * R + e;
+                const int64_t o = boff + int64_t(c0 + k) * R + e;
                 b = (scale ? B[o] * scale[c0 + k] : B[o]) - pull(as, pb + k, R, e, U);
             }
             tr[q] = b;
@@ -146,25 +149,42 @@ __global__ __launch_bounds__(256) void kb_fwd(DevSym s, BatchAssembly as,
 }
 
 // Sums the partial slots of split forward blocks, in slot order (an
-// off-diagonal row adds the children's updates first).
+// off-diagonal row adds the children's updates first). One thread per
+// element of the 64 x 64 slot (16 blocks per item); eight slots' loads are
+// issued together and then added in order.
+constexpr int RED_SPLIT = (64 * 64) / 256;
+
+__device__ inline double sum_slots(const double* p, int cnt, double sum)
+{
+    int c = 0;
+    for (; c + 8 <= cnt; c += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = p[int64_t(c + q) * PSLOT];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) sum += v[q];
+    }
+    for (; c < cnt; ++c) sum += p[int64_t(c) * PSLOT];
+    return sum;
+}
+
 __global__ __launch_bounds__(256) void kb_fwd_reduce(DevSym s, BatchAssembly as,
                                                      const BRed* __restrict__ items, int R,
                                                      const double* __restrict__ P, double* y,
                                                      double* U)
 {
-    const BRed it = items[blockIdx.x];
+    const BRed it = items[blockIdx.x / RED_SPLIT];
+    const int idx = (blockIdx.x % RED_SPLIT) * 256 + threadIdx.x;
     const int sn = it.sn;
     const int c0 = s.c0[sn], nc = s.nc[sn], nr = s.nr[sn];
     const int pb = as.pos_base[sn];
     const int64_t u = s.u[sn];
-    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-        const int e = idx >> 6, r = idx & 63, row = it.first + e;
-        if (r >= R || row >= nr) continue;
-        double sum = row < nc ? 0.0 : pull(as, pb + row, R, r, U);
-        for (int c = 0; c < it.cnt; ++c) sum += P[int64_t(it.slot + c) * PSLOT + idx];
-        if (row < nc) y[int64_t(c0 + row) * R + r] = sum;
-        else U[(u + row - nc) * R + r] = sum;
-    }
+    const int e = idx >> 6, r = idx & 63, row = it.first + e;
+    if (r >= R || row >= nr) return;
+    double sum = row < nc ? 0.0 : pull(as, pb + row, R, r, U);
+    sum = sum_slots(P + int64_t(it.slot) * PSLOT + idx, it.cnt, sum);
+    if (row < nc) y[int64_t(c0 + row) * R + r] = sum;
+    else U[(u + row - nc) * R + r] = sum;
 }
 
 // Columns first .. first + 63 of x_s for one supernode: W_s^T [y_s ; -x_off]
@@ -257,16 +277,13 @@ __global__ __launch_bounds__(256) void kb_bwd(DevSym s, const BTask* __restrict_
 __global__ __launch_bounds__(256) void kb_bwd_reduce(DevSym s, const BRed* __restrict__ items, int R,
                                                      const double* __restrict__ P, double* x)
 {
-    const BRed it = items[blockIdx.x];
+    const BRed it = items[blockIdx.x / RED_SPLIT];
+    const int idx = (blockIdx.x % RED_SPLIT) * 256 + threadIdx.x;
     const int sn = it.sn;
     const int c0 = s.c0[sn], nc = s.nc[sn];
-    for (int idx = threadIdx.x; idx < 64 * 64; idx += 256) {
-        const int e = idx >> 6, r = idx & 63, c = it.first + e;
-        if (r >= R || c >= nc) continue;
-        double sum = 0.0;
-        for (int q = 0; q < it.cnt; ++q) sum += P[int64_t(it.slot + q) * PSLOT + idx];
-        x[int64_t(c0 + c) * R + r] = sum;
-    }
+    const int e = idx >> 6, r = idx & 63, c = it.first + e;
+    if (r >= R || c >= nc) return;
+    x[int64_t(c0 + c) * R + r] = sum_slots(P + int64_t(it.slot) * PSLOT + idx, it.cnt, 0.0);
 }
 
 // ------------------------------------------------ wavefront-per-supernode
@@ -299,7 +316,8 @@ template <int WNC>
 __global__ __launch_bounds__(256) void kb_fwd_wave(DevSym s, BatchAssembly as, const int32_t* __restrict__ sns,
                                                    int count, int R, const double* __restrict__ W,
                                                    const double* __restrict__ B,
-                                                   const double* __restrict__ scale, double* y, double* U)
+                                                   const double* __restrict__ scale, double* y, double* U,
+                                                   const KState* rks)
 {
     __shared__ double Wsh[4][WNC * 64];
     const int wv = threadIdx.x >> 6, r = threadIdx.x & 63;
@@ -313,11 +331,12 @@ __global__ __launch_bounds__(256) void kb_fwd_wave(DevSym s, BatchAssembly as, c
     double* Ws = Wsh[wv];
     const bool on = r < R;
     double bt[WNC];
+    const int64_t boff = rks && on ? int64_t(rks[r].m) * s.n * R : 0;
 #pragma unroll
     for (int k = 0; k < WNC; ++k) {
         double v = 0.0;
         if (k < nc && on) {
-            const int64_t o = int64_t(c0 + k) * R + r;
+            const int64_t o = boff + int64_t(c0 + k) * R + r;
             v = (scale ? B[o] * scale[c0 + k] : B[o]) - pull(as, pb + k, R, r, U);
         }
         bt[k] = v;
@@ -465,16 +484,32 @@ __device__ inline void combine_waves(double (&acc)[N], int cnt, double* buf)
 // block's four wavefronts take interleaved rows.
 constexpr int GS_CHUNK = 16;
 
+// Basis vectors of subtask r in this pass: the launch's nv, or with ragged
+// dimensions (subtasks at different iterations) its own m + 1, read before
+// kb_col_reduce's second pass records the new column and sets m to that
+// count (`recorded`: read after it, the count is m itself); a lane works
+// only when its subtask is in the pass (act null: all) and not done.
+__device__ inline int lane_nv(const KState* ks, int r, int R, int nv, int ragged, int recorded = 0)
+{
+    return ragged ? (r < R ? ks[r].m + (recorded ? 0 : 1) : 0) : nv;
+}
+__device__ inline bool lane_on(const KState* ks, const int32_t* act, int r, int R)
+{
+    return r < R && !ks[r].done && (!act || act[r]);
+}
+
 __global__ __launch_bounds__(256) void kb_gs_dots(int64_t n, int R, const double* __restrict__ V,
-                                                  int nv, const double* __restrict__ w,
-                                                  double* partial, const KState* ks, int norm)
+                                                  int nv_all, const double* __restrict__ w,
+                                                  double* partial, const KState* ks, int norm,
+                                                  const int32_t* act, int ragged)
 {
     __shared__ double buf[2 * (GS_CHUNK + 1) * 64];
     const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int nv = lane_nv(ks, r, R, nv_all, ragged);
     const int i0 = blockIdx.y * GS_CHUNK;
     const int cnt = min(GS_CHUNK, nv - i0);
     const bool with_norm = norm && blockIdx.y == 0;
-    const bool on = r < R && !ks[r < R ? r : 0].done;
+    const bool on = lane_on(ks, act, r, R) && cnt > 0;
     double acc[GS_CHUNK + 1];
 #pragma unroll
     for (int i = 0; i <= GS_CHUNK; ++i) acc[i] = 0.0;
@@ -489,7 +524,7 @@ __global__ __launch_bounds__(256) void kb_gs_dots(int64_t n, int R, const double
         }
     }
     combine_waves(acc, GS_CHUNK + 1, buf);
-    if (wv == 0 && r < R) {
+    if (wv == 0 && on) {
         double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
 #pragma unroll
         for (int i = 0; i < GS_CHUNK; ++i)
@@ -501,19 +536,21 @@ __global__ __launch_bounds__(256) void kb_gs_dots(int64_t n, int R, const double
 // out = (w - sum_i h[i] V_i) * sc per subtask, h = h1 (mode 0, sc = 1, out
 // = w in place) or h2 (mode 1, sc = vscale, out = V_nv). The coefficients
 // sit in LDS, so a row needs only its nv basis values in flight.
-__global__ __launch_bounds__(256) void kb_gs_axpy(int64_t n, int R, double* V, int nv, double* w,
-                                                  const KState* ks, int mode)
+__global__ __launch_bounds__(256) void kb_gs_axpy(int64_t n, int R, double* V, int nv_all, double* w,
+                                                  const KState* ks, int mode, const int32_t* act, int ragged)
 {
     __shared__ double hs[NVB][64];
     const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int idx = threadIdx.x; idx < NVB * 64; idx += 256) {
         const int i = idx >> 6, q = idx & 63;
         double h = 0.0;
-        if (q < R && i < nv) h = mode == 0 ? ks[q].h1[i] : ks[q].h2[i];
+        if (q < R && i < lane_nv(ks, q, R, nv_all, ragged, mode)) h = mode == 0 ? ks[q].h1[i] : ks[q].h2[i];
         hs[i][q] = h;
     }
     __syncthreads();
-    if (r >= R || ks[r].done) return;
+    if (!lane_on(ks, act, r, R)) return;
+    // mode 1 runs after the second reduction has set m to the count
+    const int nv = lane_nv(ks, r, R, nv_all, ragged, mode);
     const double sc = mode == 0 ? 1.0 : ks[r].vscale;
     double* out = mode == 0 ? w : V + int64_t(nv) * n * R;
     for (int64_t row = int64_t(blockIdx.x) * 4 + wv; row < n; row += int64_t(gridDim.x) * 4) {
@@ -536,18 +573,19 @@ constexpr int GS_TILE = 16;
 constexpr int GS_VPW_B = (NVB + 1 + 3) / 4;
 
 __global__ __launch_bounds__(256) void kb_gs_update_dots(int64_t n, int R, const double* __restrict__ V,
-                                                         int nv, double* w, double* partial,
-                                                         const KState* ks)
+                                                         int nv_all, double* w, double* partial,
+                                                         const KState* ks, const int32_t* act, int ragged)
 {
     __shared__ double hs[NVB][64];
     __shared__ double wl[GS_TILE][64];
     const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int idx = threadIdx.x; idx < NVB * 64; idx += 256) {
         const int i = idx >> 6, q = idx & 63;
-        hs[i][q] = (q < R && i < nv) ? ks[q].h1[i] : 0.0;
+        hs[i][q] = (q < R && i < lane_nv(ks, q, R, nv_all, ragged)) ? ks[q].h1[i] : 0.0;
     }
     __syncthreads();
-    const bool on = r < R && !ks[r < R ? r : 0].done;
+    const bool on = lane_on(ks, act, r, R);
+    const int nv = lane_nv(ks, r, R, nv_all, ragged);
     double acc[GS_VPW_B];
 #pragma unroll
     for (int q = 0; q < GS_VPW_B; ++q) acc[q] = 0.0;
@@ -589,7 +627,7 @@ __global__ __launch_bounds__(256) void kb_gs_update_dots(int64_t n, int R, const
         }
         __syncthreads();
     }
-    if (r < R) {
+    if (on) {
         double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
 #pragma unroll
         for (int q = 0; q < GS_VPW_B; ++q) {
@@ -608,18 +646,19 @@ __global__ __launch_bounds__(256) void kb_gs_update_dots(int64_t n, int R, const
 constexpr int NVC = 24;
 
 __global__ __launch_bounds__(256) void kb_gs_update_dots_reg(int64_t n, int R, const double* __restrict__ V,
-                                                             int nv, double* w, double* partial,
-                                                             const KState* ks)
+                                                             int nv_all, double* w, double* partial,
+                                                             const KState* ks, const int32_t* act, int ragged)
 {
     __shared__ double hs[NVC][64];
     __shared__ double red[2][NVC + 1][64];
     const int r = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int idx = threadIdx.x; idx < NVC * 64; idx += 256) {
         const int i = idx >> 6, q = idx & 63;
-        hs[i][q] = (q < R && i < nv) ? ks[q].h1[i] : 0.0;
+        hs[i][q] = (q < R && i < lane_nv(ks, q, R, nv_all, ragged)) ? ks[q].h1[i] : 0.0;
     }
     __syncthreads();
-    const bool on = r < R && !ks[r < R ? r : 0].done;
+    const bool on = lane_on(ks, act, r, R);
+    const int nv = lane_nv(ks, r, R, nv_all, ragged);
     double acc[NVC + 1];
 #pragma unroll
     for (int i = 0; i <= NVC; ++i) acc[i] = 0.0;
@@ -656,7 +695,7 @@ __global__ __launch_bounds__(256) void kb_gs_update_dots_reg(int64_t n, int R, c
         for (int i = 0; i <= NVC; ++i) red[0][i][r] = acc[i];
     }
     __syncthreads();
-    if (wv == 0 && r < R) {
+    if (wv == 0 && on) {
         double* out = partial + (int64_t(blockIdx.x) * R + r) * (NVB + 1);
 #pragma unroll
         for (int i = 0; i < NVC; ++i)
@@ -671,12 +710,14 @@ __global__ __launch_bounds__(256) void kb_gs_update_dots_reg(int64_t n, int R, c
 // squared norm of v (setup): beta, and a reset of the state for a new basis
 // (only for subtasks with active[r]; others are marked done).
 __global__ __launch_bounds__(256) void kb_col_reduce(int R, int nblk, const double* partial,
-                                                     int stride, int nv, int mode, KState* ks,
-                                                     const int32_t* active)
+                                                     int stride, int nv_all, int mode, KState* ks,
+                                                     const int32_t* active, int ragged)
 {
     const int r = blockIdx.x;
     KState* k = ks + r;
-    if (mode < 2 && k->done) return;
+    if (mode < 2 && (k->done || (active && !active[r]))) return;
+    if (mode == 3 && !active[r]) return;   // set-up of some subtasks: the others untouched
+    const int nv = lane_nv(ks, r, R, nv_all, ragged);
     __shared__ double red[4 * (NVMAX + 1)];
     __shared__ double vals[NVMAX + 1];
     const int cnt = mode == 0 ? nv : (mode == 1 ? nv + 1 : 1);
@@ -714,7 +755,7 @@ __global__ __launch_bounds__(256) void kb_col_reduce(int R, int nblk, const doub
             k->converged = 1;
             return;
         }
-        const double beta = sqrt(vals[0]);
+        const double beta = sqrt(vals[0]);   // modes 2 and 3
         k->beta = beta;
         k->m = 0;
         k->mdec = 0;
@@ -837,6 +878,32 @@ __global__ __launch_bounds__(256) void kb_recon_full(int64_t n, int R, const dou
     }
 }
 
+// Slope changes of independently advancing subtasks from solved columns:
+// for subtask r, z1 += sum_e coef[e] Z1[:, q[e]] and z2 likewise over its
+// events e = ptr[r] .. ptr[r + 1] - 1 (in that order); Z1, Z2 column-major
+// n x columns, z1, z2 row-interleaved.
+__global__ __launch_bounds__(256) void kb_spot_cols(int64_t n, int R, const int32_t* __restrict__ ptr,
+                                                    const int32_t* __restrict__ q, const double* __restrict__ coef,
+                                                    const double* __restrict__ Z1, const double* __restrict__ Z2,
+                                                    double* z1, double* z2)
+{
+    const int r = threadIdx.x & 63;
+    if (r >= R) return;
+    const int e0 = ptr[r], e1 = ptr[r + 1];
+    if (e0 == e1) return;
+    for (int64_t row = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6); row < n; row += int64_t(gridDim.x) * 4) {
+        const int64_t o = row * R + r;
+        double a = z1[o], b = z2[o];
+        for (int e = e0; e < e1; ++e) {
+            const int64_t zo = int64_t(q[e]) * n + row;
+            a += coef[e] * Z1[zo];
+            b += coef[e] * Z2[zo];
+        }
+        z1[o] = a;
+        z2[o] = b;
+    }
+}
+
 // s[row * R + col] += d for the events of this generation ((row, col) unique).
 __global__ void kb_events(int cnt, int R, const int32_t* row, const int32_t* col, const double* d,
                           double* s)
@@ -878,18 +945,19 @@ inline int grid_rows(int64_t n, int per_block) { return int(std::min<int64_t>((n
 
 void launch_b_forward(const DevSym& s, const BatchAssembly& as, const BatchLevel& lv, int R,
                       const double* W, const double* B, const double* scale, double* y,
-                      double* U, double* P, hipStream_t st)
+                      double* U, double* P, hipStream_t st, const KState* rks)
 {
     if (lv.fwave) {
         if (lv.wave_nc <= 16)
-            kb_fwd_wave<16><<<(lv.n_fwave + 3) / 4, 256, 0, st>>>(s, as, lv.fwave, lv.n_fwave, R, W, B, scale, y, U);
+            kb_fwd_wave<16><<<(lv.n_fwave + 3) / 4, 256, 0, st>>>(s, as, lv.fwave, lv.n_fwave, R, W, B, scale, y, U,
+                                                                  rks);
         else
             kb_fwd_wave<WAVE_MAX_NC><<<(lv.n_fwave + 3) / 4, 256, 0, st>>>(s, as, lv.fwave, lv.n_fwave, R, W, B, scale,
-                                                                           y, U);
+                                                                           y, U, rks);
         return;
     }
-    kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, as, lv.fwd, R, W, B, scale, y, U, P);
-    if (lv.n_fred) kb_fwd_reduce<<<lv.n_fred, 256, 0, st>>>(s, as, lv.fred, R, P, y, U);
+    kb_fwd<<<lv.n_fwd, 256, 0, st>>>(s, as, lv.fwd, R, W, B, scale, y, U, P, rks);
+    if (lv.n_fred) kb_fwd_reduce<<<lv.n_fred * RED_SPLIT, 256, 0, st>>>(s, as, lv.fred, R, P, y, U);
 }
 
 void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
@@ -903,23 +971,23 @@ void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const doubl
         return;
     }
     kb_bwd<<<lv.n_bwd, 256, 0, st>>>(s, lv.bwd, R, W, y, x, P);
-    if (lv.n_bred) kb_bwd_reduce<<<lv.n_bred, 256, 0, st>>>(s, lv.bred, R, P, x);
+    if (lv.n_bred) kb_bwd_reduce<<<lv.n_bred * RED_SPLIT, 256, 0, st>>>(s, lv.bred, R, P, x);
 }
 
 void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial, KState* ks,
-                 hipStream_t st)
+                 hipStream_t st, const int32_t* act, int ragged)
 {
     const int nb = B_RED_BLOCKS;
     const int stride = NVB + 1;
     const dim3 gd(nb, (nv + GS_CHUNK - 1) / GS_CHUNK);
-    kb_gs_dots<<<gd, 256, 0, st>>>(n, R, V, nv, w, partial, ks, 0);
-    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 0, ks, nullptr);
+    kb_gs_dots<<<gd, 256, 0, st>>>(n, R, V, nv, w, partial, ks, 0, act, ragged);
+    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 0, ks, act, ragged);
     if (nv <= NVC)
-        kb_gs_update_dots_reg<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
+        kb_gs_update_dots_reg<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks, act, ragged);
     else
-        kb_gs_update_dots<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks);
-    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 1, ks, nullptr);
-    kb_gs_axpy<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks, 1);
+        kb_gs_update_dots<<<nb, 256, 0, st>>>(n, R, V, nv, w, partial, ks, act, ragged);
+    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, stride, nv, 1, ks, act, ragged);
+    kb_gs_axpy<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, nv, w, ks, 1, act, ragged);
 }
 
 void launch_b_checks(KState* ks, double gamma, const double* taus, const int32_t* tau_off, int cap,
@@ -940,11 +1008,12 @@ void launch_b_resume(KState* ks, const int32_t* cols, int cnt, hipStream_t st)
 }
 
 void launch_b_setup(int64_t n, int R, const double* y, const double* y0, const double* z2,
-                    double* V, double* partial, KState* ks, const int32_t* active, hipStream_t st)
+                    double* V, double* partial, KState* ks, const int32_t* active, hipStream_t st,
+                    bool keep_others)
 {
     const int nb = B_RED_BLOCKS;
     kb_setup_v<<<nb, 256, 0, st>>>(n, R, y, y0, z2, V, partial, active);
-    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, 2, 0, 2, ks, active);
+    kb_col_reduce<<<R, 256, 0, st>>>(R, nb, partial, 2, 0, keep_others ? 3 : 2, ks, active, 0);
     kb_scale_v<<<grid_rows(n, 4), 256, 0, st>>>(n, R, V, ks, active);
 }
 
@@ -968,6 +1037,12 @@ void launch_b_recon_full(int64_t n, int R, const double* col_tau, const int32_t*
 {
     kb_recon_full<<<grid_rows(n, 4), 256, 0, st>>>(n, R, col_tau, col_u, u_buf, ks, active, V, y, y0,
                                                    z1, z2);
+}
+
+void launch_b_spot_cols(int64_t n, int R, const int32_t* ptr, const int32_t* q, const double* coef,
+                        const double* Z1, const double* Z2, double* z1, double* z2, hipStream_t st)
+{
+    kb_spot_cols<<<grid_rows(n, 4), 256, 0, st>>>(n, R, ptr, q, coef, Z1, Z2, z1, z2);
 }
 
 void launch_b_events(int cnt, int R, const int32_t* row, const int32_t* col, const double* d,

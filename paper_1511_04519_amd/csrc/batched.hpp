@@ -64,15 +64,20 @@ struct BatchLevel {
 // Multi-right-hand-side pair, all n x R arrays row-interleaved (x[i * R + r]).
 // U (n_upd x R) is scratch; y is the forward result; P holds the partial
 // results of split tasks (PSLOT doubles per slot).
+// rks (or null): ragged inputs, right-hand side r read from block rks[r].m
+// of B (a basis of MAXM + 1 blocks of n x R), not from block 0.
 void launch_b_forward(const DevSym& s, const BatchAssembly& as, const BatchLevel& lv, int R,
                       const double* W, const double* B, const double* scale, double* y,
-                      double* U, double* P, hipStream_t st);
+                      double* U, double* P, hipStream_t st, const KState* rks = nullptr);
 void launch_b_backward(const DevSym& s, const BatchLevel& lv, int R, const double* W,
                        const double* y, double* x, double* P, hipStream_t st);
 // Two classical Gram-Schmidt passes for every subtask not yet done; V holds
 // MAXM + 1 blocks of n x R. partial: B_RED_BLOCKS * R * (MAXM + 2) doubles.
+// act (or null): the subtasks of this pass (others untouched); ragged:
+// subtask r at its own iteration ks[r].m (nv = the largest m + 1 of the pass),
+// otherwise all at nv.
 void launch_b_gs(int64_t n, int R, double* V, int nv, double* w, double* partial, KState* ks,
-                 hipStream_t st);
+                 hipStream_t st, const int32_t* act = nullptr, int ragged = 0);
 // Estimates for the blocks (chk_col[b], chk_idx[b]); subtask r's blocks are
 // chk_idx[col_off[r] .. + col_cnt[r]] (the checks its decision takes the
 // maximum over), its offsets taus[tau_off[r] ..], its u vectors and
@@ -84,8 +89,12 @@ void launch_b_checks(KState* ks, double gamma, const double* taus, const int32_t
                      int m_max, int update_state, hipStream_t st);
 // Lets the subtasks cols[0 .. cnt) continue iterating.
 void launch_b_resume(KState* ks, const int32_t* cols, int cnt, hipStream_t st);
+// v = y - y0 + z2 into V_0 for the active subtasks, its norm and a fresh
+// state; the other subtasks are marked done, or with keep_others left as
+// they are (subtasks that advance independently).
 void launch_b_setup(int64_t n, int R, const double* y, const double* y0, const double* z2,
-                    double* V, double* partial, KState* ks, const int32_t* active, hipStream_t st);
+                    double* V, double* partial, KState* ks, const int32_t* active, hipStream_t st,
+                    bool keep_others = false);
 void launch_b_recon_probes(int64_t n, int R, int n_probe, const int32_t* probe_perm, int n_ent,
                            const int32_t* ent_col, const int32_t* ent_t, const double* ent_tau,
                            const int32_t* ent_u, const double* u_buf, const KState* ks,
@@ -95,6 +104,10 @@ void launch_b_recon_full(int64_t n, int R, const double* col_tau, const int32_t*
                          const double* u_buf, const KState* ks, const int32_t* active,
                          const double* V, double* y, double* y0, const double* z1, const double* z2,
                          hipStream_t st);
+// z1 += sum coef[e] Z1[:, q[e]], z2 likewise, for subtask r's events
+// e in [ptr[r], ptr[r + 1]) (Z column-major n x columns; z row-interleaved).
+void launch_b_spot_cols(int64_t n, int R, const int32_t* ptr, const int32_t* q, const double* coef,
+                        const double* Z1, const double* Z2, double* z1, double* z2, hipStream_t st);
 void launch_b_events(int cnt, int R, const int32_t* row, const int32_t* col, const double* d,
                      double* s, hipStream_t st);
 // out += sgn * (sum over the batch's subtasks).

@@ -1551,6 +1551,340 @@ void reconstruct(BatchWork& bw, int R, const std::vector<int>& fin, std::vector<
     }
 }
 
+// One multi-right-hand-side pair on the batch's basis with ragged inputs
+// (right-hand side r is block ks[r].m of V): w = (C + gamma_k G)^-1 C v.
+void dev_solve_batched_ragged(const matex_factor_s& F, int which, int R, BatchWork& bw, hipStream_t st)
+{
+    const double* W = F.d_W[size_t(which)].as<double>();
+    const int L = F.sym.n_levels;
+    double* yf = bw.sc.yf.as<double>();
+    double* U = bw.sc.U.as<double>();
+    double* P = bw.sc.P.as<double>();
+    for (int lv = 0; lv < L; ++lv)
+        launch_b_forward(F.dsym, F.bas, F.blevels[size_t(lv)], R, W, bw.Vd(), F.d_cperm.as<double>(), yf, U, P, st,
+                         bw.kst());
+    for (int lv = L - 1; lv >= 0; --lv) launch_b_backward(F.dsym, F.blevels[size_t(lv)], R, W, yf, bw.w.as<double>(), P, st);
+}
+
+// Solved columns of the pulse timings (subtasks that advance independently):
+// within each subtask of a batch, the sources of one timing (delay, rise,
+// width, fall) form one column q with weight vector b_q (their amplitudes at
+// their rows), and Z1[:, q] = G^-1 b_q, Z2[:, q] = G^-1 C Z1[:, q]. The
+// subtask's slope vector is sum_q sigma_q(t) b_q with sigma_q the unit
+// pulse's slope, so at a transition spot its z1 and z2 (Eq. 6) change by the
+// change of sigma_q times these columns: no solve with G during the run.
+struct TimingCols {
+    struct Col {
+        int32_t sub;                 // subtask (column of the batch)
+        int64_t d, r, w, f;          // pulse timing (fs)
+    };
+    std::vector<Col> col;
+    DevMem Z;                        // Z1 then Z2, n x columns each
+    int64_t n = 0;
+    const double* Z1() const { return Z.as<double>(); }
+    const double* Z2() const { return Z.as<double>() + n * int64_t(col.size()); }
+};
+
+// The timing columns of subtasks b0 .. b0 + R - 1 and their solves (64 at a
+// time with the G factor). Returns false, with nothing allocated, when they
+// would take more than half the free device memory.
+bool timing_cols(const matex_factor_s& F, const matex_problem* p,
+                 const std::vector<std::vector<int32_t>>& subtasks, int b0, int R, BatchWork& bw,
+                 TimingCols& tc, matex_stats& S, hipStream_t st)
+{
+    const int64_t n = F.sym.n;
+    tc = TimingCols{};
+    tc.n = n;
+    std::vector<std::map<int32_t, double>> rows;   // per column: row -> weight
+    for (int r = 0; r < R; ++r) {
+        std::map<std::array<int64_t, 4>, int32_t> idx;
+        for (int32_t k : subtasks[size_t(b0 + r)]) {
+            const std::array<int64_t, 4> key = {p->delay[k], p->rise[k], p->width[k], p->fall[k]};
+            auto it = idx.find(key);
+            if (it == idx.end()) {
+                it = idx.emplace(key, int32_t(tc.col.size())).first;
+                tc.col.push_back({r, key[0], key[1], key[2], key[3]});
+                rows.emplace_back();
+            }
+            rows[size_t(it->second)][F.sym.iperm[p->node[k]]] += p->amp[k];
+        }
+    }
+    const int64_t nq = int64_t(tc.col.size());
+    if (nq == 0) return true;
+    size_t fr = 0, tot = 0;
+    HIPCHK(hipMemGetInfo(&fr, &tot));
+    if (sizeof(double) * size_t(n) * size_t(2 * nq) > fr / 2) return false;
+    tc.Z = DevMem(sizeof(double) * size_t(n) * size_t(2 * nq));
+    std::vector<int32_t> id(n);
+    for (int64_t i = 0; i < n; ++i) id[size_t(i)] = int32_t(i);
+    DevMem ident = upload(id);
+    double* Z1 = tc.Z.as<double>();
+    double* Z2 = Z1 + n * nq;
+    double* E = bw.s.as<double>();
+    double* X1 = bw.w.as<double>();
+    double* X2 = bw.y.as<double>();
+    for (int64_t q0 = 0; q0 < nq; q0 += bw.Rmax) {
+        const int Rc = int(std::min<int64_t>(bw.Rmax, nq - q0));
+        size_t cnt = 0;
+        for (int c = 0; c < Rc; ++c) cnt += rows[size_t(q0 + c)].size();
+        std::vector<int32_t> hr, hc;
+        std::vector<double> hd;
+        for (int c = 0; c < Rc; ++c)
+            for (auto& e : rows[size_t(q0 + c)]) { hr.push_back(e.first); hc.push_back(c); hd.push_back(e.second); }
+        DevMem dr = upload(hr), dc = upload(hc), dd = upload(hd);
+        launch_b_fill(n * Rc, 0.0, E, st);
+        launch_b_events(int(cnt), Rc, dr.as<int32_t>(), dc.as<int32_t>(), dd.as<double>(), E, st);
+        dev_solve_batched(F, int(F.gammas.size()), Rc, E, nullptr, X1, bw.sc, st);
+        launch_b_deinterleave(n, Rc, ident.as<int32_t>(), X1, Z1 + q0 * n, st);
+        dev_solve_batched(F, int(F.gammas.size()), Rc, X1, F.d_cperm.as<double>(), X2, bw.sc, st);
+        launch_b_deinterleave(n, Rc, ident.as<int32_t>(), X2, Z2 + q0 * n, st);
+        HIPCHK(hipStreamSynchronize(st));   // the small uploads are released here
+        S.solve_pairs_g += 2;
+    }
+    return true;
+}
+
+// Alg. 2 for up to RMAX subtasks at a time, each advancing on its own: a
+// subtask whose basis has converged is reconstructed and starts its next
+// step at once, while the others go on iterating. Every Krylov iteration
+// advances the largest group of running subtasks that use the same shift
+// (one factor per substitution pair), each at its own dimension; a subtask's
+// decisions (offsets, shift, step-down, halving) are those of the plain mode,
+// so both take the same steps. Slope changes come from the timing columns.
+// The shift of consecutive iterations stays the same while any subtask runs
+// with it, so the pair's columns fill up as they would in one lockstep pass,
+// and subtasks that finish and start their next step with that shift are
+// taken at once instead of idling to the end of the pass.
+void transient_batched_async(const matex_factor_s& F, const matex_problem* p, const matex_run_opts* o,
+                             const std::vector<std::vector<int32_t>>& subtasks, int64_t h_min, double ratio,
+                             bool trace, double* d_probe_out, double* d_final, matex_stats& S, hipStream_t st,
+                             bool* fell_back)
+{
+    const int64_t n = F.sym.n;
+    const int n_shifts = int(F.gammas.size());
+    const int32_t n_out = p->n_out, n_probe = p->n_probe;
+    const int64_t npo = int64_t(n_probe) * n_out;
+    const std::vector<int64_t> tout(p->t_out, p->t_out + n_out);
+    const int G = int(subtasks.size());
+    BatchWork bw(F, std::min(RMAX, G), n_out + 1, npo);
+    {
+        std::vector<int32_t> pp(std::max(1, n_probe));
+        for (int32_t k = 0; k < n_probe; ++k) pp[k] = F.sym.iperm[p->probe[k]];
+        bw.probe_perm = upload(pp);
+    }
+    const double base = o->output_droop ? 0.0 : F.vdd, sgn = o->output_droop ? 1.0 : -1.0;
+    launch_b_fill(npo, base, d_probe_out, st);
+    if (d_final) launch_b_fill(n, base, d_final, st);
+    enum Phase { SETUP, RESTART, RUN, FIN, DONE };
+    for (int b0 = 0; b0 < G; b0 += RMAX) {
+        const int R = std::min(RMAX, G - b0);
+        TimingCols tc;
+        if (!timing_cols(F, p, subtasks, b0, R, bw, tc, S, st)) {
+            *fell_back = true;
+            return;
+        }
+        std::vector<std::vector<int32_t>> my_cols(R);
+        for (size_t q = 0; q < tc.col.size(); ++q) my_cols[size_t(tc.col[q].sub)].push_back(int32_t(q));
+        std::vector<BCol> cols(R);
+        std::vector<int> ph(R, SETUP);
+        std::vector<char> full(R, 0);
+        for (int r = 0; r < R; ++r) {
+            cols[r].spots = plan_spots(p, subtasks[size_t(b0 + r)], F.sym.iperm);
+            S.subtasks++;
+        }
+        const size_t nr = sizeof(double) * size_t(n) * R;
+        for (DevMem* b : {&bw.y, &bw.y0, &bw.z1, &bw.z2, &bw.s, &bw.w}) HIPCHK(hipMemsetAsync(b->p, 0, nr, st));
+        if (npo) HIPCHK(hipMemsetAsync(bw.Yout.p, 0, sizeof(double) * npo * R, st));
+        std::vector<KsHost> hs(R, KsHost{});
+        auto offs_of = [&](int r) -> const std::vector<int64_t>& { return cols[r].offs; };
+        auto full_of = [&](int r) { return full[r] != 0; };
+        int cur_shift = -1;
+        while (true) {
+            // (1) subtasks starting a step: spot events, step plan, start vector
+            std::vector<int> su;
+            for (int r = 0; r < R; ++r)
+                if (ph[r] == SETUP || ph[r] == RESTART) su.push_back(r);
+            if (!su.empty()) {
+                std::vector<int32_t> eptr(R + 1, 0), eq;
+                std::vector<double> ecoef;
+                for (int r = 0; r < R; ++r) {
+                    if (ph[r] == SETUP) {
+                        BCol& c = cols[r];
+                        if (c.k_spot < c.spots.size() && c.spots[c.k_spot].t == c.t_a) {
+                            for (int32_t q : my_cols[r]) {
+                                const TimingCols::Col& tq = tc.col[size_t(q)];
+                                const int64_t te[4] = {tq.d, tq.d + tq.r, tq.d + tq.r + tq.w, tq.d + tq.r + tq.w + tq.f};
+                                const double ds[4] = {1.0 / (double(tq.r) * FS), -1.0 / (double(tq.r) * FS),
+                                                      -1.0 / (double(tq.f) * FS), 1.0 / (double(tq.f) * FS)};
+                                double coef = 0.0;
+                                bool any = false;
+                                for (int e = 0; e < 4; ++e)
+                                    if (te[e] == c.t_a && te[e] >= 0 && te[e] < p->t_end) { coef += ds[e]; any = true; }
+                                if (any) { eq.push_back(q); ecoef.push_back(coef); }
+                            }
+                            c.k_spot++;
+                        }
+                        c.offs = step_offsets(tout, c.t_a, c.spots[c.k_spot].t, &c.snap0);
+                        c.ksh = ladder_shift(F.gammas, c.offs[0], ratio);
+                        ladder_cut(c.offs, F.gammas, c.ksh);
+                    }
+                    eptr[r + 1] = int32_t(eq.size());
+                }
+                Packer pk(*bw.h_ev, bw.d_ev, bw.ev_bytes);
+                int32_t *d_ptr, *d_q, *d_act;
+                double* d_coef;
+                int32_t* h_ptr = pk.take<int32_t>(R + 1, &d_ptr);
+                int32_t* h_q = pk.take<int32_t>(std::max<size_t>(1, eq.size()), &d_q);
+                double* h_coef = pk.take<double>(std::max<size_t>(1, ecoef.size()), &d_coef);
+                int32_t* h_act = pk.take<int32_t>(R, &d_act);
+                std::copy(eptr.begin(), eptr.end(), h_ptr);
+                std::copy(eq.begin(), eq.end(), h_q);
+                std::copy(ecoef.begin(), ecoef.end(), h_coef);
+                std::fill(h_act, h_act + R, 0);
+                for (int r : su) { h_act[r] = 1; full[r] = 0; ph[r] = RUN; }
+                pk.upload(st);
+                if (!eq.empty())
+                    launch_b_spot_cols(n, R, d_ptr, d_q, d_coef, tc.Z1(), tc.Z2(), bw.z1.as<double>(),
+                                       bw.z2.as<double>(), st);
+                launch_b_setup(n, R, bw.y.as<double>(), bw.y0.as<double>(), bw.z2.as<double>(), bw.Vd(),
+                               bw.partial.as<double>(), bw.kst(), d_act, st, true);
+                hs = read_states(bw, R, st);   // the staging table is free again
+            }
+            // (2) one iteration of the running subtasks of one shift: the
+            // shift of the previous iteration while any subtask still runs
+            // with it (subtasks that start a step with that shift join at
+            // once), else the shift that most running subtasks use
+            std::vector<int> cnt_k(n_shifts, 0);
+            bool any_run = false;
+            for (int r = 0; r < R; ++r)
+                if (ph[r] == RUN && !hs[r].done) { cnt_k[cols[r].ksh]++; any_run = true; }
+            std::vector<int> grp;
+            if (any_run) {
+                if (cur_shift < 0 || cnt_k[cur_shift] == 0)
+                    cur_shift = int(std::max_element(cnt_k.begin(), cnt_k.end()) - cnt_k.begin());
+                const int k = cur_shift;
+                int nv = 1;
+                for (int r = 0; r < R; ++r)
+                    if (ph[r] == RUN && !hs[r].done && cols[r].ksh == k) { grp.push_back(r); nv = std::max(nv, hs[r].m + 1); }
+                CheckTab t = build_checks(bw, R, grp, offs_of, full_of, {}, st);
+                dev_solve_batched_ragged(F, k, R, bw, st);
+                launch_b_gs(n, R, bw.Vd(), nv, bw.w.as<double>(), bw.partial.as<double>(), bw.kst(), st, t.active, 1);
+                launch_tab_checks(F, bw, t, k, o->tol, o->m_max, 1, st);
+                S.solve_pairs_m++;
+                hs = read_states(bw, R, st);
+            }
+            // (3) decisions of the finished subtasks (the group's, and those
+            // whose start vector was zero)
+            std::vector<int> ver, fin, halve;
+            for (int r = 0; r < R; ++r) {
+                if (ph[r] != RUN || !hs[r].done) continue;
+                if (hs[r].converged) {
+                    if (!full[r] && hs[r].m > 0 && cols[r].offs.size() > 2) ver.push_back(r);
+                    else fin.push_back(r);
+                } else if (cols[r].ksh + 1 < n_shifts) {
+                    cols[r].ksh++;
+                    ladder_cut(cols[r].offs, F.gammas, cols[r].ksh);
+                    S.shift_downs++;
+                    S.bases++;
+                    S.krylov_dims += hs[r].m;
+                    ph[r] = RESTART;
+                } else {
+                    cols[r].hstep = cols[r].offs.back();
+                    halve.push_back(r);
+                }
+            }
+            if (!ver.empty()) {
+                // every offset evaluated once at the decided dimension (one
+                // table per shift)
+                std::vector<int> res;
+                std::vector<int> shifts;
+                for (int r : ver) shifts.push_back(cols[r].ksh);
+                std::sort(shifts.begin(), shifts.end());
+                shifts.erase(std::unique(shifts.begin(), shifts.end()), shifts.end());
+                for (int k : shifts) {
+                    std::vector<int> vk;
+                    for (int r : ver)
+                        if (cols[r].ksh == k) vk.push_back(r);
+                    CheckTab tv = build_checks(bw, R, vk, offs_of, [](int) { return true; }, {}, st);
+                    launch_tab_checks(F, bw, tv, k, o->tol, o->m_max, 0, st);
+                    std::vector<KsHost> hv = read_states(bw, R, st);
+                    for (int r : vk) {
+                        full[r] = 1;
+                        if (hv[r].converged) fin.push_back(r);
+                        else if (hv[r].m < o->m_max) res.push_back(r);
+                        else if (cols[r].ksh + 1 < n_shifts) {
+                            cols[r].ksh++;
+                            ladder_cut(cols[r].offs, F.gammas, cols[r].ksh);
+                            S.shift_downs++;
+                            S.bases++;
+                            S.krylov_dims += hv[r].m;
+                            ph[r] = RESTART;
+                        } else {
+                            cols[r].hstep = cols[r].offs.back();
+                            halve.push_back(r);
+                        }
+                        hs[r] = hv[r];
+                    }
+                }
+                if (!res.empty()) {
+                    std::vector<int32_t> ext(res.begin(), res.end());
+                    CheckTab tr = build_checks(bw, R, res, offs_of, full_of, ext, st);
+                    launch_b_resume(bw.kst(), tr.ext, int(res.size()), st);
+                    hs = read_states(bw, R, st);
+                }
+            }
+            // halve the step with the same basis until the checks pass
+            while (!halve.empty()) {
+                for (int r : halve) {
+                    BCol& c = cols[r];
+                    c.hstep /= 2;
+                    S.halvings++;
+                    if (c.hstep < h_min)
+                        throw NoConv{"no convergence at t = " + std::to_string(c.t_a) + " fs (subtask " +
+                                     std::to_string(b0 + r) + ")"};
+                    c.cand = halved_offsets(c.offs, c.hstep);
+                }
+                const int k = n_shifts - 1;
+                CheckTab t = build_checks(
+                    bw, R, halve, [&](int r) -> const std::vector<int64_t>& { return cols[r].cand; },
+                    [](int) { return true; }, {}, st);
+                launch_tab_checks(F, bw, t, k, o->tol, o->m_max, 0, st);
+                std::vector<KsHost> hh = read_states(bw, R, st);
+                std::vector<int> still;
+                for (int r : halve) {
+                    if (hh[r].converged) {
+                        cols[r].offs = cols[r].cand;
+                        fin.push_back(r);
+                    } else {
+                        still.push_back(r);
+                    }
+                }
+                halve.swap(still);
+            }
+            // (4) reconstruction of the finished steps; their next step starts
+            if (!fin.empty()) {
+                for (int r : fin) {
+                    S.bases++;
+                    S.krylov_dims += hs[r].m;
+                    S.m_peak = std::max(S.m_peak, hs[r].m);
+                }
+                reconstruct(bw, R, fin, cols, tout, n_probe, n_out, S, st);
+                for (int r : fin) ph[r] = cols[r].t_a < p->t_end ? SETUP : DONE;
+                HIPCHK(hipStreamSynchronize(st));   // the staging table of the reconstruction is free again
+            }
+            if (trace)
+                fprintf(stderr, "[matex] async batch %d: group %zu, verified %zu, finished %zu\n", b0 / RMAX,
+                        grp.size(), ver.size(), fin.size());
+            bool all_done = true;
+            for (int r = 0; r < R; ++r) all_done = all_done && ph[r] == DONE;
+            if (all_done) break;
+        }
+        launch_b_sum_out(npo, R, bw.Yout.as<double>(), sgn, d_probe_out, st);
+        if (d_final) launch_b_sum_final(n, R, F.d_perm.as<int32_t>(), bw.y.as<double>(), sgn, d_final, st);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+}
+
 // Alg. 2 for all subtasks, up to RMAX at a time in lockstep generations: in
 // each generation every unfinished subtask takes one step. Subtasks that
 // ask for different shifts of the ladder run in separate passes (the
@@ -2066,7 +2400,14 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
         std::vector<std::vector<int32_t>> subs;
         for (auto& g : groups) subs.push_back(g.second);
         try {
-            transient_batched(*f, p, o, subs, h_min, shift_ratio, trace, d_probe_out, d_final, S, st);
+            bool fell_back = o->batched_independent == 0;
+            if (!fell_back)
+                transient_batched_async(*f, p, o, subs, h_min, shift_ratio, trace, d_probe_out, d_final, S, st,
+                                        &fell_back);
+            if (fell_back) {
+                S = matex_stats{};
+                transient_batched(*f, p, o, subs, h_min, shift_ratio, trace, d_probe_out, d_final, S, st);
+            }
         } catch (const NoConv& e) {
             return fail(MATEX_E_NOCONV, e.msg);
         } catch (const HipError& e) {

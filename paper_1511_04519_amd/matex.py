@@ -58,7 +58,7 @@ class Problem(ctypes.Structure):
 
 class RunOpts(ctypes.Structure):
     _fields_ = [("tol", _f64), ("m_max", _i32), ("mode", _i32), ("h_min", _i64),
-                ("shift_ratio", _f64), ("output_droop", _i32), ("reserved_", _i32)]
+                ("shift_ratio", _f64), ("output_droop", _i32), ("batched_independent", _i32)]
 
 
 class Stats(ctypes.Structure):
@@ -262,7 +262,7 @@ def _problem_struct(prob, keep):
 
 def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
                     mode: int = MATEX_PLAIN, h_min: int = 1, device="cuda", final: bool = True,
-                    shift_ratio: float = 1.0, droop: bool = False):
+                    shift_ratio: float = 1.0, droop: bool = False, independent: bool = False):
     """Alg. 2 over every subtask, summed. Returns (x at probes (n_probe, n_out),
     x(t_end) (n,) or None, stats dict); with droop=True the droop y = Vdd - x
     instead of x."""
@@ -272,7 +272,8 @@ def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
     out = torch.empty((prob.probe.size, prob.t_out.size), dtype=torch.float64, device=device)
     fin = torch.empty(f.info["n"], dtype=torch.float64, device=device) if final else None
     st = Stats()
-    opts = RunOpts(float(tol), int(m_max), int(mode), int(h_min), float(shift_ratio), int(droop), 0)
+    opts = RunOpts(float(tol), int(m_max), int(mode), int(h_min), float(shift_ratio), int(droop),
+                   int(bool(independent)))
     _check(lib().matex_transient(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(out), _ptr(fin),
                                  ctypes.byref(st), _stream()))
     return out, fin, st.as_dict()

@@ -117,19 +117,22 @@ def test_adjoint_full_grid_against_forward_differences():
     (611, 1, 6, 5, 4, 4), (612, 2, 5, 4, 5, 1), (613, 1, 9, 3, 3, 13)])
 def test_adjoint_capacitances_match_oracle_differences(seed, layers, nx, ny, nsrc, every):
     """dJ/dc_i at every node against the oracle's complex-step derivative of
-    the dense Eq. 5 solution (J linear in x with random weights)."""
+    the dense Eq. 5 solution (J linear in x with random weights), per
+    coordinate: |g - g_ref| <= 1e-6 max(|g_ref|, 1e-3 max|g_ref|). With a
+    sample at every output about 1,500 adjoint steps contribute, each held to
+    tol relative to the largest jump: tol 1e-13 keeps their sum well inside."""
     _note(f"adjoint capacitances seed={seed} {layers}x{nx}x{ny}")
     p = I.small(seed, layers=layers, nx=nx, ny=ny, n_src=nsrc, t_end=1 * I.NS)
     F = M.matex_factor(p.netlist, GAMMA)
     w = _weights(p, every, seed)
-    ga, gc = M.matex_adjoint(F, p, _dev(w), tol=1e-11, m_max=30, grad_c=True)
+    ga, gc = M.matex_adjoint(F, p, _dev(w), tol=1e-13, m_max=30, grad_c=True)
     ref = A.c_gradient_cs(p, w)
     gc = gc.cpu().numpy()
     err = np.abs(gc - ref).max() / np.abs(ref).max()
-    print("capacitance rel err", err, "max |g|", np.abs(ref).max(), flush=True)
-    # bound: each adjoint step is held to 1e-11 of the largest jump, and with a
-    # sample at every output (100 samples) about 1,500 steps contribute
-    assert err <= 2e-6
+    bound = 1e-6 * np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())
+    worst = float((np.abs(gc - ref) / bound).max())
+    print("capacitance rel err", err, "max |g|", np.abs(ref).max(), "worst coordinate / bound", worst, flush=True)
+    assert worst <= 1.0
     # the amplitude gradients of the same call
     ra = A.amp_gradient(p, w)
     assert np.abs(ga.cpu().numpy() - ra).max() <= 1e-8 * np.abs(ra).max()

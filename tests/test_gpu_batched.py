@@ -134,3 +134,23 @@ def test_uneven_instances_concurrent():
     with pytest.raises(M.MatexError) as e:
         M.matex_transient_many(facs[:2], [probs[0], bad], n_streams=2)
     assert e.value.status == M.MATEX_E_INVALID and "instance 1" in str(e.value)
+
+
+@pytest.mark.parametrize("seed,layers,nx,ny,nsrc,groups", [
+    (421, 2, 14, 11, 20, 7), (422, 1, 19, 15, 30, 30), (423, 3, 10, 9, 12, 3)])
+def test_batched_independent_equals_lockstep(seed, layers, nx, ny, nsrc, groups):
+    """Subtasks advancing on their own (slope changes from solved timing
+    columns) and in lockstep generations (whole-batch G solves) take the
+    same steps and agree to rounding; both equal the oracle's modal truth."""
+    _note(f"independent vs lockstep seed={seed}")
+    p = I.small(seed, layers=layers, nx=nx, ny=ny, n_src=nsrc, t_end=3 * I.NS, n_groups=groups)
+    F = M.matex_factor(p.netlist, GAMMA)
+    xa, fa, sa = M.matex_transient(F, p, tol=1e-12, m_max=20, mode=M.MATEX_BATCHED, independent=True)
+    xl, fl, sl = M.matex_transient(F, p, tol=1e-12, m_max=20, mode=M.MATEX_BATCHED)
+    assert (sa["segments"], sa["bases"], sa["krylov_dims"]) == (sl["segments"], sl["bases"], sl["krylov_dims"])
+    d = float((xa - xl).abs().max())
+    print(f"max |independent - lockstep| = {d:.3e}, pairs {sa['solve_pairs_m']} vs {sl['solve_pairs_m']}", flush=True)
+    assert d <= 1e-13
+    assert float((fa - fl).abs().max()) <= 1e-13
+    ym, _ = R.modal(p)
+    assert np.abs(xa.cpu().numpy() - (p.netlist.vdd - ym)).max() <= 1e-10
