@@ -558,15 +558,18 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_update(int64_t n, const doubl
 // to working precision after the first pass, so there is no cancellation);
 // v_{j+1} = w'' / ||w''||, and column j of Ht = h1 + h2 with Ht(j+1,j) = ||w''||.
 // Every block sums the pass-2 partials itself; block 0 records the column.
-__device__ inline void publish_ticket(KState* ks, int32_t ticket)
+// The iteration's ticket: one more than the last one published (every
+// k_gs_finish launch publishes exactly once, so the count is the number of
+// iterations launched on this state, which the host counts too).
+__device__ inline void publish_ticket(KState* ks)
 {
-    __hip_atomic_store(&ks->ticket, ticket, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&ks->ticket, ks->ticket + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, int64_t ldv, int nv,
                                                    const double* __restrict__ w,
                                                    const double* partial_in, KState* ks,
-                                                   const int32_t* done, int32_t ticket)
+                                                   const int32_t* done)
 {
     __shared__ int32_t quit;
     done_stage(done, &quit);
@@ -574,7 +577,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, 
     __shared__ double sc;
     reduce_partials_waves<GS_WAVES>(partial_in, NVMAX + 1, gridDim.x, nv + 1, h);
     if (quit) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) publish_ticket(ks, ticket);
+        if (blockIdx.x == 0 && threadIdx.x == 0) publish_ticket(ks);
         return;
     }
     if (threadIdx.x == 0) {
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(GS_THREADS) void k_gs_finish(int64_t n, double* V, 
             ks->m = nv;
             ks->breakdown = brk ? 1 : 0;
             ks->brk[j] = brk ? 1 : 0;
-            publish_ticket(ks, ticket);
+            publish_ticket(ks);
         }
     }
     __syncthreads();
@@ -943,11 +946,10 @@ void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w
 }
 
 void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w,
-                      const double* partial, KState* ks, const int32_t* done, int32_t ticket,
-                      hipStream_t st)
+                      const double* partial, KState* ks, const int32_t* done, hipStream_t st)
 {
     const int64_t half = int64_t(RED_BLOCKS) * (MAXM + 2);
-    k_gs_finish<<<gs_grid(n), GS_THREADS, 0, st>>>(n, V, ldv, nv, w, partial + half, ks, done, ticket);
+    k_gs_finish<<<gs_grid(n), GS_THREADS, 0, st>>>(n, V, ldv, nv, w, partial + half, ks, done);
 }
 
 void launch_wait_ticket(KState* ks, int32_t ticket, int64_t max_ticks, hipStream_t st)

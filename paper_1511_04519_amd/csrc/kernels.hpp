@@ -107,12 +107,13 @@ void launch_gs_dots(int64_t n, const double* V, int64_t ldv, int nv, const doubl
                     double* partial, KState* ks, const int32_t* done, hipStream_t st);
 void launch_gs_update(int64_t n, const double* V, int64_t ldv, int nv, double* w,
                       double* partial, KState* ks, const int32_t* done, hipStream_t st);
-// ticket: the iteration's number, published in ks->ticket (agent-scope
-// release) once its Ht column, m and breakdown flags are written, also when
-// the state is done and the kernel does nothing else.
+// Publishes the iteration's ticket, ks->ticket + 1 (agent-scope release),
+// once its Ht column, m and breakdown flags are written, also when the state
+// is done and the kernel does nothing else: the ticket counts the
+// iterations launched on the state. No argument changes from one iteration
+// to the next, so an iteration can be replayed from a captured graph.
 void launch_gs_finish(int64_t n, double* V, int64_t ldv, int nv, const double* w,
-                      const double* partial, KState* ks, const int32_t* done, int32_t ticket,
-                      hipStream_t st);
+                      const double* partial, KState* ks, const int32_t* done, hipStream_t st);
 // One thread waits until ks->ticket has reached `ticket` (wrap-safe), so a
 // kernel queued after it on another stream sees that iteration's column
 // without a cross-stream event. After max_ticks of the 100 MHz device clock

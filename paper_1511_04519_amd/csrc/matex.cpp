@@ -562,9 +562,15 @@ struct Work {
     // main stream by about 20 us on MI355X
     hipStream_t cs = nullptr;
     int32_t ticket = 0;                // number of the last iteration launched
+    // iteration graphs (MATEX_GRAPHS=1), keyed by shift and iteration
+    bool use_graphs = false;
+    hipStream_t gs = nullptr;          // capture stream
+    std::map<int, hipGraphExec_t> graphs;
     Work(const Work&) = delete;
     Work& operator=(const Work&) = delete;
     ~Work() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        if (gs) (void)hipStreamDestroy(gs);
         if (cs) (void)hipStreamDestroy(cs);
     }
     Work(const matex_factor_s& F, int64_t max_chk) {
@@ -582,6 +588,8 @@ struct Work {
         est = DevMem(sizeof(double) * max_checks);
         taus = DevMem(sizeof(double) * max_checks);
         sel = DevMem(sizeof(int32_t) * 2);
+        const char* ge = std::getenv("MATEX_GRAPHS");
+        use_graphs = ge && ge[0] == '1';
     }
     KState* kst() const { return ks.as<KState>(); }
     const int32_t* done() const { return &ks.as<KState>()->done; }
@@ -615,7 +623,7 @@ double read_est(const Work& wk, double* pinned, hipStream_t st)
 
 // One Krylov iteration j (0-based): w = M^-1 C v_j, two Gram-Schmidt passes,
 // v_{j+1} and column j of Ht.
-void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, hipStream_t st)
+void iteration_launches(const matex_factor_s& F, int shift, Work& wk, int j, hipStream_t st)
 {
     const int64_t n = wk.n;
     double* V = wk.V.as<double>();
@@ -623,8 +631,37 @@ void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, hipSt
               wk.tmp.as<double>(), wk.upd.as<double>(), wk.done(), st);
     launch_gs_dots(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
     launch_gs_update(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
-    launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(),
-                     ++wk.ticket, st);
+    launch_gs_finish(n, V, n, j + 1, wk.w.as<double>(), wk.partial.as<double>(), wk.kst(), wk.done(), st);
+}
+
+// With graphs on (MATEX_GRAPHS=1 when the work is made), the launches of
+// iteration j with shift k are captured once on the work's capture stream
+// (kernels only: no copy or fill) and replayed on st as one graph; every
+// argument is fixed for the work's lifetime (the ticket is counted on the
+// device).
+
+void krylov_iteration(const matex_factor_s& F, int shift, Work& wk, int j, hipStream_t st)
+{
+    ++wk.ticket;
+    if (!wk.use_graphs) {
+        iteration_launches(F, shift, wk, j, st);
+        return;
+    }
+    const int key = shift * (MAXM + 1) + j;
+    auto it = wk.graphs.find(key);
+    if (it == wk.graphs.end()) {
+        if (!wk.gs) HIPCHK(hipStreamCreateWithFlags(&wk.gs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(wk.gs, hipStreamCaptureModeThreadLocal));
+        iteration_launches(F, shift, wk, j, wk.gs);
+        HIPCHK(hipStreamEndCapture(wk.gs, &g));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+        it = wk.graphs.emplace(key, ex).first;
+    }
+    HIPCHK(hipGraphLaunch(it->second, st));
 }
 
 // Host-side timing of the iteration loop (diagnostics, MATEX_HOST_TIMES=1):
@@ -2797,7 +2834,8 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                 launch_gs_update(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
                                  wf->done(), st);
                 launch_gs_finish(n, Vf, n, j + 1, wf->w.as<double>(), wf->partial.as<double>(), wf->kst(),
-                                 wf->done(), ++wf->ticket, st);
+                                 wf->done(), st);
+                ++wf->ticket;
             }
         };
         if (d_grad_c) {

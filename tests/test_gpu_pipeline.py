@@ -48,3 +48,23 @@ def test_pipeline_counts_and_diagnostics(capfd):
     assert np.array_equal(x2.cpu().numpy(), x)
     assert np.array_equal(xf2.cpu().numpy(), xf.cpu().numpy())
     assert st2["krylov_dims"] == st["krylov_dims"] and st2["segments"] == st["segments"]
+
+
+def test_graph_replayed_iterations_match_eager(monkeypatch):
+    """Krylov iterations replayed from captured graphs (MATEX_GRAPHS=1): each
+    (shift, dimension) graph is replayed many times in one transient, between
+    the checks' eager launches and the host's synchronisations; the outputs
+    equal the eager launches' bit for bit, on two transients in a row."""
+    import numpy as np
+    from paper_1511_04519_amd import instances as I
+    from paper_1511_04519_amd import matex as M
+    p = I.small(91, layers=2, nx=14, ny=12, n_src=12, t_end=2 * I.NS)
+    F = M.matex_factor(p.netlist, p.gamma)
+    monkeypatch.setenv("MATEX_GRAPHS", "0")
+    xe, fe, se = M.matex_transient(F, p, tol=1e-12)
+    monkeypatch.setenv("MATEX_GRAPHS", "1")
+    for _ in range(2):
+        xg, fg, sg = M.matex_transient(F, p, tol=1e-12)
+        assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy())
+        assert np.array_equal(fg.cpu().numpy(), fe.cpu().numpy())
+        assert (sg["bases"], sg["krylov_dims"]) == (se["bases"], se["krylov_dims"])
