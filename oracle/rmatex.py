@@ -289,3 +289,64 @@ class RMatex:
             y_out += o
             y_end += ye
         return self.nl.vdd - y_out, y_end
+
+
+class IMatex(RMatex):
+    """I-MATEX (Sec. 3.3.1): the inverted Krylov subspace K_m(A^-1, v).
+
+    Alg. 1 with X1 = G (factored once) and X2 = C: each step is
+    w = G^-1 (C v_j) = -A^-1 v_j, so the Arnoldi matrix H' of this process is
+    minus that of A^-1 and H_m = (-H')^-1 = -H'^-1. The stopping estimate is
+    the empirical one of Sec. 3.3.3 with h_{m+1,m} = h'_{m+1,m} (the same
+    estimate as R-MATEX, difference term included). There is no shift, so no
+    ladder: a segment that does not converge within m_max is halved (Alg. 2).
+    """
+
+    def __init__(self, netlist):
+        self.nl = netlist
+        self.n = netlist.n
+        self.gammas = [np.inf]          # one factor; pick_shift keeps whole segments
+        self.c = np.asarray(netlist.c_node, dtype=np.float64)
+        rp, ci, gv = assemble_G(netlist)
+        self.G = (rp, ci, gv)
+        self.Gf = Cholesky(rp, ci, gv)
+        self.stats = Stats()
+        self.trace = False
+
+    def arnoldi(self, v: np.ndarray, check_taus, tol: float, m_max: int,
+                safety: float = 1.0, breakdown: float = 1e-14, shift: int = 0):
+        """Inverted Arnoldi on K_m(G^-1 C, v); returns (basis, converged) with
+        the stopping rule applied as in RMatex.arnoldi."""
+        n = v.size
+        taus = np.sort(np.asarray(check_taus, dtype=np.float64))
+        beta = float(np.linalg.norm(v))
+        if beta == 0.0:
+            return KrylovBasis(np.zeros((n, 0)), np.zeros((0, 0)), 0.0, 0.0, 0, True), True
+        V = np.zeros((n, m_max + 1))
+        Hp = np.zeros((m_max + 1, m_max))
+        V[:, 0] = v / beta
+        basis = None
+        for j in range(m_max):
+            w = self.Gf.solve(self.c * V[:, j])          # X1^-1 (X2 v_j), X1 = G
+            self.stats.solve_pairs_M += 1
+            for i in range(j + 1):                         # modified Gram-Schmidt
+                Hp[i, j] = w @ V[:, i]
+                w = w - Hp[i, j] * V[:, i]
+            Hp[j + 1, j] = np.linalg.norm(w)
+            m = j + 1
+            Hprev = basis.Hm if basis is not None else None
+            Hm = -np.linalg.inv(Hp[:m, :m])
+            exact = Hp[j + 1, j] <= breakdown * np.abs(Hp[:m + 1, :m]).max()
+            basis = KrylovBasis(V[:, :m].copy(), Hm, beta, float(Hp[j + 1, j]), m,
+                                bool(exact), Hprev)
+            if exact:
+                self.stats.m_hist.append(m)
+                return basis, True
+            V[:, j + 1] = w / Hp[j + 1, j]
+            ends = (taus[0], taus[-1])
+            if all(safety * basis.estimate(t) < tol for t in ends):
+                if all(safety * basis.estimate(t) < tol for t in taus):
+                    self.stats.m_hist.append(m)
+                    return basis, True
+        self.stats.m_hist.append(basis.m)
+        return basis, False
