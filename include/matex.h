@@ -175,7 +175,8 @@ matex_status matex_solve_noalloc(matex_factor_t f, int32_t which, const double* 
 /*
  * matex_krylov_step - e^{tau_k A} v_r (Eq. 9) for every tau_k and every
  * right-hand side v_r, with one rational Krylov basis per v_r (Alg. 1 with
- * X1 = C + gamma_s G, X2 = C; shift index `shift` of the ladder).
+ * X1 = C + gamma_s G, X2 = C; shift index `shift` of the ladder), or with
+ * shift = -1 one inverted Krylov basis (X1 = G, X2 = C, Sec. 3.3.1).
  * d_v: device, n x nrhs column-major, natural order. tau: host [n_tau],
  * seconds, > 0. Stops at the first m whose estimate is < tol for every tau
  * (the estimate is the larger of the empirical form of Sec. 3.3.3 and the
@@ -210,6 +211,14 @@ typedef struct {
 
 typedef enum { MATEX_PLAIN = 0, MATEX_BATCHED = 1 } matex_mode;
 
+/* The Krylov subspace of Alg. 1. MATEX_RATIONAL: R-MATEX (Sec. 3.3.2),
+ * X1 = C + gamma_k G with the shift ladder, H_m = (I - Ht_m^-1) / gamma_k.
+ * MATEX_INVERTED: I-MATEX (Sec. 3.3.1), X1 = G (the factor's last panel
+ * set), X2 = C, H_m = H'_m^-1 with H' the Arnoldi matrix of A^-1; one
+ * factor, so a step that does not converge within m_max is only halved.
+ * Both use the empirical estimate of Sec. 3.3.3 with the difference term. */
+typedef enum { MATEX_RATIONAL = 0, MATEX_INVERTED = 1 } matex_krylov;
+
 typedef struct {
     double tol;              /* per-basis error estimate bound (V), > 0          */
     int32_t m_max;           /* largest Krylov dimension, 1..32                  */
@@ -229,6 +238,10 @@ typedef struct {
                                 lockstep when those do not fit half the free
                                 memory); the same steps and results to
                                 rounding, more pairs on the 1M-node workload  */
+    int32_t krylov;          /* MATEX_RATIONAL (0) or MATEX_INVERTED (1); with
+                                MATEX_INVERTED, batched subtasks run in
+                                lockstep, and matex_adjoint refuses it        */
+    int32_t reserved_;       /* 0                                               */
 } matex_run_opts;
 
 typedef struct {

@@ -403,7 +403,10 @@ __device__ inline void solve_wave(double* Q, double* P, int m, int ncol)
     }
 }
 
-// H = (I - Ht_m^-1) / gamma into H (row-major, stride L); uses T1.
+// H_m from the process's Arnoldi matrix Ht_m into H (row-major, stride L);
+// uses T1. Rational space (X1 = C + gamma G, gamma > 0; Sec. 3.3.2):
+// H_m = (I - Ht_m^-1) / gamma. Inverted space (X1 = G, passed as gamma = 0;
+// Sec. 3.3.1): the process runs on G^-1 C = -A^-1, so H_m = -Ht_m^-1.
 template <int L = LD>
 __device__ inline void form_h(const KState* ks, int m, double gamma, double* H, double* T1)
 {
@@ -416,7 +419,7 @@ __device__ inline void form_h(const KState* ks, int m, double gamma, double* H, 
     __syncthreads();
     for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
         const int i = idx / m, j = idx % m;
-        H[i * L + j] = ((i == j ? 1.0 : 0.0) - H[i * L + j]) / gamma;
+        H[i * L + j] = gamma > 0.0 ? ((i == j ? 1.0 : 0.0) - H[i * L + j]) / gamma : -H[i * L + j];
     }
     __syncthreads();
 }

@@ -198,6 +198,13 @@ struct matex_factor_s {
     }
 };
 
+// gamma of factor index k as the check kernels take it: gamma_k for a shift
+// of the ladder, 0 for G (the inverted space of Sec. 3.3.1, X1 = G).
+inline double shift_gamma(const matex_factor_s& F, int k)
+{
+    return k < int(F.gammas.size()) ? F.gammas[k] : 0.0;
+}
+
 namespace {
 
 // Blocks the device holds at once at 256 threads each (256 compute units x 8).
@@ -712,7 +719,7 @@ KsHost run_arnoldi(const matex_factor_s& F, int shift, Work& wk, int n_tau, doub
     // a zero start vector has the state done already: the first check then
     // returns at once and its read shows it
     KsHost h{};
-    const double gamma = F.gammas[shift];
+    const double gamma = shift_gamma(F, shift);
     auto launch_iter = [&](int i) {
         const double t0 = now_s();
         g_host_times.stamp(0, st);
@@ -1186,7 +1193,8 @@ matex_status matex_krylov_step(matex_factor_t f, int32_t shift, int32_t nrhs, co
 {
     if (!f || !d_v || !d_out || !tau || nrhs < 0 || n_tau <= 0)
         return fail(MATEX_E_INVALID, "bad argument");
-    if (shift < 0 || shift >= int(f->gammas.size())) return fail(MATEX_E_INVALID, "shift out of range");
+    if (shift < -1 || shift >= int(f->gammas.size())) return fail(MATEX_E_INVALID, "shift out of range");
+    if (shift < 0) shift = int(f->gammas.size());   // the inverted space, X1 = G
     if (m_max < 1 || m_max > MAXM) return fail(MATEX_E_INVALID, "m_max must be in 1..32");
     if (!(tol >= 0.0)) return fail(MATEX_E_INVALID, "tol must be >= 0");
     for (int k = 0; k < n_tau; ++k)
@@ -1468,7 +1476,7 @@ CheckTab build_checks(BatchWork& bw, int R, const std::vector<int>& cols_in, Off
 void launch_tab_checks(const matex_factor_s& F, BatchWork& bw, const CheckTab& t, int k, double tol, int m_max,
                        int update, hipStream_t st)
 {
-    launch_b_checks(bw.kst(), F.gammas[k], t.taus, t.off, bw.cap, t.col, t.idx, t.coff, t.ccnt, t.n_chk, tol,
+    launch_b_checks(bw.kst(), shift_gamma(F, k), t.taus, t.off, bw.cap, t.col, t.idx, t.coff, t.ccnt, t.n_chk, tol,
                     bw.u.as<double>(), bw.est.as<double>(), m_max, update, st);
 }
 
@@ -1948,6 +1956,7 @@ void transient_batched(const matex_factor_s& F, const matex_problem* p, const ma
     const double base = o->output_droop ? 0.0 : F.vdd, sgn = o->output_droop ? 1.0 : -1.0;
     launch_b_fill(npo, base, d_probe_out, st);
     if (d_final) launch_b_fill(n, base, d_final, st);
+    const bool inverted = o->krylov == MATEX_INVERTED;
     int m_guess = 6;
     for (int b0 = 0; b0 < G; b0 += RMAX) {
         const int R = std::min(RMAX, G - b0);
@@ -2012,8 +2021,12 @@ void transient_batched(const matex_factor_s& F, const matex_problem* p, const ma
             for (int r : act) {
                 BCol& c = cols[r];
                 c.offs = step_offsets(tout, c.t_a, c.spots[c.k_spot].t, &c.snap0);
-                c.ksh = ladder_shift(F.gammas, c.offs[0], ratio);
-                ladder_cut(c.offs, F.gammas, c.ksh);
+                if (inverted) {
+                    c.ksh = n_shifts;   // G: no ladder
+                } else {
+                    c.ksh = ladder_shift(F.gammas, c.offs[0], ratio);
+                    ladder_cut(c.offs, F.gammas, c.ksh);
+                }
             }
             std::vector<int> pending = act;
             while (!pending.empty()) {
@@ -2114,6 +2127,7 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
 {
     const int64_t n = f->sym.n;
     const int n_shifts = int(f->gammas.size());
+    const bool inverted = o->krylov == MATEX_INVERTED;
     const int32_t n_out = p->n_out, n_probe = p->n_probe;
     // largest check set: outputs inside one spot interval + 1
     Work wk(*f, int64_t(n_out) + 1);
@@ -2251,8 +2265,11 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
             }
             int32_t snap0 = 0;
             std::vector<int64_t> offs = step_offsets(tout, t_a, spots[k_spot].t, &snap0);
-            int ksh = ladder_shift(f->gammas, offs[0], shift_ratio);
-            ladder_cut(offs, f->gammas, ksh);
+            int ksh = n_shifts;   // the inverted space: G, no ladder
+            if (!inverted) {
+                ksh = ladder_shift(f->gammas, offs[0], shift_ratio);
+                ladder_cut(offs, f->gammas, ksh);
+            }
             KsHost h{};
             int launched = 0;
             std::vector<double> ests;
@@ -2286,7 +2303,7 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
                     fprintf(stderr, "[matex] not converged t_a=%lld shift=%d m=%d est=%.3e checks=%zu first=%lld last=%lld\n",
                             (long long)t_a, ksh, h.m, read_est(wk, hest, st), offs.size(),
                             (long long)offs[0], (long long)offs.back());
-                if (h.converged || ksh + 1 == n_shifts) break;
+                if (h.converged || ksh + 1 >= n_shifts) break;
                 ksh++;
                 S.shift_downs++;
                 ladder_cut(offs, f->gammas, ksh);
@@ -2303,7 +2320,7 @@ static void transient_plain(matex_factor_s* f, const matex_problem* p, const mat
                     std::vector<double> taus(o2.size());
                     for (size_t q = 0; q < o2.size(); ++q) taus[q] = double(o2[q]) * FS;
                     ring.copy(wk.taus.p, taus.data(), sizeof(double) * taus.size(), st);
-                    launch_checks(wk.kst(), f->gammas[ksh], wk.taus.as<double>(), nullptr, int(taus.size()),
+                    launch_checks(wk.kst(), shift_gamma(*f, ksh), wk.taus.as<double>(), nullptr, int(taus.size()),
                                   o->tol, wk.u.as<double>(), wk.est.as<double>(), o->m_max, 0, -1, st);
                     KsHost hh = read_state(wk, hks, st);
                     if (trace)
@@ -2380,6 +2397,8 @@ static matex_status check_problem(matex_factor_t f, const matex_problem* p, cons
         return fail(MATEX_E_INVALID, "null source array");
     if (!p->t_out || (p->n_probe > 0 && !p->probe)) return fail(MATEX_E_INVALID, "null array");
     if (o->mode != MATEX_PLAIN && o->mode != MATEX_BATCHED) return fail(MATEX_E_INVALID, "unknown mode");
+    if (o->krylov != MATEX_RATIONAL && o->krylov != MATEX_INVERTED)
+        return fail(MATEX_E_INVALID, "unknown Krylov subspace");
     if (o->m_max < 1 || o->m_max > MAXM) return fail(MATEX_E_INVALID, "m_max must be in 1..32");
     if (!(o->tol > 0.0)) return fail(MATEX_E_INVALID, "tol must be > 0");
     for (int32_t k = 0; k < p->n_src; ++k) {
@@ -2437,7 +2456,7 @@ extern "C" matex_status matex_transient(matex_factor_t f, const matex_problem* p
         std::vector<std::vector<int32_t>> subs;
         for (auto& g : groups) subs.push_back(g.second);
         try {
-            bool fell_back = o->batched_independent == 0;
+            bool fell_back = o->batched_independent == 0 || o->krylov == MATEX_INVERTED;
             if (!fell_back)
                 transient_batched_async(*f, p, o, subs, h_min, shift_ratio, trace, d_probe_out, d_final, S, st,
                                         &fell_back);
@@ -2482,6 +2501,7 @@ extern "C" matex_status matex_trapezoidal(matex_factor_t f, const matex_problem*
     if (!d_probe_out || !o) return fail(MATEX_E_INVALID, "null argument");
     matex_run_opts oo = *o;
     oo.mode = MATEX_PLAIN;
+    oo.krylov = MATEX_RATIONAL;
     if (!(oo.tol > 0.0)) oo.tol = 1.0;
     if (oo.m_max < 1) oo.m_max = 1;
     if (matex_status cs = check_problem(f, p, &oo)) return cs;
@@ -2656,6 +2676,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
     if (!d_dJdx) return fail(MATEX_E_INVALID, "null argument");
     if (matex_status cs = check_problem(f, p, o)) return cs;
     if (o->m_max > MAXM - 2) return fail(MATEX_E_INVALID, "m_max must be <= 30 for the adjoint");
+    if (o->krylov != MATEX_RATIONAL) return fail(MATEX_E_INVALID, "the adjoint runs the rational space only");
     const int64_t n = f->sym.n;
     const int n_shifts = int(f->gammas.size());
     const int32_t n_out = p->n_out, n_probe = p->n_probe, n_src = p->n_src;
@@ -2900,7 +2921,7 @@ extern "C" matex_status matex_adjoint(matex_factor_t f, const matex_problem* p, 
                                wk.partial.as<double>(), wk.kst(), st);
                 launch_normalize_v(n, V, wk.partial.as<double>(), wk.kst(), st);
                 h = run_arnoldi(*f, ksh, wk, 1, o->tol, o->m_max, hks, st);
-                if (h.converged || ksh + 1 == n_shifts) break;
+                if (h.converged || ksh + 1 >= n_shifts) break;
                 ksh++;
             }
             if (trace)

@@ -24,6 +24,7 @@ LIB_PATH = os.path.join(_HERE, "libmatex.so")
 MATEX_OK, MATEX_E_INVALID, MATEX_E_NOT_SPD, MATEX_E_OOM, MATEX_E_HIP, MATEX_E_NOCONV, \
     MATEX_E_UNSUPPORTED, MATEX_E_NONFINITE = range(8)
 MATEX_PLAIN, MATEX_BATCHED = 0, 1
+MATEX_RATIONAL, MATEX_INVERTED = 0, 1
 
 _i32, _i64, _f64, _vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
 _pi32, _pi64, _pf64 = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
@@ -58,7 +59,8 @@ class Problem(ctypes.Structure):
 
 class RunOpts(ctypes.Structure):
     _fields_ = [("tol", _f64), ("m_max", _i32), ("mode", _i32), ("h_min", _i64),
-                ("shift_ratio", _f64), ("output_droop", _i32), ("batched_independent", _i32)]
+                ("shift_ratio", _f64), ("output_droop", _i32), ("batched_independent", _i32),
+                ("krylov", _i32), ("reserved_", _i32)]
 
 
 class Stats(ctypes.Structure):
@@ -228,7 +230,9 @@ def matex_solve_noalloc(f: FactorHandle, which: int, b, x, scale=None):
 def matex_krylov_step(f: FactorHandle, v, taus, shift: int = 0, m_max: int = 20,
                       tol: float = 1e-12):
     """e^{tau A} v for every tau (seconds). v: (n,) or (nrhs, n) device tensor.
-    Returns (out (n_tau, nrhs, n), m_used[nrhs], est[nrhs], converged)."""
+    shift: index of the ladder's shift (rational space), or -1 for the
+    inverted space (X1 = G). Returns (out (n_tau, nrhs, n), m_used[nrhs],
+    est[nrhs], converged)."""
     import torch
     n = f.info["n"]
     v2 = v.reshape(-1, n).contiguous()
@@ -262,7 +266,8 @@ def _problem_struct(prob, keep):
 
 def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
                     mode: int = MATEX_PLAIN, h_min: int = 1, device="cuda", final: bool = True,
-                    shift_ratio: float = 1.0, droop: bool = False, independent: bool = False):
+                    shift_ratio: float = 1.0, droop: bool = False, independent: bool = False,
+                    krylov: int = MATEX_RATIONAL):
     """Alg. 2 over every subtask, summed. Returns (x at probes (n_probe, n_out),
     x(t_end) (n,) or None, stats dict); with droop=True the droop y = Vdd - x
     instead of x."""
@@ -273,7 +278,7 @@ def matex_transient(f: FactorHandle, prob, tol: float = 1e-11, m_max: int = 20,
     fin = torch.empty(f.info["n"], dtype=torch.float64, device=device) if final else None
     st = Stats()
     opts = RunOpts(float(tol), int(m_max), int(mode), int(h_min), float(shift_ratio), int(droop),
-                   int(bool(independent)))
+                   int(bool(independent)), int(krylov))
     _check(lib().matex_transient(f.handle, ctypes.byref(pr), ctypes.byref(opts), _ptr(out), _ptr(fin),
                                  ctypes.byref(st), _stream()))
     return out, fin, st.as_dict()
@@ -298,7 +303,8 @@ def matex_trapezoidal(f: FactorHandle, prob, h_fs: int, device="cuda", final: bo
 
 def matex_transient_many(factors, probs, tol: float = 1e-11, m_max: int = 20,
                          mode: int = MATEX_PLAIN, h_min: int = 1, n_streams: int = 4,
-                         device="cuda", final: bool = True, shift_ratio: float = 1.0):
+                         device="cuda", final: bool = True, shift_ratio: float = 1.0,
+                         krylov: int = MATEX_RATIONAL):
     """Independent instances (own factor each) advanced concurrently on
     n_streams library streams. Returns a list of (x, x_final or None, stats)."""
     import torch
@@ -312,7 +318,7 @@ def matex_transient_many(factors, probs, tol: float = 1e-11, m_max: int = 20,
     po = (_vp * max(1, k))(*[_ptr(t) for t in outs])
     pf = (_vp * max(1, k))(*[_ptr(t) for t in fins]) if final else None
     opts = (RunOpts * max(1, k))(*[RunOpts(float(tol), int(m_max), int(mode), int(h_min),
-                                           float(shift_ratio)) for _ in range(k)])
+                                           float(shift_ratio), 0, 0, int(krylov)) for _ in range(k)])
     sts = (Stats * max(1, k))()
     _check(lib().matex_transient_many(k, fh, prs, opts, po, pf, sts, int(n_streams), _stream()))
     return [(outs[i], fins[i] if final else None, sts[i].as_dict()) for i in range(k)]

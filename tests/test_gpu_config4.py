@@ -1,0 +1,105 @@
+"""The adjoint workload on the 180k-node grid (2 x 300 x 300, 2000 sources,
+20 ns): 512 observed bottom-layer nodes (the probes), samples at s * 0.1 ns
+for s = 1..200.
+
+* The literal objective J = sum over samples and nodes of max(0, 0.95 - v)^2
+  is identically zero on this grid (its droop stays below 0.5 mV), so J = 0
+  and its gradients are zero.
+* The thresholded J_q = sum max(0, y - theta)^2 of the droop y = Vdd - v,
+  theta the 90th percentile of the sampled droops (a tenth of the samples
+  active), is differentiated by matex_adjoint with respect to all 2000
+  amplitudes and all 180k capacitances.
+* Amplitudes: 25 seeded sources against central differences of J_q with the
+  relative step 1e-6. The two perturbed forward runs come from linearity in
+  the amplitudes (Sec. 3.1): y(a +- d e_k) = y(a) +- d y_k, y_k the GPU
+  droop of source k alone at unit amplitude. Pass rule per coordinate:
+  |g - g_fd| <= 1e-6 max(|g_fd|, 1e-3 max|g_fd|).
+* Capacitances: the node of the largest gradient against central
+  differences of two refactored 20 ns forward runs (relative step 1e-4,
+  tolerance 1e-13). Each coordinate costs two factorisations and two full
+  forward runs (about a minute), so one coordinate is checked; the
+  oracle's complex-step references check every node on small grids."""
+import numpy as np
+import pytest
+
+from paper_1511_04519_amd import instances as I
+from paper_1511_04519_amd import matex as M
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _note(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def adj():
+    p = I.config1()
+    samp = np.zeros(p.t_out.size, bool)
+    samp[10::10] = True                                   # t = s * 0.1 ns, s = 1..200
+    assert samp.sum() == 200 and p.probe.size == 512
+    F = M.matex_factor(p.netlist, p.gamma)
+    y, _, _ = M.matex_transient(F, p, tol=1e-13, m_max=24, final=False, droop=True)
+    y = y.cpu().numpy()
+    ys = y[:, samp]
+    theta = float(np.quantile(ys, 0.9))
+    w = np.zeros_like(y)
+    w[:, samp] = -2.0 * np.maximum(0.0, ys - theta)       # dJ_q/dv
+    ga, gc = M.matex_adjoint(F, p, torch.as_tensor(w, device="cuda:0"), tol=1e-13, m_max=30, grad_c=True)
+    return dict(p=p, F=F, samp=samp, ys=ys, theta=theta, ga=ga.cpu().numpy(), gc=gc.cpu().numpy())
+
+
+def _jq(ys, theta):
+    return float(np.sum(np.maximum(0.0, ys - theta) ** 2))
+
+
+def test_config4_literal_objective_is_zero(adj):
+    _note("config4 literal J")
+    p, ys = adj["p"], adj["ys"]
+    v = p.netlist.vdd - ys
+    assert float(np.sum(np.maximum(0.0, 0.95 - v) ** 2)) == 0.0
+    w = torch.zeros((p.probe.size, p.t_out.size), dtype=torch.float64, device="cuda:0")
+    ga, gc = M.matex_adjoint(adj["F"], p, w, tol=1e-10, m_max=30, grad_c=True)
+    assert not ga.any().item() and not gc.any().item()
+
+
+def test_config4_amplitude_gradients_against_differences(adj):
+    _note("config4 J_q amplitudes")
+    p, ga, samp, ys, theta = adj["p"], adj["ga"], adj["samp"], adj["ys"], adj["theta"]
+    s = p.sources
+    ks = np.random.default_rng(44).choice(s.n_src, 25, replace=False)
+    fd = np.zeros(ks.size)
+    for i, k in enumerate(ks):
+        one = I.Sources(s.node[k:k + 1], np.ones(1), s.delay[k:k + 1], s.rise[k:k + 1], s.width[k:k + 1],
+                        s.fall[k:k + 1], np.zeros(1, s.group.dtype))
+        q = I.Problem(p.name, p.netlist, one, p.t_end, p.t_out, p.probe)
+        yk, _, _ = M.matex_transient(adj["F"], q, tol=1e-13, m_max=24, final=False, droop=True)
+        yk = yk.cpu().numpy()[:, samp]
+        d = 1e-6 * abs(s.amp[k])
+        fd[i] = (_jq(ys + d * yk, theta) - _jq(ys - d * yk, theta)) / (2 * d)
+    bound = 1e-6 * np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
+    worst = float((np.abs(ga[ks] - fd) / bound).max())
+    print(f"amplitudes: max |g| {np.abs(fd).max():.3e}, worst |g - g_fd| / bound {worst:.3f}", flush=True)
+    assert worst <= 1.0
+
+
+def test_config4_capacitance_gradient_against_differences(adj):
+    _note("config4 J_q capacitance")
+    p, gc, samp, theta = adj["p"], adj["gc"], adj["samp"], adj["theta"]
+    nl = p.netlist
+    i = int(np.argmax(np.abs(gc)))
+    vals = []
+    for sg in (1, -1):
+        c2 = nl.c_node.copy()
+        c2[i] *= 1.0 + sg * 1e-4
+        nl2 = I.Netlist(nl.n, nl.br_a, nl.br_b, nl.br_g, c2, nl.pad_node, nl.pad_g, nl.vdd, nl.coord)
+        F2 = M.matex_factor(nl2, p.gamma)
+        y2, _, _ = M.matex_transient(F2, I.Problem(p.name, nl2, p.sources, p.t_end, p.t_out, p.probe),
+                                     tol=1e-13, m_max=24, final=False, droop=True)
+        vals.append(_jq(y2.cpu().numpy()[:, samp], theta))
+        del F2
+    fd = (vals[0] - vals[1]) / (2e-4 * nl.c_node[i])
+    rel = abs(gc[i] - fd) / abs(fd)
+    print(f"node {i}: adjoint {gc[i]:.12e} differences {fd:.12e} rel {rel:.2e}", flush=True)
+    assert rel <= 5e-6
