@@ -95,7 +95,11 @@ typedef struct {
                                 of C + gamma G); 1 = fixed (256-column split
                                 tasks on every level); 2 = fixed (one
                                 wavefront per supernode where allowed, else
-                                64-column split tasks)                        */
+                                64-column split tasks). With the environment
+                                variable MATEX_TUNE_CACHE naming a file, 0
+                                first looks the factor's structure up there
+                                and takes the recorded choice (no timing),
+                                else tunes and appends its choice          */
 } matex_factor_opts;
 
 typedef struct {

@@ -436,8 +436,88 @@ void build_tasks(matex_factor_s& F, int32_t subtree_limit)
 // after one untimed launch), and the fastest forward and the fastest
 // backward are kept. The choice depends on the structure and the device
 // only; values do not change the timing (zero right-hand sides).
+void keep_batched_choice(matex_factor_s& F, int lv, int bf, int bb)
+{
+    const auto& cand = F.bcand[size_t(lv)];
+    BatchLevel m = cand[size_t(bf)].lv;
+    const BatchLevel& mb = cand[size_t(bb)].lv;
+    m.bwd = mb.bwd; m.n_bwd = mb.n_bwd; m.bred = mb.bred; m.n_bred = mb.n_bred;
+    m.bwave = mb.bwave; m.n_bwave = mb.n_bwave;
+    m.fwave = cand[size_t(bf)].lv.fwave;
+    m.n_fwave = cand[size_t(bf)].lv.n_fwave;
+    m.wave_nc = std::max(cand[size_t(bf)].lv.wave_nc, mb.wave_nc);
+    F.blevels[size_t(lv)] = m;
+    F.bchoice[size_t(lv)] = {bf, bb};
+}
+
+// The tuner's cache (file named by MATEX_TUNE_CACHE; none when unset): one
+// line per factor structure, "key L f_0 b_0 ... f_{L-1} b_{L-1}", the key
+// made of the sizes that fix the candidates (nodes, supernodes, levels,
+// stored panel entries, structural nonzeros, update rows) and the candidate
+// counts per level. A factor of a structure found there takes the recorded
+// choices instead of timing them, so that every process that shares the
+// file runs the same schedule.
+std::string tune_key(const matex_factor_s& F)
+{
+    std::string k = std::to_string(F.sym.n) + ":" + std::to_string(F.sym.sn.size()) + ":" +
+                    std::to_string(F.sym.n_levels) + ":" + std::to_string(F.sym.n_w) + ":" +
+                    std::to_string(F.sym.nnz_exact) + ":" + std::to_string(F.sym.n_upd) + ":";
+    for (const auto& c : F.bcand) k += std::to_string(c.size());
+    return k;
+}
+
+bool load_tuned(matex_factor_s& F)
+{
+    const char* path = std::getenv("MATEX_TUNE_CACHE");
+    if (!path || !path[0]) return false;
+    std::FILE* fp = std::fopen(path, "r");
+    if (!fp) return false;
+    const std::string key = tune_key(F);
+    const int L = F.sym.n_levels;
+    bool found = false;
+    char buf[8192];
+    while (!found && std::fgets(buf, sizeof buf, fp)) {
+        std::string line(buf);
+        if (line.compare(0, key.size() + 1, key + " ") != 0) continue;
+        std::vector<int> v;
+        const char* q = buf + key.size() + 1;
+        char* end = nullptr;
+        for (long x = std::strtol(q, &end, 10); end != q; x = std::strtol(q, &end, 10)) {
+            v.push_back(int(x));
+            q = end;
+        }
+        if (int(v.size()) != 1 + 2 * L || v[0] != L) continue;
+        bool ok = true;
+        for (int lv = 0; lv < L && ok; ++lv) {
+            const int nc = int(F.bcand[size_t(lv)].size());
+            ok = v[1 + 2 * lv] >= 0 && v[1 + 2 * lv] < nc && v[2 + 2 * lv] >= 0 && v[2 + 2 * lv] < nc;
+        }
+        if (!ok) continue;
+        for (int lv = 0; lv < L; ++lv) keep_batched_choice(F, lv, v[1 + 2 * lv], v[2 + 2 * lv]);
+        found = true;
+    }
+    std::fclose(fp);
+    return found;
+}
+
+void store_tuned(const matex_factor_s& F)
+{
+    const char* path = std::getenv("MATEX_TUNE_CACHE");
+    if (!path || !path[0]) return;
+    std::FILE* fp = std::fopen(path, "a");
+    if (!fp) return;
+    std::fprintf(fp, "%s %d", tune_key(F).c_str(), F.sym.n_levels);
+    for (const auto& c : F.bchoice) std::fprintf(fp, " %d %d", c.first, c.second);
+    std::fprintf(fp, "\n");
+    std::fclose(fp);
+}
+
 void tune_batched(matex_factor_s& F, hipStream_t st)
 {
+    if (load_tuned(F)) {
+        F.info.seconds_tune = 0.0;
+        return;
+    }
     const int L = F.sym.n_levels;
     const int R = RMAX;
     const int64_t n = F.sym.n;
@@ -482,20 +562,13 @@ void tune_batched(matex_factor_s& F, hipStream_t st)
             if (f < tf) { tf = f; bf = int(c); }
             if (g < tb) { tb = g; bb = int(c); }
         }
-        BatchLevel m = cand[size_t(bf)].lv;
-        const BatchLevel& mb = cand[size_t(bb)].lv;
-        m.bwd = mb.bwd; m.n_bwd = mb.n_bwd; m.bred = mb.bred; m.n_bred = mb.n_bred;
-        m.bwave = mb.bwave; m.n_bwave = mb.n_bwave;
-        m.fwave = cand[size_t(bf)].lv.fwave;
-        m.n_fwave = cand[size_t(bf)].lv.n_fwave;
-        m.wave_nc = std::max(cand[size_t(bf)].lv.wave_nc, mb.wave_nc);
-        F.blevels[size_t(lv)] = m;
-        F.bchoice[size_t(lv)] = {bf, bb};
+        keep_batched_choice(F, lv, bf, bb);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     HIPCHK(hipStreamSynchronize(st));
     F.info.seconds_tune = now_s() - t0;
+    store_tuned(F);
 }
 
 // One line per level: the supernodes' widths and the schedules kept.

@@ -132,3 +132,19 @@ def test_inverted_space_refusals():
     with pytest.raises(M.MatexError) as e:
         M.matex_transient(F, p, tol=1e-10, krylov=2)
     assert e.value.status == M.MATEX_E_INVALID
+
+
+def test_inverted_uneven_instances():
+    """Independent grids of uneven size in the inverted space, advanced
+    concurrently: equal to one-at-a-time runs and to the modal solution."""
+    _note("inverted uneven instances")
+    probs = [I.small(131 + i, layers=1 + i % 2, nx=6 + 3 * i, ny=5 + 2 * i, n_src=3 + i, t_end=2 * I.NS)
+             for i in range(4)]
+    factors = [M.matex_factor(q.netlist, GAMMA) for q in probs]
+    res = M.matex_transient_many(factors, probs, tol=1e-12, m_max=30, n_streams=3, krylov=INV)
+    for q, F, (x, _, st) in zip(probs, factors, res):
+        x1, _, st1 = M.matex_transient(F, q, tol=1e-12, m_max=30, krylov=INV, final=False)
+        assert np.array_equal(x.cpu().numpy(), x1.cpu().numpy())
+        assert st["bases"] == st1["bases"] and st["shift_downs"] == 0
+        ym, _ = R.modal(q)
+        assert np.abs(x.cpu().numpy() - (q.netlist.vdd - ym)).max() <= 1e-10

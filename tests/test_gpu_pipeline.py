@@ -68,3 +68,27 @@ def test_graph_replayed_iterations_match_eager(monkeypatch):
         assert np.array_equal(xg.cpu().numpy(), xe.cpu().numpy())
         assert np.array_equal(fg.cpu().numpy(), fe.cpu().numpy())
         assert (sg["bases"], sg["krylov_dims"]) == (se["bases"], se["krylov_dims"])
+
+
+def test_tuner_cache_replays_the_schedule(monkeypatch, tmp_path):
+    """With MATEX_TUNE_CACHE set, the first factor of a structure times the
+    batched schedule's candidates and records the choice; a second factor of
+    the same structure takes the recorded choice without timing, and
+    another structure gets its own line."""
+    from paper_1511_04519_amd import instances as I
+    from paper_1511_04519_amd import matex as M
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("MATEX_TUNE_CACHE", str(path))
+    p = I.small(93, layers=2, nx=30, ny=24, n_src=4)
+    F1 = M.matex_factor(p.netlist, p.gamma)
+    assert F1.info["seconds_tune"] > 0.0 and len(path.read_text().splitlines()) == 1
+    F2 = M.matex_factor(p.netlist, p.gamma)
+    assert F2.info["seconds_tune"] == 0.0
+    assert M.matex_factor_describe(F2) == M.matex_factor_describe(F1)
+    q = I.small(94, layers=1, nx=40, ny=20, n_src=4)
+    M.matex_factor(q.netlist, q.gamma)
+    assert len(path.read_text().splitlines()) == 2
+    b = torch.as_tensor(np.random.default_rng(1).random((64, p.netlist.n)), device="cuda:0")
+    x1 = M.matex_solve(F1, 0, b)
+    x2 = M.matex_solve(F2, 0, b)
+    assert torch.equal(x1, x2)
