@@ -304,7 +304,7 @@ def matex_trapezoidal(f: FactorHandle, prob, h_fs: int, device="cuda", final: bo
 def matex_transient_many(factors, probs, tol: float = 1e-11, m_max: int = 20,
                          mode: int = MATEX_PLAIN, h_min: int = 1, n_streams: int = 4,
                          device="cuda", final: bool = True, shift_ratio: float = 1.0,
-                         krylov: int = MATEX_RATIONAL):
+                         krylov: int = MATEX_RATIONAL, droop: bool = False):
     """Independent instances (own factor each) advanced concurrently on
     n_streams library streams. Returns a list of (x, x_final or None, stats)."""
     import torch
@@ -318,7 +318,8 @@ def matex_transient_many(factors, probs, tol: float = 1e-11, m_max: int = 20,
     po = (_vp * max(1, k))(*[_ptr(t) for t in outs])
     pf = (_vp * max(1, k))(*[_ptr(t) for t in fins]) if final else None
     opts = (RunOpts * max(1, k))(*[RunOpts(float(tol), int(m_max), int(mode), int(h_min),
-                                           float(shift_ratio), 0, 0, int(krylov)) for _ in range(k)])
+                                           float(shift_ratio), int(droop), 0, int(krylov))
+                                   for _ in range(k)])
     sts = (Stats * max(1, k))()
     _check(lib().matex_transient_many(k, fh, prs, opts, po, pf, sts, int(n_streams), _stream()))
     return [(outs[i], fins[i] if final else None, sts[i].as_dict()) for i in range(k)]
