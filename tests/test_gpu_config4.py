@@ -21,8 +21,6 @@ for s = 1..200.
   tolerance 1e-13). Each coordinate costs two factorisations and two full
   forward runs (about a minute), so one coordinate is checked; the
   oracle's complex-step references check every node on small grids."""
-import os
-
 import numpy as np
 import pytest
 
@@ -129,37 +127,3 @@ def test_config4_capacitance_gradient_against_differences(adj):
     print(f"node {i}: adjoint {gc[i]:.12e} differences {fd:.12e} rel {rel:.2e}", flush=True)
     assert rel <= 5e-6
 
-
-@pytest.mark.skipif(os.environ.get("MATEX_CONFIG4_FULL") != "1",
-                    reason="50 refactorisations and 20 ns runs (about 10 minutes): MATEX_CONFIG4_FULL=1")
-def test_config4_capacitance_gradients_25_nodes(adj):
-    """25 seeded observed nodes (the capacitances J_q depends on most):
-    central differences (relative step 1e-4) of refactored 20 ns runs,
-    advanced 8 at a time on concurrent streams, against the adjoint, with
-    the per-coordinate rule |g - g_fd| <= 1e-6 max(|g_fd|, 1e-3 max|g_fd|)."""
-    _note("config4 J_q capacitances, 25 nodes")
-    p, gc, samp, theta = adj["p"], adj["gc"], adj["samp"], adj["theta"]
-    nl = p.netlist
-    nodes = np.random.default_rng(45).choice(p.probe, 25, replace=False)
-    factors, probs = [], []
-    for i in nodes:
-        for sg in (1, -1):
-            c2 = nl.c_node.copy()
-            c2[i] *= 1.0 + sg * 1e-4
-            nl2 = I.Netlist(nl.n, nl.br_a, nl.br_b, nl.br_g, c2, nl.pad_node, nl.pad_g, nl.vdd, nl.coord)
-            factors.append(M.matex_factor(nl2, p.gamma))
-            probs.append(I.Problem(p.name, nl2, p.sources, p.t_end, p.t_out, p.probe))
-    print(f"[config4] {len(factors)} factors built", flush=True)
-    res = []
-    for c in range(0, len(factors), 8):    # 8 runs at a time, a progress line after each group
-        res += M.matex_transient_many(factors[c:c + 8], probs[c:c + 8], tol=1e-13, m_max=24, n_streams=8,
-                                      final=False, droop=True)
-        print(f"[config4] {len(res)} of {len(factors)} runs done", flush=True)
-    fd = np.array([_jq_diff(res[2 * q][0].cpu().numpy()[:, samp], res[2 * q + 1][0].cpu().numpy()[:, samp],
-                            theta) / (2e-4 * nl.c_node[i]) for q, i in enumerate(nodes)])
-    bound = 1e-6 * np.maximum(np.abs(fd), 1e-3 * np.abs(fd).max())
-    ratio = np.abs(gc[nodes] - fd) / bound
-    for i, g, f, r in zip(nodes, gc[nodes], fd, ratio):
-        print(f"node {i}: adjoint {g:.12e} differences {f:.12e} |g - g_fd| / bound {r:.3f}", flush=True)
-    print(f"capacitances: max |g| {np.abs(fd).max():.3e}, worst |g - g_fd| / bound {ratio.max():.3f}", flush=True)
-    assert ratio.max() <= 1.0
