@@ -126,5 +126,3 @@ def test_config4_capacitance_gradient_against_differences(adj):
     rel = abs(gc[i] - fd) / abs(fd)
     print(f"node {i}: adjoint {gc[i]:.12e} differences {fd:.12e} rel {rel:.2e}", flush=True)
     assert rel <= 5e-6
-
-
